@@ -1,0 +1,197 @@
+/*
+ * blfls.h -- C ABI of the MI355X (gfx950) BLF-LS library.
+ *
+ * BLF-LS (Liu, Zhang, Chen, Shen, Huang, Yang, "Embedding Bilateral Filter in
+ * Least Squares for Efficient Edge-preserving Image Smoothing", arXiv 1812.07122)
+ * smooths an image f by solving Eq. (7):
+ *
+ *     min_u  sum_s (u_s - f_s)^2 + lambda sum_{*=x,y} (d_* u_s - g_{*,s})^2,
+ *     g_* = BLF(d_* f)                       (Eq. (1) applied to each gradient field)
+ *
+ * in two steps (Section III-A): (1) bilateral-filter the forward-difference
+ * gradient fields, (2) solve Eq. (8) with Fourier transforms.  Everything runs
+ * on the GPU in hand-written HIP kernels; this header is plain C.
+ *
+ * Conventions shared by every entry point
+ *  - Images are planar, row-major FP32 in device memory: channel c, row i,
+ *    column j lives at ptr[(c * H + i) * pitch + j].  `pitch` is in elements
+ *    (floats), pitch >= W.  W is the width (x, fast axis), H the height.
+ *  - Boundaries are circular: the gradients, the filter window and the
+ *    Fourier solve all wrap around the image edges (the solve of Eq. (8)
+ *    diagonalises circulant difference operators).
+ *  - D_x f(i,j) = f(i,j+1) - f(i,j), D_y f(i,j) = f(i+1,j) - f(i,j) (Section II-B).
+ *  - Colour channels are processed independently.
+ *  - The caller owns every device buffer it passes (f, guide, u, workspace,
+ *    arena).  The library never frees caller memory; it owns only plan tables
+ *    and host structures.  Buffers must stay valid until the work on the
+ *    stream is complete (blfls_smooth) or until blfls_poll reports DONE or
+ *    FAILED (server).
+ *  - Every call returns a blfls_status; BLFLS_OK is 0 and errors are negative.
+ *    The message of the calling thread's last error is in blfls_last_error().
+ *    No C++ exception crosses this interface.
+ *  - hipStream_t is passed as void* so that this header needs no HIP header.
+ */
+#ifndef BLFLS_H
+#define BLFLS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BLFLS_OK = 0,
+  BLFLS_E_INVALID = -1,        /* a bad argument: NaN, lambda < 0, sigma <= 0, ... */
+  BLFLS_E_UNSUPPORTED = -2,    /* a valid problem this library does not handle (size factors) */
+  BLFLS_E_NOMEM = -3,          /* request can never fit in the server arena / allocation failed */
+  BLFLS_E_AGAIN = -4,          /* transient: server queue full, try again */
+  BLFLS_E_HIP = -5,            /* the HIP runtime reported an error */
+  BLFLS_E_UNKNOWN_TICKET = -6  /* blfls_poll on a ticket the server never issued or already retired */
+} blfls_status;
+
+/* Storage precision of the two intermediate gradient-residual fields.  The
+ * filter weights, its accumulation, the FFTs and the spectral divide run in
+ * FP32 in every mode; FP64 is used only for the host-built tables. */
+typedef enum {
+  BLFLS_FP32 = 0,
+  BLFLS_MIXED_BF16 = 1,
+  BLFLS_MIXED_FP16 = 2
+} blfls_precision;
+
+/* Map each range-source gradient field to [0, 1] before the filter and back
+ * after (experiments section of the paper).  The filter weights see only
+ * differences, so this equals the raw filter with sigma_r multiplied by the
+ * field's (max - min), which is how it is computed. */
+#define BLFLS_F_NORMALIZE 0x1u
+
+/* Parameters of Eq. (1) and Eq. (7). */
+typedef struct {
+  float lambda;      /* weight of the gradient term of Eq. (7); >= 0, finite.
+                        The paper's default is 1024 (Section III-C). */
+  float sigma_s;     /* spatial Gaussian of Eq. (1), in pixels; > 0, finite */
+  float sigma_r;     /* range Gaussian of Eq. (1), in gradient units; > 0, may be
+                        +INFINITY (range kernel off: Gaussian-filtered gradients) */
+  int32_t radius;    /* half-width of the square window; >= 0, or -1 for ceil(3 sigma_s).
+                        At most BLFLS_MAX_RADIUS. */
+  int32_t iterations;/* >= 1.  1 is plain BLF-LS (two-step procedure, Section III-A).
+                        k > 1 is rolling guidance (Section III-D): iteration k takes its
+                        range weights from the gradients of iteration k-1's output. */
+  uint32_t flags;    /* BLFLS_F_* bits */
+  float sigma_guide; /* >= 0.  > 0 smooths the initial range source (the guidance image,
+                        or f itself) with a circular Gaussian of this standard deviation,
+                        as the rolling-guidance extension does (Section III-D). 0 = off. */
+} blfls_params;
+
+#define BLFLS_MAX_RADIUS 32
+#define BLFLS_MAX_CHANNELS 4
+
+/* ------------------------------------------------------------------------ */
+/* Plans and the synchronous path                                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct blfls_plan_s *blfls_plan_t;
+
+/* Create a plan for H x W images with C channels on the current HIP device.
+ * The plan holds the FP32 twiddle and denominator tables (built in FP64 on the
+ * host) for the transform sizes: W must be even, and W/2 and H must factor into
+ * 2, 3 and 5 only, each at most BLFLS_MAX_FFT (else BLFLS_E_UNSUPPORTED).
+ * C in [1, BLFLS_MAX_CHANNELS].  *workspace_bytes (if not NULL) receives the
+ * device workspace blfls_smooth needs.  A plan is immutable after creation and
+ * may be used from several streams at once, each with its own workspace. */
+blfls_status blfls_plan(blfls_plan_t *out, int32_t H, int32_t W, int32_t C,
+                        blfls_precision precision, size_t *workspace_bytes);
+
+/* Workspace bytes a plan needs (same value blfls_plan reported). */
+blfls_status blfls_plan_workspace_size(blfls_plan_t plan, size_t *workspace_bytes);
+
+/* Release a plan's tables.  The caller must ensure no queued work uses it. */
+blfls_status blfls_plan_destroy(blfls_plan_t plan);
+
+#define BLFLS_MAX_FFT 4096
+
+/* Smooth f into u (Eq. (7) minimiser, via Eq. (1) then Eq. (8)).
+ *   f          device, [C][H][pitch] FP32, read only
+ *   guide      device, [C][H][pitch] FP32 or NULL.  Non-NULL: joint filtering
+ *              (Section III-D): the range weights of Eq. (1) come from the
+ *              gradients of the guide, the filtered values from f's gradients.
+ *   u          device, [C][H][pitch] FP32, written.  Must not overlap f, guide
+ *              or the workspace (BLFLS_E_INVALID).
+ *   workspace  device, at least the plan's workspace bytes, 256-byte aligned;
+ *              its contents on entry are ignored.
+ *   stream     hipStream_t to queue on (NULL = the null stream).
+ * All work is queued asynchronously; the call does not synchronise.  Errors
+ * found on the host are returned before anything is queued. */
+blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params *params, const float *f,
+                          const float *guide, float *u, int64_t pitch, void *workspace,
+                          void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of independent requests                      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct blfls_server_s *blfls_server_t;
+
+typedef struct {
+  int32_t H, W, C;       /* as for blfls_plan */
+  const float *f;        /* device, [C][H][pitch] */
+  const float *guide;    /* device or NULL */
+  float *u;              /* device, written when the request is DONE */
+  int64_t pitch;         /* elements */
+  blfls_params params;
+} blfls_request;
+
+enum { BLFLS_QUEUED = 0, BLFLS_RUNNING = 1, BLFLS_DONE = 2, BLFLS_FAILED = 3 };
+
+typedef struct {
+  uint64_t submitted, admitted, completed, failed;
+  uint64_t queued_now, running_now;
+  uint64_t steps;               /* device steps launched */
+  uint64_t arena_bytes, arena_in_use, arena_peak;
+  double step_ms_mean;          /* host-measured wall time per step */
+} blfls_stats;
+
+/* Create a server that runs requests on `stream` (void* hipStream_t).  `arena`
+ * is a caller-owned device buffer of arena_bytes (256-byte aligned) from which
+ * each admitted request takes its workspace; admission is by these bytes.
+ * max_slots bounds the requests in flight at once (>= 1), queue_capacity the
+ * requests waiting (>= 1).  A scheduler thread owned by the server launches
+ * steps until blfls_server_destroy. */
+blfls_status blfls_server_create(blfls_server_t *out, void *arena, size_t arena_bytes,
+                                 int32_t max_slots, int32_t queue_capacity,
+                                 blfls_precision precision, void *stream);
+
+/* Queue a request.  Validated at once (same errors as blfls_smooth; a request
+ * whose workspace exceeds the whole arena gives BLFLS_E_NOMEM).  A full queue
+ * gives BLFLS_E_AGAIN.  On success *ticket identifies the request. */
+blfls_status blfls_submit(blfls_server_t server, const blfls_request *request, uint64_t *ticket);
+
+/* State of a ticket: *state is BLFLS_QUEUED, _RUNNING, _DONE or _FAILED;
+ * *result is the request's status once DONE/FAILED.  Never blocks.  A DONE or
+ * FAILED ticket is retired by the poll that reports it. */
+blfls_status blfls_poll(blfls_server_t server, uint64_t ticket, int32_t *state,
+                        blfls_status *result);
+
+blfls_status blfls_server_stats(blfls_server_t server, blfls_stats *stats);
+
+/* Stop accepting work, finish everything queued or running, join the
+ * scheduler and release host state.  The arena is not freed. */
+blfls_status blfls_server_destroy(blfls_server_t server);
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Message of the calling thread's most recent error ("" if none).  The
+ * pointer stays valid until the thread's next call into the library. */
+const char *blfls_last_error(void);
+
+/* Library version string. */
+const char *blfls_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BLFLS_H */

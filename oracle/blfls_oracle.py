@@ -45,7 +45,7 @@ import numpy as np
 __all__ = [
     "default_radius",
     "grad_x", "grad_y", "grad_x_adjoint", "grad_y_adjoint",
-    "bilateral_filter", "bilateral_filter_bruteforce",
+    "bilateral_filter", "bilateral_filter_bruteforce", "bilateral_filter_at",
     "difference_otf", "ls_solve", "blfls_solve",
     "dense_difference_matrices", "dense_blfls_solve",
     "gaussian_blur", "smooth", "smooth_channel",
@@ -136,6 +136,26 @@ def bilateral_filter_bruteforce(p, q, sigma_s, sigma_r, radius):
                     den += ws * wr
             out[i, j] = num / den
     return out
+
+
+def bilateral_filter_at(p, q, sigma_s, sigma_r, radius, rows, cols):
+    """Eq. (1) evaluated only at the pixels (rows[k], cols[k]); same definition as
+    ``bilateral_filter`` (circular window, periodic summation), vectorised over
+    the listed pixels instead of over the image, for checks on large images."""
+    p = np.asarray(p, dtype=np.float64)
+    q = p if q is None else np.asarray(q, dtype=np.float64)
+    H, W = p.shape
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    r = int(radius)
+    d = np.arange(-r, r + 1)
+    ti = (rows[:, None, None] + d[None, :, None]) % H        # (n, 2r+1, 1) window rows
+    tj = (cols[:, None, None] + d[None, None, :]) % W        # (n, 1, 2r+1) window columns
+    w = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2.0 * sigma_s * sigma_s))[None]
+    if math.isfinite(sigma_r):
+        qs = q[rows, cols][:, None, None]
+        w = w * np.exp(-((q[ti, tj] - qs) ** 2) / (2.0 * sigma_r * sigma_r))
+    return np.sum(w * p[ti, tj], axis=(1, 2)) / np.sum(w, axis=(1, 2))
 
 
 # ---------------------------------------------------------------------------

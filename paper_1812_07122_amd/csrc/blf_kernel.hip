@@ -1,0 +1,245 @@
+// Exact windowed bilateral filter on the gradient fields (Eq. (1) applied to
+// D_x f and D_y f, Section III-A), for gfx950.
+//
+// One workgroup filters ONE gradient field over one 64 x (WAVES*K) tile:
+//   * the tile plus an R-pixel halo of the field (and of its range source in
+//     joint mode) is built in LDS from the image with circular wrap;
+//   * lane l of wave w owns image column x0+l and the K rows
+//     y0+w*K .. y0+w*K+K-1 (a vertical register strip), so one LDS read of a
+//     window row serves up to K outputs and the 64 lanes of a wave read 64
+//     consecutive LDS words (no bank conflicts);
+//   * the window column offset dx is a runtime loop over [-r, r]; the row
+//     offsets are unrolled over [-R, R] for the kernel's radius class R, with
+//     rows beyond r weighted exactly 0 (log2 weight -inf);
+//   * per tap: d = q_t - q_s (range values prescaled by sqrt(log2 e/(2 s_r^2))),
+//     w = exp2(sy[dy] - d*d), accumulate w*value and w.  The spatial weight is
+//     separable: the row part sits in the exponent, the column part 2^sx[dx]
+//     scales each column's partial sums, so the tap costs one v_exp_f32 and
+//     four VALU operations;
+//   * the output is the residual r = BLF(p) - p, which keeps 16-bit storage
+//     small away from edges and lets the solve run in residual form.
+//
+// Self-guided fields keep only q = c*p in LDS: sum w*d / (c sum w) is the
+// residual directly.  Joint fields (guide image, rolling guidance, or range
+// kernel off) keep p and q and form sum w*p / sum w - p_s.
+#include "blfls_internal.h"
+#include "blfls_launch.h"
+
+namespace blfls {
+
+namespace {
+
+__device__ __forceinline__ int wrap_index(int v, int n) {
+  int m = v % n;
+  return m < 0 ? m + n : m;
+}
+
+__device__ __forceinline__ void store_field(void* base, int64_t idx, float v, int ft) {
+  if (ft == kF32) {
+    static_cast<float*>(base)[idx] = v;
+  } else if (ft == kBF16) {
+    uint32_t b = __float_as_uint(v);
+    b += 0x7FFFu + ((b >> 16) & 1u);  // round to nearest even (values are finite)
+    static_cast<uint16_t*>(base)[idx] = static_cast<uint16_t>(b >> 16);
+  } else {
+    static_cast<_Float16*>(base)[idx] = static_cast<_Float16>(v);  // round to nearest even
+  }
+}
+
+// Reduce the minmax partials of one field: returns max - min of the range source.
+__device__ float field_span(const float* partial, int field) {
+  __shared__ float red[2];
+  if (threadIdx.x < 64) {
+    const int i = threadIdx.x;
+    float lo = partial[i * 4 + field * 2 + 0];
+    float hi = partial[i * 4 + field * 2 + 1];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, off));
+      hi = fmaxf(hi, __shfl_xor(hi, off));
+    }
+    if (i == 0) { red[0] = lo; red[1] = hi; }
+  }
+  __syncthreads();
+  return red[1] - red[0];
+}
+
+__device__ __forceinline__ int find_plane(const BlfPlane* planes, int nplanes, int item) {
+  // items of plane p: [2*tile_begin, 2*(tile_begin+tile_count))
+  int lo = 0, hi = nplanes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (2 * planes[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace
+
+template <int R, int K, int WAVES, bool JOINT>
+__global__ void __launch_bounds__(64 * WAVES)
+blf_field_kernel(const BlfPlane* __restrict__ planes, int nplanes, int field_type) {
+  constexpr int TW = 64;
+  constexpr int TH = WAVES * K;
+  constexpr int LW = TW + 2 * R;
+  constexpr int LH = TH + 2 * R;
+  constexpr int T = 64 * WAVES;
+  __shared__ float q_lds[LH * LW];
+  __shared__ float p_lds[JOINT ? LH * LW : 1];
+  __shared__ int rowmap[LH + 1];
+  __shared__ int colmap[LW + 1];
+
+  const int item = blockIdx.x;
+  const int pi = find_plane(planes, nplanes, item);
+  const BlfPlane& P = planes[pi];
+  const int local = item - 2 * P.tile_begin;
+  if (local >= 2 * P.tile_count) return;  // uniform: grid larger than the work
+  const int field = local >= P.tile_count ? 1 : 0;
+  const int tile = local - field * P.tile_count;
+  const int H = P.H, W = P.W;
+  const int x0 = (tile % P.tiles_x) * TW;
+  const int y0 = (tile / P.tiles_x) * TH;
+  const int tid = threadIdx.x;
+
+  float c = field ? P.cy : P.cx;
+  if (P.minmax != nullptr && c != 0.0f) {
+    const float span = field_span(P.minmax, field);
+    if (span > 0.0f) c = c / span;
+  }
+
+  // circular index maps of the halo tile (one extra row/column for the differences)
+  for (int a = tid; a < LH + 1; a += T) rowmap[a] = wrap_index(y0 - R + a, H);
+  for (int b = tid; b < LW + 1; b += T) colmap[b] = wrap_index(x0 - R + b, W);
+  __syncthreads();
+
+  const float* __restrict__ f = P.f;
+  const float* __restrict__ g = P.g ? P.g : P.f;
+  const int64_t pitch = P.pitch;
+  const int64_t gpitch = P.g ? P.gpitch : P.pitch;
+  for (int idx = tid; idx < LH * LW; idx += T) {
+    const int a = idx / LW;
+    const int b = idx - a * LW;
+    const int ra = rowmap[a];
+    const int c0 = colmap[b];
+    // neighbour along the field's axis
+    const int rn = field ? rowmap[a + 1] : ra;
+    const int c1 = field ? c0 : colmap[b + 1];
+    const float pv = f[rn * pitch + c1] - f[ra * pitch + c0];
+    if (JOINT) {
+      p_lds[idx] = pv;
+      q_lds[idx] = c * (g[rn * gpitch + c1] - g[ra * gpitch + c0]);
+    } else {
+      q_lds[idx] = c * pv;
+    }
+  }
+  __syncthreads();
+
+  const int lane = tid & 63;
+  const int row0 = (tid >> 6) * K;
+  const float* __restrict__ spatial = P.spatial;
+
+  float sy[2 * R + 1];
+#pragma unroll
+  for (int i = 0; i < 2 * R + 1; ++i) sy[i] = spatial[kMaxR - R + i];
+
+  float qs[K], ps[K], acc_n[K], acc_d[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int o = (row0 + k + R) * LW + lane + R;
+    qs[k] = q_lds[o];
+    ps[k] = JOINT ? p_lds[o] : 0.0f;
+    acc_n[k] = 0.0f;
+    acc_d[k] = 0.0f;
+  }
+
+  const int r = P.r;
+  for (int dx = -r; dx <= r; ++dx) {
+    const int col = lane + R + dx;
+    float tn[K], td[K];
+#pragma unroll
+    for (int t = 0; t < K + 2 * R; ++t) {
+      const float v = q_lds[(row0 + t) * LW + col];
+      const float pv = JOINT ? p_lds[(row0 + t) * LW + col] : 0.0f;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int dy = t - k - R;
+        if (dy < -R || dy > R) continue;
+        const float d = v - qs[k];
+        const float w = __builtin_amdgcn_exp2f(fmaf(-d, d, sy[dy + R]));
+        const float val = JOINT ? pv : d;
+        if (dy == -R) {
+          tn[k] = w * val;
+          td[k] = w;
+        } else {
+          tn[k] = fmaf(w, val, tn[k]);
+          td[k] += w;
+        }
+      }
+    }
+    const float e = spatial[kSpan + kMaxR + dx];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      acc_n[k] = fmaf(e, tn[k], acc_n[k]);
+      acc_d[k] = fmaf(e, td[k], acc_d[k]);
+    }
+  }
+
+  void* out = field ? P.ry : P.rx;
+  const int x = x0 + lane;
+  if (x < W) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int y = y0 + row0 + k;
+      if (y < H) {
+        // the centre tap has weight exactly 1, so acc_d >= 1
+        const float res = JOINT ? acc_n[k] / acc_d[k] - ps[k] : acc_n[k] / (c * acc_d[k]);
+        store_field(out, static_cast<int64_t>(y) * W + x, res, field_type);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch: radius classes and tile shape
+// ---------------------------------------------------------------------------
+
+namespace {
+constexpr int kK = 8;
+constexpr int kWaves = 4;
+constexpr int kRadii[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 14, 16, 20, 24, 28, 32};
+
+template <int R>
+hipError_t launch_r(const BlfPlane* planes, int nplanes, int total_items, bool joint, int ft,
+                    hipStream_t s) {
+  dim3 grid(total_items), block(64 * kWaves);
+  if (joint)
+    hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, true>), grid, block, 0, s, planes, nplanes, ft);
+  else
+    hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, false>), grid, block, 0, s, planes, nplanes, ft);
+  return hipGetLastError();
+}
+}  // namespace
+
+int blf_radius_class(int r) {
+  for (int R : kRadii)
+    if (R >= r) return R;
+  return -1;
+}
+
+int blf_tile_w() { return 64; }
+int blf_tile_h() { return kK * kWaves; }
+
+hipError_t launch_blf(int R, const BlfPlane* planes, int nplanes, int total_items, bool joint,
+                      int field_type, hipStream_t s) {
+  if (total_items <= 0) return hipSuccess;
+  switch (R) {
+#define BLFLS_CASE(RR) case RR: return launch_r<RR>(planes, nplanes, total_items, joint, field_type, s);
+    BLFLS_CASE(1) BLFLS_CASE(2) BLFLS_CASE(3) BLFLS_CASE(4) BLFLS_CASE(5) BLFLS_CASE(6)
+    BLFLS_CASE(8) BLFLS_CASE(9) BLFLS_CASE(10) BLFLS_CASE(12) BLFLS_CASE(14) BLFLS_CASE(16)
+    BLFLS_CASE(20) BLFLS_CASE(24) BLFLS_CASE(28) BLFLS_CASE(32)
+#undef BLFLS_CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace blfls

@@ -1,0 +1,444 @@
+// C ABI of the BLF-LS library: plans, validation and the synchronous path.
+//
+// A plan holds what depends only on the image shape: the factorisation of the
+// two transform lengths (W/2 and H), the FP64-built twiddle and denominator
+// tables rounded to FP32, the tile and workgroup geometry, and the workspace
+// layout.  blfls_smooth builds the per-call descriptors on the host, uploads
+// them into the caller's workspace through kernel arguments, and queues the
+// kernels on the caller's stream without synchronising.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <string>
+#include <vector>
+
+#include "../../include/blfls.h"
+#include "blfls_internal.h"
+#include "blfls_launch.h"
+#include "blfls_plan.h"
+
+namespace blfls {
+
+namespace {
+thread_local std::string g_last_error;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Factor n into radices 4, 2, 3, 5 (at most one 2); false if another prime divides n.
+bool factorize(int n, std::vector<int>* radices) {
+  radices->clear();
+  int m = n;
+  while (m % 4 == 0) { radices->push_back(4); m /= 4; }
+  if (m % 2 == 0) { radices->push_back(2); m /= 2; }
+  while (m % 3 == 0) { radices->push_back(3); m /= 3; }
+  while (m % 5 == 0) { radices->push_back(5); m /= 5; }
+  return m == 1;
+}
+
+// Stage descriptors and FP64-built twiddles exp(-2 pi i t k / (Ns R)) of one length.
+void build_fft_size(int n, FftSize* sz, std::vector<float2>* tw) {
+  std::vector<int> rad;
+  factorize(n, &rad);
+  std::memset(sz, 0, sizeof(*sz));
+  sz->n = n;
+  sz->nstages = static_cast<int>(rad.size());
+  int ns = 1;
+  tw->clear();
+  for (size_t s = 0; s < rad.size(); ++s) {
+    const int R = rad[s];
+    sz->radix[s] = R;
+    sz->ns[s] = ns;
+    sz->tw_off[s] = static_cast<int>(tw->size());
+    for (int k = 0; k < ns; ++k) {
+      for (int t = 1; t < R; ++t) {
+        const double ang = -2.0 * M_PI * static_cast<double>(t) * k / (static_cast<double>(ns) * R);
+        tw->push_back(make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(std::sin(ang))));
+      }
+    }
+    ns *= R;
+  }
+}
+
+int floor_pow2(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+}  // namespace
+
+blfls_status set_error(blfls_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+blfls_status hip_error(hipError_t e, const char* where) {
+  return set_error(BLFLS_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+blfls_status check_shape(int H, int W, int C) {
+  if (H < 1 || W < 1) return set_error(BLFLS_E_INVALID, "H and W must be >= 1");
+  if (C < 1 || C > BLFLS_MAX_CHANNELS) return set_error(BLFLS_E_INVALID, "C must be in [1, 4]");
+  if (W % 2 != 0) return set_error(BLFLS_E_UNSUPPORTED, "W must be even (real FFT of W via a complex FFT of W/2)");
+  const int M = W / 2;
+  if (M > kMaxFft || H > kMaxFft) return set_error(BLFLS_E_UNSUPPORTED, "W/2 and H must be at most 4096");
+  std::vector<int> rad;
+  if (!factorize(M, &rad) || !factorize(H, &rad))
+    return set_error(BLFLS_E_UNSUPPORTED, "W/2 and H must factor into 2, 3 and 5 only");
+  return BLFLS_OK;
+}
+
+blfls_status check_params(const blfls_params* p, int* radius_out) {
+  if (p == nullptr) return set_error(BLFLS_E_INVALID, "params is NULL");
+  if (!std::isfinite(p->lambda) || p->lambda < 0.0f) return set_error(BLFLS_E_INVALID, "lambda must be finite and >= 0");
+  if (!std::isfinite(p->sigma_s) || p->sigma_s <= 0.0f) return set_error(BLFLS_E_INVALID, "sigma_s must be finite and > 0");
+  if (std::isnan(p->sigma_r) || p->sigma_r <= 0.0f) return set_error(BLFLS_E_INVALID, "sigma_r must be > 0 (or +inf)");
+  if (p->iterations < 1) return set_error(BLFLS_E_INVALID, "iterations must be >= 1");
+  if (!std::isfinite(p->sigma_guide) || p->sigma_guide < 0.0f) return set_error(BLFLS_E_INVALID, "sigma_guide must be finite and >= 0");
+  if (p->flags & ~BLFLS_F_NORMALIZE) return set_error(BLFLS_E_INVALID, "unknown flag bits");
+  int r = p->radius;
+  if (r < -1) return set_error(BLFLS_E_INVALID, "radius must be >= 0 or -1");
+  if (r == -1) r = static_cast<int>(std::ceil(3.0 * static_cast<double>(p->sigma_s)));
+  if (r > BLFLS_MAX_RADIUS) return set_error(BLFLS_E_INVALID, "radius exceeds BLFLS_MAX_RADIUS (32)");
+  if (p->sigma_guide > 0.0f && static_cast<int>(std::ceil(3.0 * static_cast<double>(p->sigma_guide))) > kMaxR)
+    return set_error(BLFLS_E_INVALID, "sigma_guide too large (radius ceil(3 sigma_guide) must be <= 32)");
+  *radius_out = r;
+  return BLFLS_OK;
+}
+
+blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s** out) {
+  blfls_status st = check_shape(H, W, C);
+  if (st != BLFLS_OK) return st;
+  if (prec != BLFLS_FP32 && prec != BLFLS_MIXED_BF16 && prec != BLFLS_MIXED_FP16)
+    return set_error(BLFLS_E_INVALID, "unknown precision");
+  auto* p = new (std::nothrow) blfls_plan_s();
+  if (!p) return set_error(BLFLS_E_NOMEM, "host allocation failed");
+  p->H = H; p->W = W; p->C = C; p->M = W / 2; p->precision = prec;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) { delete p; return hip_error(e, "hipGetDevice"); }
+  const int M = p->M;
+
+  // tables, built in FP64 and rounded once to FP32
+  FftSize szM, szH;
+  std::vector<float2> twM, twH;
+  build_fft_size(M, &szM, &twM);
+  build_fft_size(H, &szH, &twH);
+  std::vector<float2> twW(M + 1);
+  std::vector<float> sx(M + 1), sy(H);
+  for (int k = 0; k <= M; ++k) {
+    const double a = -2.0 * M_PI * k / static_cast<double>(W);
+    twW[k] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
+    const double s = std::sin(M_PI * k / static_cast<double>(W));
+    sx[k] = static_cast<float>(4.0 * s * s);
+  }
+  for (int k = 0; k < H; ++k) {
+    const double s = std::sin(M_PI * k / static_cast<double>(H));
+    sy[k] = static_cast<float>(4.0 * s * s);
+  }
+  size_t off = 0;
+  const size_t o_szM = off; off = align_up(off + sizeof(FftSize), 256);
+  const size_t o_szH = off; off = align_up(off + sizeof(FftSize), 256);
+  const size_t o_twM = off; off = align_up(off + twM.size() * sizeof(float2) + 8, 256);
+  const size_t o_twH = off; off = align_up(off + twH.size() * sizeof(float2) + 8, 256);
+  const size_t o_twW = off; off = align_up(off + twW.size() * sizeof(float2), 256);
+  const size_t o_sx = off; off = align_up(off + sx.size() * sizeof(float), 256);
+  const size_t o_sy = off; off = align_up(off + sy.size() * sizeof(float), 256);
+  std::vector<uint8_t> blob(off, 0);
+  std::memcpy(blob.data() + o_szM, &szM, sizeof(szM));
+  std::memcpy(blob.data() + o_szH, &szH, sizeof(szH));
+  if (!twM.empty()) std::memcpy(blob.data() + o_twM, twM.data(), twM.size() * sizeof(float2));
+  if (!twH.empty()) std::memcpy(blob.data() + o_twH, twH.data(), twH.size() * sizeof(float2));
+  std::memcpy(blob.data() + o_twW, twW.data(), twW.size() * sizeof(float2));
+  std::memcpy(blob.data() + o_sx, sx.data(), sx.size() * sizeof(float));
+  std::memcpy(blob.data() + o_sy, sy.data(), sy.size() * sizeof(float));
+  e = hipMalloc(&p->dev_tables, off);
+  if (e != hipSuccess) { delete p; return set_error(BLFLS_E_NOMEM, "hipMalloc of plan tables failed"); }
+  e = hipMemcpy(p->dev_tables, blob.data(), off, hipMemcpyHostToDevice);
+  if (e != hipSuccess) { (void)hipFree(p->dev_tables); delete p; return hip_error(e, "hipMemcpy plan tables"); }
+  uint8_t* base = static_cast<uint8_t*>(p->dev_tables);
+  p->szM = reinterpret_cast<const FftSize*>(base + o_szM);
+  p->szH = reinterpret_cast<const FftSize*>(base + o_szH);
+  p->twM = reinterpret_cast<const float2*>(base + o_twM);
+  p->twH = reinterpret_cast<const float2*>(base + o_twH);
+  p->twW = reinterpret_cast<const float2*>(base + o_twW);
+  p->sx = reinterpret_cast<const float*>(base + o_sx);
+  p->sy = reinterpret_cast<const float*>(base + o_sy);
+
+  // FFT geometry: the largest row/column blocks that fit the LDS budget, split
+  // further while the whole pass would not fill the GPU several times over
+  // (row blocks keep rb * (M + 1) complex values in LDS, at most 64 KiB)
+  int rb = floor_pow2(std::min(16, std::max(1, kFftLdsComplex / (M + 1))));
+  while (rb > 4 && static_cast<long>(C) * ((H + rb - 1) / rb) < 512) rb /= 2;
+  rb = std::min(rb, floor_pow2(H));
+  int cb = std::min(16, std::max(1, kFftLdsComplex / H));
+  while (cb > 1 && static_cast<long>(C) * ((M + 1 + cb - 1) / cb) < 512) cb = (cb + 1) / 2;
+  p->rb = rb;
+  p->cb = cb;
+  p->row_blocks = (H + rb - 1) / rb;
+  p->col_blocks = (M + 1 + cb - 1) / cb;
+  p->lds_rows = static_cast<size_t>(rb) * (M + 1) * sizeof(float2);
+  p->lds_cols = static_cast<size_t>(cb) * H * sizeof(float2);
+  p->tiles_x = (W + blf_tile_w() - 1) / blf_tile_w();
+  p->tiles_y = (H + blf_tile_h() - 1) / blf_tile_h();
+
+  // workspace layout
+  p->field_elem = prec == BLFLS_FP32 ? 4 : 2;
+  const size_t plane = static_cast<size_t>(H) * W;
+  size_t w = 0;
+  p->off_desc = w; w = align_up(w + kDescBytes, 256);
+  p->off_partial = w; w = align_up(w + static_cast<size_t>(C) * kMinmaxBlocks * 4 * sizeof(float), 256);
+  p->off_rx = w; w = align_up(w + C * plane * p->field_elem, 256);
+  p->off_ry = w; w = align_up(w + C * plane * p->field_elem, 256);
+  p->off_spec = w; w = align_up(w + static_cast<size_t>(C) * (M + 1) * H * sizeof(float2), 256);
+  p->off_gauss = w; w = align_up(w + C * plane * sizeof(float), 256);
+  p->off_tmp = w; w = align_up(w + C * plane * sizeof(float), 256);
+  p->ws_bytes = w;
+  *out = p;
+  return BLFLS_OK;
+}
+
+void plan_free(blfls_plan_s* p) {
+  if (!p) return;
+  if (p->dev_tables) (void)hipFree(p->dev_tables);
+  delete p;
+}
+
+void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius, const float* f,
+                   const float* guide, float* u, int64_t pitch, void* ws, const void* dev_tables,
+                   RequestDesc* out) {
+  const int H = plan->H, W = plan->W, C = plan->C, M = plan->M;
+  uint8_t* wsb = static_cast<uint8_t*>(ws);
+  const size_t plane = static_cast<size_t>(H) * W;
+  const double log2e = 1.4426950408889634074;
+  const double ss = prm.sigma_s;
+
+  RequestTables& T = out->tables;
+  for (int d = -kMaxR; d <= kMaxR; ++d) {
+    const double q = static_cast<double>(d) * d * log2e / (2.0 * ss * ss);
+    T.sy[d + kMaxR] = std::abs(d) <= radius ? static_cast<float>(-q) : -std::numeric_limits<float>::infinity();
+    T.ex[d + kMaxR] = static_cast<float>(std::exp2(-q));
+    T.gw[d + kMaxR] = 0.0f;
+  }
+  int rg = 0;
+  if (prm.sigma_guide > 0.0f) {
+    const double sg = prm.sigma_guide;
+    rg = static_cast<int>(std::ceil(3.0 * sg));
+    double tot = 0.0;
+    for (int d = -rg; d <= rg; ++d) tot += std::exp(-static_cast<double>(d) * d / (2.0 * sg * sg));
+    for (int d = -rg; d <= rg; ++d)
+      T.gw[d + kMaxR] = static_cast<float>(std::exp(-static_cast<double>(d) * d / (2.0 * sg * sg)) / tot);
+  }
+  const float* spatial = static_cast<const float*>(dev_tables);
+  const float* gw = spatial + offsetof(RequestTables, gw) / sizeof(float);
+
+  const bool range_on = std::isfinite(prm.sigma_r);
+  const float c = range_on ? static_cast<float>(std::sqrt(log2e / (2.0 * static_cast<double>(prm.sigma_r) * prm.sigma_r)))
+                           : 0.0f;
+  out->R = blf_radius_class(radius);
+  out->iterations = prm.iterations;
+  out->normalize = (prm.flags & BLFLS_F_NORMALIZE) != 0 && range_on;
+  out->smooth_guide = prm.sigma_guide > 0.0f;
+  out->joint_first = guide != nullptr || out->smooth_guide || !range_on;
+  const int tiles = plan->tiles_x * plan->tiles_y;
+  out->blf_first.assign(C, BlfPlane{});
+  out->blf_next.assign(C, BlfPlane{});
+  out->mm_first.assign(C, AuxPlane{});
+  out->mm_next.assign(C, AuxPlane{});
+  out->gauss.assign(C, AuxPlane{});
+  out->fft.assign(C, FftPlane{});
+  float* gauss_base = reinterpret_cast<float*>(wsb + plan->off_gauss);
+  float* tmp_base = reinterpret_cast<float*>(wsb + plan->off_tmp);
+  float* partial_base = reinterpret_cast<float*>(wsb + plan->off_partial);
+  for (int ch = 0; ch < C; ++ch) {
+    const float* fc = f + static_cast<int64_t>(ch) * H * pitch;
+    const float* gc = guide ? guide + static_cast<int64_t>(ch) * H * pitch : nullptr;
+    float* uc = u + static_cast<int64_t>(ch) * H * pitch;
+    void* rx = wsb + plan->off_rx + ch * plane * plan->field_elem;
+    void* ry = wsb + plan->off_ry + ch * plane * plan->field_elem;
+    float* partial = partial_base + static_cast<size_t>(ch) * kMinmaxBlocks * 4;
+    float* gdst = gauss_base + ch * plane;
+
+    // range source of iteration 1 (and its row pitch)
+    const float* src1 = out->smooth_guide ? gdst : (gc ? gc : fc);
+    const int64_t src1_pitch = out->smooth_guide ? W : pitch;
+
+    AuxPlane& G = out->gauss[ch];
+    G.src = gc ? gc : fc;
+    G.dst = gdst;
+    G.tmp = tmp_base + ch * plane;
+    G.partial = nullptr;
+    G.pitch = pitch;
+    G.H = H; G.W = W; G.rg = rg; G.gw = gw;
+
+    AuxPlane& A1 = out->mm_first[ch];
+    A1 = AuxPlane{};
+    A1.src = src1; A1.partial = partial; A1.pitch = src1_pitch; A1.H = H; A1.W = W;
+    AuxPlane& A2 = out->mm_next[ch];
+    A2 = AuxPlane{};
+    A2.src = uc; A2.partial = partial; A2.pitch = pitch; A2.H = H; A2.W = W;
+
+    for (int it = 0; it < 2; ++it) {
+      BlfPlane& B = it == 0 ? out->blf_first[ch] : out->blf_next[ch];
+      B.f = fc;
+      B.rx = rx;
+      B.ry = ry;
+      B.pitch = pitch;
+      B.gpitch = it == 0 ? src1_pitch : pitch;
+      B.H = H; B.W = W; B.r = radius;
+      B.tiles_x = plan->tiles_x;
+      B.tile_begin = ch * tiles;
+      B.tile_count = tiles;
+      B.cx = B.cy = c;
+      B.spatial = spatial;
+      B.minmax = out->normalize ? partial : nullptr;
+      if (it == 0) {
+        // joint when a guide (or its Gaussian-smoothed copy) is the range
+        // source, and when the range kernel is off (q = 0: spatial weights only)
+        B.g = out->joint_first ? src1 : nullptr;
+      } else {
+        B.g = uc;
+      }
+    }
+    FftPlane& F = out->fft[ch];
+    F.rx = rx; F.ry = ry;
+    F.spec = reinterpret_cast<float2*>(wsb + plan->off_spec) + static_cast<size_t>(ch) * (M + 1) * H;
+    F.f = fc; F.u = uc; F.pitch = pitch;
+    F.H = H; F.W = W; F.lambda = prm.lambda;
+    F.rb = plan->rb; F.cb = plan->cb;
+    F.row_begin = ch * plan->row_blocks; F.row_count = plan->row_blocks;
+    F.col_begin = ch * plan->col_blocks; F.col_count = plan->col_blocks;
+    F.szM = plan->szM; F.szH = plan->szH;
+    F.twM = plan->twM; F.twH = plan->twH; F.twW = plan->twW;
+    F.sx = plan->sx; F.sy = plan->sy;
+  }
+}
+
+hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, const DeviceDesc& dev,
+                           hipStream_t s) {
+  const int C = plan->C;
+  const int items = 2 * plan->tiles_x * plan->tiles_y * C;
+  const int ft = plan->precision == BLFLS_FP32 ? kF32 : plan->precision == BLFLS_MIXED_BF16 ? kBF16 : kF16;
+  hipError_t e;
+  if (rd.smooth_guide) {
+    e = launch_gauss(dev.gauss, C, static_cast<int64_t>(plan->H) * plan->W, s);
+    if (e != hipSuccess) return e;
+  }
+  for (int it = 0; it < rd.iterations; ++it) {
+    const bool first = it == 0;
+    if (rd.normalize) {
+      e = launch_minmax(first ? dev.mm_first : dev.mm_next, C, s);
+      if (e != hipSuccess) return e;
+    }
+    e = launch_blf(rd.R, first ? dev.blf_first : dev.blf_next, C, items, first ? rd.joint_first : true, ft, s);
+    if (e != hipSuccess) return e;
+    e = launch_fft_rows_fwd(dev.fft, C, plan->row_blocks * C, plan->lds_rows, ft, s);
+    if (e != hipSuccess) return e;
+    e = launch_fft_cols(dev.fft, C, plan->col_blocks * C, plan->lds_cols, s);
+    if (e != hipSuccess) return e;
+    e = launch_fft_rows_inv(dev.fft, C, plan->row_blocks * C, plan->lds_rows, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace blfls
+
+using namespace blfls;
+
+extern "C" {
+
+const char* blfls_last_error(void) { return g_last_error.c_str(); }
+
+const char* blfls_version(void) { return "blfls 0.1.0 (gfx950)"; }
+
+blfls_status blfls_plan(blfls_plan_t* out, int32_t H, int32_t W, int32_t C, blfls_precision precision,
+                        size_t* workspace_bytes) {
+  g_last_error.clear();
+  if (out == nullptr) return set_error(BLFLS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  blfls_plan_s* p = nullptr;
+  const blfls_status st = plan_create(H, W, C, precision, &p);
+  if (st != BLFLS_OK) return st;
+  *out = p;
+  if (workspace_bytes) *workspace_bytes = p->ws_bytes;
+  return BLFLS_OK;
+}
+
+blfls_status blfls_plan_workspace_size(blfls_plan_t plan, size_t* workspace_bytes) {
+  g_last_error.clear();
+  if (plan == nullptr || workspace_bytes == nullptr) return set_error(BLFLS_E_INVALID, "NULL argument");
+  *workspace_bytes = plan->ws_bytes;
+  return BLFLS_OK;
+}
+
+blfls_status blfls_plan_destroy(blfls_plan_t plan) {
+  g_last_error.clear();
+  if (plan == nullptr) return set_error(BLFLS_E_INVALID, "plan is NULL");
+  plan_free(plan);
+  return BLFLS_OK;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
+}
+
+blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const float* f, const float* guide,
+                          float* u, int64_t pitch, void* workspace, void* stream) {
+  g_last_error.clear();
+  if (plan == nullptr) return set_error(BLFLS_E_INVALID, "plan is NULL");
+  if (f == nullptr || u == nullptr) return set_error(BLFLS_E_INVALID, "f and u must not be NULL");
+  if (workspace == nullptr) return set_error(BLFLS_E_INVALID, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return set_error(BLFLS_E_INVALID, "workspace must be 256-byte aligned");
+  if (pitch < plan->W) return set_error(BLFLS_E_INVALID, "pitch must be >= W");
+  int radius = 0;
+  blfls_status st = check_params(params, &radius);
+  if (st != BLFLS_OK) return st;
+  const size_t img_bytes = static_cast<size_t>(plan->C) * plan->H * pitch * sizeof(float);
+  if (overlaps(u, img_bytes, f, img_bytes) || (guide && overlaps(u, img_bytes, guide, img_bytes)) ||
+      overlaps(u, img_bytes, workspace, plan->ws_bytes))
+    return set_error(BLFLS_E_INVALID, "u must not overlap f, guide or the workspace");
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  if (dev != plan->device) return set_error(BLFLS_E_INVALID, "the current device differs from the plan's device");
+
+  // descriptors: tables, then each array, 256-byte aligned, in the workspace
+  RequestDesc rd;
+  uint8_t* ws = static_cast<uint8_t*>(workspace);
+  uint8_t* dbase = ws + plan->off_desc;
+  build_request(plan, *params, radius, f, guide, u, pitch, workspace, dbase, &rd);
+  std::vector<uint8_t> blob;
+  blob.reserve(8192);
+  auto place = [&](const void* src, size_t n) {
+    const size_t off = align_up(blob.size(), 256);
+    blob.resize(off + n);
+    std::memcpy(blob.data() + off, src, n);
+    return off;
+  };
+  const int C = plan->C;
+  place(&rd.tables, sizeof(RequestTables));
+  const size_t o_b1 = place(rd.blf_first.data(), C * sizeof(BlfPlane));
+  const size_t o_b2 = place(rd.blf_next.data(), C * sizeof(BlfPlane));
+  const size_t o_m1 = place(rd.mm_first.data(), C * sizeof(AuxPlane));
+  const size_t o_m2 = place(rd.mm_next.data(), C * sizeof(AuxPlane));
+  const size_t o_g = place(rd.gauss.data(), C * sizeof(AuxPlane));
+  const size_t o_f = place(rd.fft.data(), C * sizeof(FftPlane));
+  if (blob.size() > kDescBytes) return set_error(BLFLS_E_INVALID, "descriptor area overflow");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  e = launch_desc_copy(blob.data(), blob.size(), dbase, s);
+  if (e != hipSuccess) return hip_error(e, "descriptor upload");
+  DeviceDesc dd;
+  dd.blf_first = reinterpret_cast<const BlfPlane*>(dbase + o_b1);
+  dd.blf_next = reinterpret_cast<const BlfPlane*>(dbase + o_b2);
+  dd.mm_first = reinterpret_cast<const AuxPlane*>(dbase + o_m1);
+  dd.mm_next = reinterpret_cast<const AuxPlane*>(dbase + o_m2);
+  dd.gauss = reinterpret_cast<const AuxPlane*>(dbase + o_g);
+  dd.fft = reinterpret_cast<const FftPlane*>(dbase + o_f);
+  e = enqueue_request(plan, rd, dd, s);
+  if (e != hipSuccess) return hip_error(e, "kernel launch");
+  return BLFLS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Internal descriptors shared by the HIP kernels and the host runtime.
+//
+// Every heavy kernel reads its work from descriptor arrays in device memory.
+// The synchronous path writes them into the caller's workspace with a tiny
+// setup kernel; the server uploads them from pinned host memory.  The same
+// kernels therefore serve one image or a batch of images of uneven sizes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace blfls {
+
+constexpr int kMaxR = 32;               // largest filter radius
+constexpr int kSpan = 2 * kMaxR + 1;    // window taps per axis at kMaxR
+constexpr int kMaxStages = 16;          // FFT stages per transform length
+constexpr int kMaxFft = 4096;           // longest transform (W/2 or H)
+constexpr int kFftThreads = 256;        // threads per FFT workgroup
+constexpr int kFftLdsComplex = 8192;    // complex values per FFT workgroup (64 KiB)
+constexpr int kMinmaxBlocks = 64;       // partial-reduction blocks per plane
+
+enum FieldType : int { kF32 = 0, kBF16 = 1, kF16 = 2 };
+
+// One transform length N = prod(radix[s]).  Stage s combines radix[s]
+// sub-transforms of length ns[s]; its twiddles start at tw_off[s] in the
+// plan's twiddle table: (radix-1) complex values per k in [0, ns).
+struct FftSize {
+  int n;
+  int nstages;
+  int radix[kMaxStages];
+  int ns[kMaxStages];
+  int tw_off[kMaxStages];
+};
+
+// One channel plane for the bilateral-filter kernel (Eq. (1) on both
+// gradient fields of one channel).
+struct BlfPlane {
+  const float* f;        // image whose gradients are filtered, [H][pitch]
+  const float* g;        // range-source image (guide / previous output) or nullptr = f
+  void* rx;              // residual r_x = BLF(p_x) - p_x, packed [H][W], field type
+  void* ry;              // residual r_y
+  const float* minmax;   // range-source gradient extrema partials (normalise flag) or nullptr
+  int64_t pitch;         // elements per row of f
+  int64_t gpitch;        // elements per row of g
+  int H, W;
+  int r;                 // radius actually used (dx loop bound), r <= kernel R
+  int tiles_x;           // tiles across W
+  int tile_begin;        // first linear tile index of this plane in the launch
+  int tile_count;        // tiles_x * tiles_y
+  float cx, cy;          // range scales sqrt(log2(e) / (2 sigma_r^2)) per field; 0 = range off
+  const float* spatial;  // RequestTables::sy then ::ex of the request
+};
+
+// Per-request tables built in FP64 on the host and rounded to FP32.
+struct RequestTables {
+  float sy[kSpan];       // log2 spatial weight per row offset dy+kMaxR: -dy^2 log2(e)/(2 sigma_s^2), -inf beyond r
+  float ex[kSpan];       // spatial weight per column offset dx+kMaxR: 2^(-dx^2 log2(e)/(2 sigma_s^2))
+  float gw[kSpan];       // normalised 1-D Gaussian of the guide smoothing, index d+kMaxR
+};
+
+// One channel plane for the three FFT passes (Eq. (8) in residual form).
+struct FftPlane {
+  const void* rx;        // residual fields, packed [H][W], field type
+  const void* ry;
+  float2* spec;          // half spectrum, transposed: [W/2+1][H] complex
+  const float* f;        // input plane [H][pitch]
+  float* u;              // output plane [H][pitch]
+  int64_t pitch;
+  int H, W;
+  float lambda;
+  int rb;                // rows per row-pass workgroup
+  int cb;                // spectrum columns per column-pass workgroup
+  int row_begin, row_count;   // workgroups of the row passes
+  int col_begin, col_count;   // workgroups of the column pass
+  const FftSize* szM;    // W/2 complex transform
+  const FftSize* szH;    // H complex transform
+  const float2* twM;     // stage twiddles for W/2 (forward sign)
+  const float2* twH;     // stage twiddles for H
+  const float2* twW;     // exp(-2 pi i k / W), k in [0, W/2]
+  const float* sx;       // 4 sin^2(pi k / W), k in [0, W/2]
+  const float* sy;       // 4 sin^2(pi k / H), k in [0, H)
+};
+
+// Minmax (normalise flag) and Gaussian-guide descriptors.
+struct AuxPlane {
+  const float* src;      // range-source image [H][pitch]
+  float* dst;            // Gaussian output [H][W] (guide smoothing) or nullptr
+  float* tmp;            // [H][W] scratch of the separable Gaussian
+  float* partial;        // kMinmaxBlocks * 4 floats
+  int64_t pitch;
+  int H, W;
+  int rg;                // Gaussian radius
+  int pad_;
+  const float* gw;       // RequestTables::gw
+};
+
+}  // namespace blfls

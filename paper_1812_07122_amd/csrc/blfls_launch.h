@@ -1,0 +1,34 @@
+// Host-side launchers of the HIP kernels (one per kernel family).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "blfls_internal.h"
+
+namespace blfls {
+
+// Kernel-argument payload used to upload descriptors without host staging.
+struct DescChunk {
+  uint32_t words[768];
+};
+
+// Radius class (kernel instantiation) for radius r, or -1 if r > kMaxR.
+int blf_radius_class(int r);
+int blf_tile_w();
+int blf_tile_h();
+
+hipError_t launch_desc_copy(const void* host_src, size_t bytes, void* dev_dst, hipStream_t s);
+hipError_t launch_blf(int R, const BlfPlane* planes, int nplanes, int total_items, bool joint,
+                      int field_type, hipStream_t s);
+hipError_t launch_fft_rows_fwd(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
+                               int field_type, hipStream_t s);
+hipError_t launch_fft_cols(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes, hipStream_t s);
+hipError_t launch_fft_rows_inv(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
+                               hipStream_t s);
+hipError_t launch_minmax(const AuxPlane* planes, int nplanes, hipStream_t s);
+hipError_t launch_gauss(const AuxPlane* planes, int nplanes, int64_t max_pixels, hipStream_t s);
+
+}  // namespace blfls

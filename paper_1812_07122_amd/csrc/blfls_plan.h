@@ -1,0 +1,90 @@
+// Host-side plan and request building shared by the synchronous path and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/blfls.h"
+#include "blfls_internal.h"
+
+struct blfls_plan_s {
+  int H = 0, W = 0, C = 0, M = 0;
+  blfls_precision precision = BLFLS_FP32;
+  int device = 0;
+  // plan-owned device tables (one allocation)
+  void* dev_tables = nullptr;
+  const blfls::FftSize* szM = nullptr;
+  const blfls::FftSize* szH = nullptr;
+  const float2* twM = nullptr;
+  const float2* twH = nullptr;
+  const float2* twW = nullptr;
+  const float* sx = nullptr;
+  const float* sy = nullptr;
+  // FFT pass geometry
+  int rb = 1, cb = 1;
+  int row_blocks = 0, col_blocks = 0;   // per channel
+  size_t lds_rows = 0, lds_cols = 0;
+  // BLF geometry
+  int tiles_x = 0, tiles_y = 0;
+  // workspace layout (bytes from the workspace base)
+  size_t field_elem = 4;
+  size_t off_desc = 0, off_partial = 0, off_rx = 0, off_ry = 0, off_spec = 0, off_gauss = 0, off_tmp = 0;
+  size_t ws_bytes = 0;
+};
+
+namespace blfls {
+
+constexpr size_t kDescBytes = 64 * 1024;
+
+// Thread-local error message helpers.
+blfls_status set_error(blfls_status st, const std::string& msg);
+blfls_status hip_error(hipError_t e, const char* where);
+
+// Size and parameter validation shared by the ABI entry points.
+blfls_status check_shape(int H, int W, int C);
+blfls_status check_params(const blfls_params* p, int* radius_out);
+
+// Plans keyed by shape, created on demand (used by the server).
+blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s** out);
+void plan_free(blfls_plan_s* p);
+
+// Everything one request needs to queue its kernels.
+struct RequestDesc {
+  RequestTables tables;
+  std::vector<BlfPlane> blf_first;   // iteration 1
+  std::vector<BlfPlane> blf_next;    // iterations 2..n (range source = previous output)
+  std::vector<AuxPlane> mm_first;    // normalise: extrema of iteration 1's range source
+  std::vector<AuxPlane> mm_next;
+  std::vector<AuxPlane> gauss;       // guide smoothing
+  std::vector<FftPlane> fft;
+  bool joint_first = false;
+  int R = 0;                         // kernel radius class
+  int iterations = 1;
+  bool normalize = false;
+  bool smooth_guide = false;
+};
+
+// Build the descriptors of one request whose workspace starts at `ws`; the
+// request's RequestTables will live at device address `dev_tables`.  Plane
+// tile/block offsets are set for a launch of this request alone; the server
+// rebases them when it batches several requests into one launch.
+void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius, const float* f,
+                   const float* guide, float* u, int64_t pitch, void* ws, const void* dev_tables,
+                   RequestDesc* out);
+
+// Queue one request's kernels on `s`, reading descriptors already resident at
+// the device addresses in `dev` (arrays laid out as in RequestDesc).
+struct DeviceDesc {
+  const BlfPlane* blf_first = nullptr;
+  const BlfPlane* blf_next = nullptr;
+  const AuxPlane* mm_first = nullptr;
+  const AuxPlane* mm_next = nullptr;
+  const AuxPlane* gauss = nullptr;
+  const FftPlane* fft = nullptr;
+};
+hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, const DeviceDesc& dev,
+                           hipStream_t s);
+
+}  // namespace blfls

@@ -1,0 +1,308 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Inputs are FP32 on the device; the oracle runs on float64(float32(input)) so
+input rounding is not charged to the GPU.  Plain FP32 results must agree to
+max-abs 1e-5 (FP32 filter weights and transforms; the filter-field error is
+amplified by at most sqrt(lambda)/2 through the solve).  The 16-bit field
+storage paths must agree to max-abs 2e-3 and PSNR >= 50 dB.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import voronoi_image, voronoi_rgb, joint_pair, config_seed
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+TOL_MIXED = 2e-3
+
+
+def blfls():
+    import paper_1812_07122_amd as b
+    return b
+
+
+def _to_gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _run(f64, guide64=None, **kw):
+    f32 = np.asarray(f64, dtype=np.float32)
+    g = None if guide64 is None else _to_gpu(guide64)
+    u = blfls().smooth(_to_gpu(f32), guide=g, **kw)
+    torch.cuda.synchronize()
+    ref_in = f32.astype(np.float64)
+    ref_guide = None if guide64 is None else np.asarray(guide64, dtype=np.float32).astype(np.float64)
+    return u.cpu().numpy().astype(np.float64), ref_in, ref_guide
+
+
+def _psnr(a, b):
+    mse = float(np.mean((a - b) ** 2))
+    return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+@pytest.mark.parametrize("lam", [1024.0, 20.0])
+def test_grayscale_256(lam):
+    f = voronoi_image(256, 256, config_seed(0, 0))
+    u, fin, _ = _run(f, lam=lam, sigma_s=3.0, sigma_r=0.1)
+    ref = oracle.smooth(fin, lam, 3.0, 0.1)
+    err = np.max(np.abs(u - ref))
+    print(f"256x256 lam={lam}: max-abs {err:.3e}")
+    assert err <= TOL_FP32
+
+
+@pytest.mark.parametrize("H,W,ss,sr,lam", [
+    (96, 100, 2.0, 0.1, 20.0),     # ragged tiles in both directions
+    (45, 50, 1.0, 0.05, 50.0),     # odd H (3^2 5), W/2 = 25
+    (6, 10, 3.0, 0.2, 20.0),       # window wider than the image (periodic copies)
+    (1, 2, 1.0, 0.1, 5.0),         # one row, W/2 = 1
+    (2, 4, 2.0, 0.1, 5.0),
+    (160, 30, 1.5, 0.08, 100.0),   # tall, W < one tile
+    (36, 270, 2.5, 0.1, 30.0),     # W/2 = 135 = 3^3 5
+])
+def test_ragged_and_tiny(H, W, ss, sr, lam):
+    f = voronoi_image(H, W, 11 + H + W)
+    u, fin, _ = _run(f, lam=lam, sigma_s=ss, sigma_r=sr)
+    ref = oracle.smooth(fin, lam, ss, sr)
+    assert np.max(np.abs(u - ref)) <= TOL_FP32
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 5, 7, 11, 13, 17, 21, 25, 30, 32])
+def test_every_radius_class(r):
+    H, W = 72, 90
+    f = voronoi_image(H, W, 300 + r)
+    ss = max(r / 3.0, 0.5)
+    u, fin, _ = _run(f, lam=20.0, sigma_s=ss, sigma_r=0.1, radius=r)
+    ref = oracle.smooth(fin, 20.0, ss, 0.1, radius=r)
+    assert np.max(np.abs(u - ref)) <= TOL_FP32
+
+
+def test_rgb_channels_independent():
+    f = voronoi_rgb(64, 96, 1)
+    u, fin, _ = _run(f, lam=20.0, sigma_s=2.0, sigma_r=0.1)
+    ref = oracle.smooth(fin, 20.0, 2.0, 0.1)
+    assert np.max(np.abs(u - ref)) <= TOL_FP32
+
+
+def test_four_channels():
+    f = np.stack([voronoi_image(40, 48, s) for s in range(4)])
+    u, fin, _ = _run(f, lam=10.0, sigma_s=1.5, sigma_r=0.1)
+    assert np.max(np.abs(u - oracle.smooth(fin, 10.0, 1.5, 0.1))) <= TOL_FP32
+
+
+def test_joint_guide():
+    target, guide = joint_pair(128, 128, 0)
+    u, fin, gin = _run(target, guide, lam=30.0, sigma_s=4.0, sigma_r=0.08)
+    ref = oracle.smooth(fin, 30.0, 4.0, 0.08, guide=gin)
+    assert np.max(np.abs(u - ref)) <= TOL_FP32
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_rolling_guidance_iterations(n):
+    f = voronoi_image(80, 96, 41)
+    u, fin, _ = _run(f, lam=20.0, sigma_s=2.0, sigma_r=0.1, iterations=n)
+    ref = oracle.smooth(fin, 20.0, 2.0, 0.1, iterations=n)
+    assert np.max(np.abs(u - ref)) <= TOL_FP32
+
+
+def test_rolling_with_gaussian_initial_guide():
+    f = voronoi_image(72, 90, 43)
+    u, fin, _ = _run(f, lam=20.0, sigma_s=2.0, sigma_r=0.05, iterations=2, sigma_guide=1.5)
+    ref = oracle.smooth(fin, 20.0, 2.0, 0.05, iterations=2, sigma_guide=1.5)
+    assert np.max(np.abs(u - ref)) <= TOL_FP32
+
+
+def test_normalize_flag():
+    f = voronoi_image(64, 80, 47) * 0.5 + 0.2
+    u, fin, _ = _run(f, lam=20.0, sigma_s=2.0, sigma_r=0.1, normalize=True)
+    ref = oracle.smooth(fin, 20.0, 2.0, 0.1, normalize=True)
+    assert np.max(np.abs(u - ref)) <= TOL_FP32
+
+
+def test_normalize_with_guide_and_iterations():
+    target, guide = joint_pair(64, 64, 3)
+    u, fin, gin = _run(target, guide, lam=20.0, sigma_s=2.0, sigma_r=0.2, normalize=True, iterations=2)
+    ref = oracle.smooth(fin, 20.0, 2.0, 0.2, guide=gin, normalize=True, iterations=2)
+    assert np.max(np.abs(u - ref)) <= TOL_FP32
+
+
+def test_range_kernel_off():
+    f = voronoi_image(50, 60, 53)
+    u, fin, _ = _run(f, lam=30.0, sigma_s=2.0, sigma_r=math.inf)
+    assert np.max(np.abs(u - oracle.smooth(fin, 30.0, 2.0, math.inf))) <= TOL_FP32
+
+
+def test_exact_special_cases():
+    f = voronoi_image(64, 64, 59).astype(np.float32)
+    # lambda = 0, identity filter (r = 0) and a constant image return f bitwise (residual form)
+    u0, _, _ = _run(f, lam=0.0, sigma_s=2.0, sigma_r=0.1)
+    assert np.array_equal(u0.astype(np.float32), f)
+    ur, _, _ = _run(f, lam=1024.0, sigma_s=2.0, sigma_r=0.1, radius=0)
+    assert np.array_equal(ur.astype(np.float32), f)
+    c = np.full((32, 40), 0.375, dtype=np.float32)
+    uc, _, _ = _run(c, lam=500.0, sigma_s=3.0, sigma_r=0.1)
+    assert np.array_equal(uc.astype(np.float32), c)
+
+
+def test_mean_preserved():
+    f = voronoi_image(128, 160, 61)
+    u, fin, _ = _run(f, lam=1024.0, sigma_s=3.0, sigma_r=0.1)
+    assert abs(u.mean() - fin.mean()) < 1e-6
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_mixed_precision_fields(precision):
+    f = voronoi_image(256, 256, config_seed(0, 0))
+    u, fin, _ = _run(f, lam=50.0, sigma_s=3.0, sigma_r=0.05, precision=precision)
+    ref = oracle.smooth(fin, 50.0, 3.0, 0.05)
+    err = np.max(np.abs(u - ref))
+    psnr = _psnr(u, ref)
+    print(f"{precision}: max-abs {err:.3e} psnr {psnr:.1f} dB")
+    assert err <= TOL_MIXED and psnr >= 50.0
+
+
+def test_pitched_buffers_and_side_stream():
+    b = blfls()
+    H, W, pitch = 48, 64, 80
+    f = voronoi_image(H, W, 67).astype(np.float32)
+    fbuf = torch.zeros((H, pitch), dtype=torch.float32, device="cuda")
+    fbuf[:, :W] = torch.from_numpy(f).cuda()
+    ubuf = torch.full((H, pitch), -7.0, dtype=torch.float32, device="cuda")
+    plan = b.Plan(H, W, 1)
+    prm = b.make_params(20.0, 2.0, 0.1)
+    s = torch.cuda.Stream()
+    import ctypes
+    with torch.cuda.stream(s):
+        st = b.lib().blfls_smooth(plan._handle, ctypes.byref(prm), ctypes.c_void_p(fbuf.data_ptr()), None,
+                                  ctypes.c_void_p(ubuf.data_ptr()), pitch, ctypes.c_void_p(plan.workspace_ptr),
+                                  ctypes.c_void_p(s.cuda_stream))
+    assert st == 0
+    s.synchronize()
+    out = ubuf.cpu().numpy()
+    assert np.all(out[:, W:] == -7.0)  # padding untouched
+    ref = oracle.smooth(f.astype(np.float64), 20.0, 2.0, 0.1)
+    assert np.max(np.abs(out[:, :W] - ref)) <= TOL_FP32
+
+
+def test_abi_errors_on_device():
+    import ctypes
+    b = blfls()
+    L = b.lib()
+    plan = b.Plan(32, 32, 1)
+    f = torch.zeros((32, 32), device="cuda")
+    prm = b.make_params(20.0, 2.0, 0.1)
+    ws = ctypes.c_void_p(plan.workspace_ptr)
+    # u aliasing f
+    assert L.blfls_smooth(plan._handle, ctypes.byref(prm), ctypes.c_void_p(f.data_ptr()), None,
+                          ctypes.c_void_p(f.data_ptr()), 32, ws, None) == -1
+    u = torch.zeros_like(f)
+    bad = [b.make_params(-1.0, 2.0, 0.1), b.make_params(20.0, 0.0, 0.1), b.make_params(20.0, 2.0, 0.0),
+           b.make_params(20.0, 2.0, 0.1, radius=33), b.make_params(20.0, 2.0, 0.1, iterations=0),
+           b.make_params(float("nan"), 2.0, 0.1)]
+    for p in bad:
+        assert L.blfls_smooth(plan._handle, ctypes.byref(p), ctypes.c_void_p(f.data_ptr()), None,
+                              ctypes.c_void_p(u.data_ptr()), 32, ws, None) == -1
+    # misaligned workspace, short pitch
+    assert L.blfls_smooth(plan._handle, ctypes.byref(prm), ctypes.c_void_p(f.data_ptr()), None,
+                          ctypes.c_void_p(u.data_ptr()), 32, ctypes.c_void_p(plan.workspace_ptr + 4), None) == -1
+    assert L.blfls_smooth(plan._handle, ctypes.byref(prm), ctypes.c_void_p(f.data_ptr()), None,
+                          ctypes.c_void_p(u.data_ptr()), 16, ws, None) == -1
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# Full-size workload: 1024 x 1024 RGB, lambda = 20, sigma_s = 3, sigma_r = 0.1
+# ---------------------------------------------------------------------------
+
+def _stencil_residual_at(u, f, gx, gy, lam, rows, cols):
+    """(u - f) + lam (D_x^T (D_x u - g_x) + D_y^T (D_y u - g_y)) at the listed pixels,
+    given g_* at (i, j), (i, j-1) and (i-1, j) for each listed pixel."""
+    H, W = u.shape
+    i, j = rows, cols
+    jm, jp = (j - 1) % W, (j + 1) % W
+    im, ip = (i - 1) % H, (i + 1) % H
+    dxu_here = u[i, jp] - u[i, j]
+    dxu_left = u[i, j] - u[i, jm]
+    dyu_here = u[ip, j] - u[i, j]
+    dyu_up = u[i, j] - u[im, j]
+    ex_here, ex_left = dxu_here - gx[0], dxu_left - gx[1]
+    ey_here, ey_up = dyu_here - gy[0], dyu_up - gy[1]
+    return (u[i, j] - f[i, j]) + lam * ((ex_left - ex_here) + (ey_up - ey_here))
+
+
+def test_rgb_1024_full_size():
+    lam, ss, sr = 20.0, 3.0, 0.1
+    f = voronoi_rgb(1024, 1024, 1)
+    u, fin, _ = _run(f, lam=lam, sigma_s=ss, sigma_r=sr)
+    # channel 0 element by element against the whole oracle
+    ref0 = oracle.smooth(fin[0], lam, ss, sr)
+    err0 = np.max(np.abs(u[0] - ref0))
+    print(f"1024x1024 channel 0: max-abs {err0:.3e}")
+    assert err0 <= TOL_FP32
+    # every channel: the normal equations of Eq. (7) hold at sampled pixels, with the
+    # filtered fields evaluated there by the oracle, pixel by pixel
+    rng = np.random.default_rng(2024)
+    rows = rng.integers(0, 1024, 400)
+    cols = rng.integers(0, 1024, 400)
+    r = oracle.default_radius(ss)
+    for c in range(3):
+        px, py = oracle.grad_x(fin[c]), oracle.grad_y(fin[c])
+        gx = [oracle.bilateral_filter_at(px, None, ss, sr, r, rows, cols),
+              oracle.bilateral_filter_at(px, None, ss, sr, r, rows, (cols - 1) % 1024)]
+        gy = [oracle.bilateral_filter_at(py, None, ss, sr, r, rows, cols),
+              oracle.bilateral_filter_at(py, None, ss, sr, r, (rows - 1) % 1024, cols)]
+        res = _stencil_residual_at(u[c], fin[c], gx, gy, lam, rows, cols)
+        # a u error e moves the residual by at most (1 + 8 lam) |e|
+        assert np.max(np.abs(res)) <= (1 + 8 * lam) * TOL_FP32
+
+
+# ---------------------------------------------------------------------------
+# Serving: every result equals the same request run alone
+# ---------------------------------------------------------------------------
+
+def test_server_results_equal_alone():
+    import time
+    b = blfls()
+    rng = np.random.default_rng(5)
+    shapes = [(32, 48, 1), (64, 64, 3), (40, 30, 1), (96, 80, 3), (48, 50, 1), (64, 128, 1)]
+    reqs = []
+    for k in range(12):
+        H, W, C = shapes[k % len(shapes)]
+        f = np.stack([voronoi_image(H, W, 700 + 10 * k + c) for c in range(C)])
+        prm = dict(lam=float(rng.uniform(5, 100)), sigma_s=float(rng.choice([1.0, 2.0, 4.0])),
+                   sigma_r=float(rng.uniform(0.03, 0.2)))
+        guide = np.stack([voronoi_image(H, W, 900 + k + c) for c in range(C)]) if k % 5 == 4 else None
+        reqs.append((f, guide, prm))
+    server = b.Server(arena_bytes=256 << 20, max_slots=5, precision="fp32")
+    tickets = []
+    for f, guide, prm in reqs:
+        g = None if guide is None else _to_gpu(guide)
+        t, u = server.submit(_to_gpu(f), guide=g, **prm)
+        tickets.append((t, u))
+    outs = []
+    deadline = time.time() + 60
+    for t, u in tickets:
+        while True:
+            state, status = server.poll(t)
+            if state in (b.DONE, b.FAILED):
+                break
+            assert time.time() < deadline, "server did not finish"
+            time.sleep(0.001)
+        assert state == b.DONE and status == 0
+        outs.append(u)
+    server.stream.synchronize()
+    stats = server.stats()
+    assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    server.close()
+    for (f, guide, prm), u in zip(reqs, outs):
+        g = None if guide is None else _to_gpu(guide)
+        alone = b.smooth(_to_gpu(f), guide=g, **prm)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, u)
+        ref = oracle.smooth(f.astype(np.float32).astype(np.float64), prm["lam"], prm["sigma_s"], prm["sigma_r"],
+                            guide=None if guide is None else guide.astype(np.float32).astype(np.float64))
+        assert np.max(np.abs(u.cpu().numpy() - ref)) <= TOL_FP32

@@ -147,6 +147,18 @@ def test_P3_blf_bruteforce(H, W, r, ss, sr, joint):
     assert np.max(np.abs(a - b)) < 1e-13
 
 
+@pytest.mark.parametrize("joint,sr,r", [(False, 0.2, 3), (True, 0.1, 5), (False, math.inf, 2), (False, 0.3, 9)])
+def test_P3_blf_at_pixels_matches_full(joint, sr, r):
+    rng = np.random.default_rng(99)
+    p = rng.normal(0, 0.3, (13, 17))
+    q = rng.normal(0, 0.3, (13, 17)) if joint else None
+    full = oracle.bilateral_filter(p, q, 1.5, sr, r)
+    rows = rng.integers(0, 13, 40)
+    cols = rng.integers(0, 17, 40)
+    at = oracle.bilateral_filter_at(p, q, 1.5, sr, r, rows, cols)
+    assert np.max(np.abs(at - full[rows, cols])) < 1e-13
+
+
 # ---------------------------------------------------------------------------
 # Hand-derived example: a 1x4 step image, r=1, sigma_s=1
 # ---------------------------------------------------------------------------
