@@ -183,6 +183,33 @@ blfls_status blfls_server_destroy(blfls_server_t server);
 /* Diagnostics                                                               */
 /* ------------------------------------------------------------------------ */
 
+/* Kernel families of one blfls_smooth call, in queue order. */
+enum {
+  BLFLS_STAGE_UPLOAD = 0,   /* descriptor upload into the workspace */
+  BLFLS_STAGE_GAUSS = 1,    /* Gaussian smoothing of the initial guidance (sigma_guide > 0) */
+  BLFLS_STAGE_MINMAX = 2,   /* gradient extrema of the range source (BLFLS_F_NORMALIZE) */
+  BLFLS_STAGE_BLF = 3,      /* Eq. (1) on both gradient fields */
+  BLFLS_STAGE_ROWS_FWD = 4, /* right-hand side + row real FFTs */
+  BLFLS_STAGE_COLS = 5,     /* column FFTs, spectral divide, inverse column FFTs */
+  BLFLS_STAGE_ROWS_INV = 6, /* inverse row FFTs, u = f + delta */
+  BLFLS_STAGE_COUNT = 7
+};
+
+typedef struct {
+  double ms[BLFLS_STAGE_COUNT];          /* summed GPU time between the stage's bracketing events */
+  uint64_t launches[BLFLS_STAGE_COUNT];  /* bracketed launches summed */
+} blfls_profile;
+
+/* Process-wide switch: while enabled, blfls_smooth records a HIP event on its
+ * stream before and after each kernel family (no synchronisation).  Meant for
+ * benchmarks; it adds two event records per kernel launch. */
+blfls_status blfls_profile_enable(int enable);
+
+/* Wait for every recorded event, add the elapsed times per stage into *out,
+ * and (reset != 0) drop the records.  Fails with BLFLS_E_HIP if an event
+ * reports an error. */
+blfls_status blfls_profile_read(blfls_profile *out, int reset);
+
 /* Message of the calling thread's most recent error ("" if none).  The
  * pointer stays valid until the thread's next call into the library. */
 const char *blfls_last_error(void);

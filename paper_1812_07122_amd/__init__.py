@@ -16,7 +16,7 @@ import os
 import threading
 
 __all__ = [
-    "Params", "Plan", "Server", "BlflsError", "smooth", "lib", "library_path",
+    "Params", "Plan", "Server", "BlflsError", "smooth", "lib", "library_path", "profile_enable", "profile_read",
     "FP32", "MIXED_BF16", "MIXED_FP16", "F_NORMALIZE", "MAX_RADIUS",
     "QUEUED", "RUNNING", "DONE", "FAILED",
 ]
@@ -75,6 +75,14 @@ class Stats(ctypes.Structure):
     ]
 
 
+STAGES = ["upload", "gauss", "minmax", "blf", "rows_fwd", "cols", "rows_inv"]
+
+
+class Profile(ctypes.Structure):
+    """Mirror of ``blfls_profile``."""
+    _fields_ = [("ms", ctypes.c_double * 7), ("launches", ctypes.c_uint64 * 7)]
+
+
 _lib = None
 _lib_lock = threading.Lock()
 
@@ -94,6 +102,8 @@ SIGNATURES = [
                                   ctypes.POINTER(ctypes.c_int)]),
     ("blfls_server_stats", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Stats)]),
     ("blfls_server_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("blfls_profile_enable", ctypes.c_int, [ctypes.c_int]),
+    ("blfls_profile_read", ctypes.c_int, [ctypes.POINTER(Profile), ctypes.c_int]),
     ("blfls_last_error", ctypes.c_char_p, []),
     ("blfls_version", ctypes.c_char_p, []),
 ]
@@ -137,6 +147,18 @@ def _stream_handle(stream) -> int:
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return int(s.cuda_stream)
+
+
+def profile_enable(enable: bool = True):
+    """Record HIP events around each kernel family of blfls_smooth (diagnostics)."""
+    _check(lib().blfls_profile_enable(1 if enable else 0))
+
+
+def profile_read(reset: bool = True) -> dict:
+    """{stage: (ms summed, launches)} of the recorded events (waits for them)."""
+    pr = Profile()
+    _check(lib().blfls_profile_read(ctypes.byref(pr), 1 if reset else 0))
+    return {name: (pr.ms[i], int(pr.launches[i])) for i, name in enumerate(STAGES)}
 
 
 class Plan:

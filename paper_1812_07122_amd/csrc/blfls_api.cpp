@@ -18,6 +18,7 @@
 #include "blfls_internal.h"
 #include "blfls_launch.h"
 #include "blfls_plan.h"
+#include "blfls_profile.h"
 
 namespace blfls {
 
@@ -321,23 +322,37 @@ hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, cons
   const int ft = plan->precision == BLFLS_FP32 ? kF32 : plan->precision == BLFLS_MIXED_BF16 ? kBF16 : kF16;
   hipError_t e;
   if (rd.smooth_guide) {
+    StageTimer t(BLFLS_STAGE_GAUSS, s);
     e = launch_gauss(dev.gauss, C, static_cast<int64_t>(plan->H) * plan->W, s);
     if (e != hipSuccess) return e;
   }
   for (int it = 0; it < rd.iterations; ++it) {
     const bool first = it == 0;
     if (rd.normalize) {
+      StageTimer t(BLFLS_STAGE_MINMAX, s);
       e = launch_minmax(first ? dev.mm_first : dev.mm_next, C, s);
       if (e != hipSuccess) return e;
     }
-    e = launch_blf(rd.R, first ? dev.blf_first : dev.blf_next, C, items, first ? rd.joint_first : true, ft, s);
-    if (e != hipSuccess) return e;
-    e = launch_fft_rows_fwd(dev.fft, C, plan->row_blocks * C, plan->lds_rows, ft, s);
-    if (e != hipSuccess) return e;
-    e = launch_fft_cols(dev.fft, C, plan->col_blocks * C, plan->lds_cols, s);
-    if (e != hipSuccess) return e;
-    e = launch_fft_rows_inv(dev.fft, C, plan->row_blocks * C, plan->lds_rows, s);
-    if (e != hipSuccess) return e;
+    {
+      StageTimer t(BLFLS_STAGE_BLF, s);
+      e = launch_blf(rd.R, first ? dev.blf_first : dev.blf_next, C, items, first ? rd.joint_first : true, ft, s);
+      if (e != hipSuccess) return e;
+    }
+    {
+      StageTimer t(BLFLS_STAGE_ROWS_FWD, s);
+      e = launch_fft_rows_fwd(dev.fft, C, plan->row_blocks * C, plan->lds_rows, ft, s);
+      if (e != hipSuccess) return e;
+    }
+    {
+      StageTimer t(BLFLS_STAGE_COLS, s);
+      e = launch_fft_cols(dev.fft, C, plan->col_blocks * C, plan->lds_cols, s);
+      if (e != hipSuccess) return e;
+    }
+    {
+      StageTimer t(BLFLS_STAGE_ROWS_INV, s);
+      e = launch_fft_rows_inv(dev.fft, C, plan->row_blocks * C, plan->lds_rows, s);
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
@@ -427,7 +442,10 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   const size_t o_f = place(rd.fft.data(), C * sizeof(FftPlane));
   if (blob.size() > kDescBytes) return set_error(BLFLS_E_INVALID, "descriptor area overflow");
   hipStream_t s = static_cast<hipStream_t>(stream);
-  e = launch_desc_copy(blob.data(), blob.size(), dbase, s);
+  {
+    StageTimer t(BLFLS_STAGE_UPLOAD, s);
+    e = launch_desc_copy(blob.data(), blob.size(), dbase, s);
+  }
   if (e != hipSuccess) return hip_error(e, "descriptor upload");
   DeviceDesc dd;
   dd.blf_first = reinterpret_cast<const BlfPlane*>(dbase + o_b1);
