@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="rgb1024", choices=["rgb1024", "uhd", "serve", "joint"])
+    ap.add_argument("--workload", default="rgb1024", choices=["rgb1024", "uhd", "serve", "joint", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=2000)
     return ap.parse_args()

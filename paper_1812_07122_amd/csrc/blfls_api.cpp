@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,16 +28,32 @@ thread_local std::string g_last_error;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Factor n into radices 4, 2, 3, 5 (at most one 2); false if another prime divides n.
+// Factor n into radices 8, 4, 2, 3, 5 (powers of two as 8s, then one 4 or 2);
+// false if another prime divides n.
 bool factorize(int n, std::vector<int>* radices) {
   radices->clear();
   int m = n;
-  while (m % 4 == 0) { radices->push_back(4); m /= 4; }
+  while (m % 8 == 0) { radices->push_back(8); m /= 8; }
+  if (m % 4 == 0) { radices->push_back(4); m /= 4; }
   if (m % 2 == 0) { radices->push_back(2); m /= 2; }
   while (m % 3 == 0) { radices->push_back(3); m /= 3; }
   while (m % 5 == 0) { radices->push_back(5); m /= 5; }
   return m == 1;
 }
+
+}  // namespace
+
+FastDiv make_fastdiv(uint32_t d) {
+  // l = ceil(log2 d); mul = floor(2^32 (2^l - d) / d) + 1
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  FastDiv f;
+  f.mul = static_cast<uint32_t>(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  f.shift = l;
+  return f;
+}
+
+namespace {
 
 // Stage descriptors and FP64-built twiddles exp(-2 pi i t k / (Ns R)) of one length.
 void build_fft_size(int n, FftSize* sz, std::vector<float2>* tw) {
@@ -49,9 +66,13 @@ void build_fft_size(int n, FftSize* sz, std::vector<float2>* tw) {
   tw->clear();
   for (size_t s = 0; s < rad.size(); ++s) {
     const int R = rad[s];
-    sz->radix[s] = R;
-    sz->ns[s] = ns;
-    sz->tw_off[s] = static_cast<int>(tw->size());
+    FftStage& S = sz->st[s];
+    S.radix = R;
+    S.ns = ns;
+    S.per = n / R;
+    S.per_div = make_fastdiv(static_cast<uint32_t>(n / R));
+    S.ns_div = make_fastdiv(static_cast<uint32_t>(ns));
+    S.tw_off = static_cast<int>(tw->size());
     for (int k = 0; k < ns; ++k) {
       for (int t = 1; t < R; ++t) {
         const double ang = -2.0 * M_PI * static_cast<double>(t) * k / (static_cast<double>(ns) * R);
@@ -113,6 +134,10 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   if (st != BLFLS_OK) return st;
   if (prec != BLFLS_FP32 && prec != BLFLS_MIXED_BF16 && prec != BLFLS_MIXED_FP16)
     return set_error(BLFLS_E_INVALID, "unknown precision");
+  static std::once_flag init_once;
+  static hipError_t init_err = hipSuccess;
+  std::call_once(init_once, [] { init_err = fft_init_kernels(); });
+  if (init_err != hipSuccess) return hip_error(init_err, "FFT kernel attributes");
   auto* p = new (std::nothrow) blfls_plan_s();
   if (!p) return set_error(BLFLS_E_NOMEM, "host allocation failed");
   p->H = H; p->W = W; p->C = C; p->M = W / 2; p->precision = prec;
@@ -166,20 +191,20 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   p->sx = reinterpret_cast<const float*>(base + o_sx);
   p->sy = reinterpret_cast<const float*>(base + o_sy);
 
-  // FFT geometry: the largest row/column blocks that fit the LDS budget, split
-  // further while the whole pass would not fill the GPU several times over
-  // (row blocks keep rb * (M + 1) complex values in LDS, at most 64 KiB)
-  int rb = floor_pow2(std::min(16, std::max(1, kFftLdsComplex / (M + 1))));
-  while (rb > 4 && static_cast<long>(C) * ((H + rb - 1) / rb) < 512) rb /= 2;
+  // FFT geometry: rows per row-pass workgroup (a power of two, rb * W/2 complex
+  // values in LDS) and spectrum columns per column-pass workgroup (cb * H),
+  // split further while the whole pass would not give every CU a workgroup
+  int rb = floor_pow2(std::min(16, std::max(1, kFftLdsComplex / M)));
+  while (rb > 4 && static_cast<long>(C) * ((H + rb - 1) / rb) < 256) rb /= 2;
   rb = std::min(rb, floor_pow2(H));
   int cb = std::min(16, std::max(1, kFftLdsComplex / H));
-  while (cb > 1 && static_cast<long>(C) * ((M + 1 + cb - 1) / cb) < 512) cb = (cb + 1) / 2;
+  while (cb > 1 && static_cast<long>(C) * ((M + 1 + cb - 1) / cb) < 256) cb = (cb + 1) / 2;
   p->rb = rb;
   p->cb = cb;
   p->row_blocks = (H + rb - 1) / rb;
   p->col_blocks = (M + 1 + cb - 1) / cb;
-  p->lds_rows = static_cast<size_t>(rb) * (M + 1) * sizeof(float2);
-  p->lds_cols = static_cast<size_t>(cb) * H * sizeof(float2);
+  p->lds_rows = fft_rows_lds_bytes(M, rb);
+  p->lds_cols = fft_cols_lds_bytes(H, cb);
   p->tiles_x = (W + blf_tile_w() - 1) / blf_tile_w();
   p->tiles_y = (H + blf_tile_h() - 1) / blf_tile_h();
 
@@ -312,6 +337,9 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
     F.szM = plan->szM; F.szH = plan->szH;
     F.twM = plan->twM; F.twH = plan->twH; F.twW = plan->twW;
     F.sx = plan->sx; F.sy = plan->sy;
+    F.m_div = make_fastdiv(static_cast<uint32_t>(M));
+    F.h_div = make_fastdiv(static_cast<uint32_t>(H));
+    F.rb_div = make_fastdiv(static_cast<uint32_t>(plan->rb));
   }
 }
 

@@ -15,21 +15,32 @@ constexpr int kMaxR = 32;               // largest filter radius
 constexpr int kSpan = 2 * kMaxR + 1;    // window taps per axis at kMaxR
 constexpr int kMaxStages = 16;          // FFT stages per transform length
 constexpr int kMaxFft = 4096;           // longest transform (W/2 or H)
-constexpr int kFftThreads = 256;        // threads per FFT workgroup
+constexpr int kFftThreads = 512;        // threads per FFT workgroup
 constexpr int kFftLdsComplex = 8192;    // complex values per FFT workgroup (64 KiB)
 constexpr int kMinmaxBlocks = 64;       // partial-reduction blocks per plane
 
 enum FieldType : int { kF32 = 0, kBF16 = 1, kF16 = 2 };
 
-// One transform length N = prod(radix[s]).  Stage s combines radix[s]
-// sub-transforms of length ns[s]; its twiddles start at tw_off[s] in the
-// plan's twiddle table: (radix-1) complex values per k in [0, ns).
+// Division by an invariant n via multiply-high and shift (valid for numerators < 2^31):
+// q = (umulhi(x, mul) + x) >> shift.
+struct FastDiv {
+  uint32_t mul;
+  uint32_t shift;
+};
+
+// One radix stage of a Stockham transform: it combines `radix` sub-transforms
+// of length `ns`; per = N / radix butterflies per transform; its twiddles
+// start at tw_off in the transform's twiddle table, (radix-1) per k in [0, ns).
+struct FftStage {
+  int radix, ns, per, tw_off;
+  FastDiv per_div, ns_div;
+};
+
+// One transform length N = prod of the stage radices.
 struct FftSize {
   int n;
   int nstages;
-  int radix[kMaxStages];
-  int ns[kMaxStages];
-  int tw_off[kMaxStages];
+  FftStage st[kMaxStages];
 };
 
 // One channel plane for the bilateral-filter kernel (Eq. (1) on both
@@ -79,6 +90,9 @@ struct FftPlane {
   const float2* twW;     // exp(-2 pi i k / W), k in [0, W/2]
   const float* sx;       // 4 sin^2(pi k / W), k in [0, W/2]
   const float* sy;       // 4 sin^2(pi k / H), k in [0, H)
+  FastDiv m_div;         // division by W/2
+  FastDiv h_div;         // division by H
+  FastDiv rb_div;        // division by rb
 };
 
 // Minmax (normalise flag) and Gaussian-guide descriptors.

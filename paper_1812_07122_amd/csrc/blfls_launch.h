@@ -23,6 +23,9 @@ int blf_tile_h();
 hipError_t launch_desc_copy(const void* host_src, size_t bytes, void* dev_dst, hipStream_t s);
 hipError_t launch_blf(int R, const BlfPlane* planes, int nplanes, int total_items, bool joint,
                       int field_type, hipStream_t s);
+size_t fft_rows_lds_bytes(int M, int rb);
+size_t fft_cols_lds_bytes(int H, int cb);
+hipError_t fft_init_kernels();
 hipError_t launch_fft_rows_fwd(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
                                int field_type, hipStream_t s);
 hipError_t launch_fft_cols(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes, hipStream_t s);

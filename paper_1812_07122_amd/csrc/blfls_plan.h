@@ -42,6 +42,8 @@ constexpr size_t kDescBytes = 64 * 1024;
 blfls_status set_error(blfls_status st, const std::string& msg);
 blfls_status hip_error(hipError_t e, const char* where);
 
+FastDiv make_fastdiv(uint32_t d);
+
 // Size and parameter validation shared by the ABI entry points.
 blfls_status check_shape(int H, int W, int C);
 blfls_status check_params(const blfls_params* p, int* radius_out);

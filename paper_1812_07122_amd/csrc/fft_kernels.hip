@@ -15,8 +15,10 @@
 //   cols     : per spectrum column: forward FFT over H, multiply by
 //              1/(H W den), inverse FFT over H, all in LDS (one read, one write);
 //   rows_inv : complex-to-real inverse of each row, u = f + delta.
-// Transforms are in-place Stockham passes in LDS with radices 2, 3, 4, 5;
-// twiddles come from FP64 host tables rounded to FP32.
+// Transforms are in-place Stockham passes in LDS with radices 2, 3, 4, 5, 8.
+// Each workgroup first stages the twiddles of its transform length (FP64
+// host tables rounded to FP32) in LDS next to the data, so no stage waits on
+// global memory; index arithmetic uses precomputed multiply-shift division.
 #include "blfls_internal.h"
 #include "blfls_launch.h"
 
@@ -33,6 +35,10 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 // multiply by i*sg (sg = +-1)
 __device__ __forceinline__ float2 cmul_isg(float2 a, float sg) { return make_float2(-sg * a.y, sg * a.x); }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) {
+  return (__umulhi(n, d.mul) + n) >> d.shift;
+}
 
 // DFT of R points, A_k = sum_t a_t exp(sg * 2 pi i t k / R)
 template <int R>
@@ -86,80 +92,115 @@ __device__ __forceinline__ void butterfly<5>(float2* a, float sg) {
   a[3] = csub(b2, m2);
 }
 
+// Radix 8 as 2 x 4: with t = t1 + 4 t2 and k = 2 k1 + k2,
+// A_{2k1+k2} = sum_{t1} w4^{t1 k1} [ w8^{t1 k2} (a_{t1} + (-1)^{k2} a_{t1+4}) ].
+template <>
+__device__ __forceinline__ void butterfly<8>(float2* a, float sg) {
+  constexpr float kH = 0.70710678118654752440f;  // 1/sqrt(2)
+  float2 e[4], o[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    e[t] = cadd(a[t], a[t + 4]);
+    o[t] = csub(a[t], a[t + 4]);
+  }
+  // o[t] *= w8^t, w8 = (1 + i sg)/sqrt(2)
+  o[1] = cscale(cadd(o[1], cmul_isg(o[1], sg)), kH);
+  o[2] = cmul_isg(o[2], sg);
+  o[3] = cscale(csub(cmul_isg(o[3], sg), o[3]), kH);
+  butterfly<4>(e, sg);
+  butterfly<4>(o, sg);
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    a[2 * k1] = e[k1];
+    a[2 * k1 + 1] = o[k1];
+  }
+}
+
 // One in-place Stockham stage over `batch` transforms of length N at
 // buf[b * stride + n].  Input element j + t*N/R of a transform, output element
-// (j - k) * R + k + t * Ns with k = j mod Ns (decimation in time).  All inputs
-// are read into registers before the barrier, so the update is in place.
-template <int R>
-__device__ void fft_stage(float2* buf, int stride, int batch, int N, int Ns, const float2* __restrict__ tw,
-                          float sg) {
-  constexpr int kMaxB = (kFftLdsComplex / R + kFftThreads - 1) / kFftThreads;
-  const int per = N / R;
+// (j - k) * R + k + t * Ns with k = j mod Ns (decimation in time).  Inputs are
+// read into registers before the barrier, so the update is in place.  The
+// stage's twiddles exp(-2 pi i t k/(Ns R)) sit in LDS at tw[k (R-1) + t - 1].
+template <int R, int T>
+__device__ void fft_stage(float2* buf, int stride, int batch, const FftStage& S, const float2* tw, float sg) {
+  constexpr int kMaxB = (kFftLdsComplex / R + T - 1) / T;
+  const int per = S.per;
+  const int Ns = S.ns;
   const int total = per * batch;
   float2 a[kMaxB][R];
-  int base[kMaxB], jj[kMaxB];
+  int out[kMaxB];
 #pragma unroll
   for (int m = 0; m < kMaxB; ++m) {
-    const int gidx = threadIdx.x + m * kFftThreads;
-    if (gidx < total) {
-      const int b = gidx / per;
-      const int j = gidx - b * per;
-      base[m] = b * stride;
-      jj[m] = j;
+    const int g = threadIdx.x + m * T;
+    if (g < total) {
+      const int b = static_cast<int>(fdiv(static_cast<uint32_t>(g), S.per_div));
+      const int j = g - b * per;
+      const int base = b * stride;
 #pragma unroll
-      for (int t = 0; t < R; ++t) a[m][t] = buf[base[m] + j + t * per];
+      for (int t = 0; t < R; ++t) a[m][t] = buf[base + j + t * per];
+      const int k = j - static_cast<int>(fdiv(static_cast<uint32_t>(j), S.ns_div)) * Ns;
+      out[m] = base + (j - k) * R + k;
+      if (Ns > 1) {
+        const float2* w = tw + k * (R - 1);
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          float2 wt = w[t - 1];
+          wt.y = sg > 0.0f ? -wt.y : wt.y;  // the inverse takes the conjugate
+          a[m][t] = cmul(a[m][t], wt);
+        }
+      }
     }
   }
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < kMaxB; ++m) {
-    const int gidx = threadIdx.x + m * kFftThreads;
-    if (gidx < total) {
-      const int j = jj[m];
-      const int k = j % Ns;
-      if (Ns > 1) {
-        const float2* w = tw + k * (R - 1);
-#pragma unroll
-        for (int t = 1; t < R; ++t) {
-          // the table holds exp(-2 pi i t k/(Ns R)); the inverse takes its conjugate
-          float2 wt = w[t - 1];
-          if (sg > 0.0f) wt.y = -wt.y;
-          a[m][t] = cmul(a[m][t], wt);
-        }
-      }
+    const int g = threadIdx.x + m * T;
+    if (g < total) {
       butterfly<R>(a[m], sg);
-      const int o = base[m] + (j - k) * R + k;
 #pragma unroll
-      for (int t = 0; t < R; ++t) buf[o + t * Ns] = a[m][t];
+      for (int t = 0; t < R; ++t) buf[out[m] + t * Ns] = a[m][t];
     }
   }
   __syncthreads();
 }
 
 // Full transform: forward (sg = -1) or inverse without scaling (sg = +1).
-__device__ void lds_fft(float2* buf, int stride, int batch, const FftSize& sz, const float2* __restrict__ tw,
-                        float sg) {
-  const int N = sz.n;
+template <int T>
+__device__ void lds_fft(float2* buf, int stride, int batch, const FftSize& sz, const float2* tw, float sg) {
   for (int s = 0; s < sz.nstages; ++s) {
-    const int R = sz.radix[s];
-    const int Ns = sz.ns[s];
-    const float2* w = tw + sz.tw_off[s];
-    switch (R) {
-      case 2: fft_stage<2>(buf, stride, batch, N, Ns, w, sg); break;
-      case 3: fft_stage<3>(buf, stride, batch, N, Ns, w, sg); break;
-      case 4: fft_stage<4>(buf, stride, batch, N, Ns, w, sg); break;
-      default: fft_stage<5>(buf, stride, batch, N, Ns, w, sg); break;
+    const FftStage& S = sz.st[s];
+    const float2* w = tw + S.tw_off;
+    switch (S.radix) {
+      case 2: fft_stage<2, T>(buf, stride, batch, S, w, sg); break;
+      case 3: fft_stage<3, T>(buf, stride, batch, S, w, sg); break;
+      case 4: fft_stage<4, T>(buf, stride, batch, S, w, sg); break;
+      case 5: fft_stage<5, T>(buf, stride, batch, S, w, sg); break;
+      default: fft_stage<8, T>(buf, stride, batch, S, w, sg); break;
     }
   }
 }
 
-__device__ __forceinline__ float load_field(const void* base, int64_t idx, int ft) {
-  if (ft == kF32) return static_cast<const float*>(base)[idx];
-  if (ft == kBF16) {
-    const uint32_t b = static_cast<uint32_t>(static_cast<const uint16_t*>(base)[idx]) << 16;
-    return __uint_as_float(b);
-  }
-  return static_cast<float>(static_cast<const _Float16*>(base)[idx]);
+// Two consecutive field values at an even index, as FP32.
+template <int FT>
+__device__ __forceinline__ float2 load_pair(const void* base, int64_t idx) {
+  if (FT == kF32) return *reinterpret_cast<const float2*>(static_cast<const float*>(base) + idx);
+  const uint32_t w = *reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(base) + idx);
+  if (FT == kBF16) return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xFFFF0000u));
+  _Float16 h0, h1;
+  const uint16_t lo = static_cast<uint16_t>(w & 0xFFFFu), hi = static_cast<uint16_t>(w >> 16);
+  __builtin_memcpy(&h0, &lo, 2);
+  __builtin_memcpy(&h1, &hi, 2);
+  return make_float2(static_cast<float>(h0), static_cast<float>(h1));
+}
+
+template <int FT>
+__device__ __forceinline__ float load_one(const void* base, int64_t idx) {
+  if (FT == kF32) return static_cast<const float*>(base)[idx];
+  const uint16_t v = static_cast<const uint16_t*>(base)[idx];
+  if (FT == kBF16) return __uint_as_float(static_cast<uint32_t>(v) << 16);
+  _Float16 h;
+  __builtin_memcpy(&h, &v, 2);
+  return static_cast<float>(h);
 }
 
 template <bool COLS>
@@ -173,14 +214,22 @@ __device__ __forceinline__ int find_fft_plane(const FftPlane* planes, int nplane
   return lo;
 }
 
+template <int T>
+__device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += T) dst[i] = src[i];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Pass 1: c = lam (D_x^T r_x + D_y^T r_y), real FFT of each row, transposed store
+// LDS: [stage twiddles of W/2: M][split twiddles: M+1][rows: rb x (M+1)]
 // ---------------------------------------------------------------------------
+template <int FT>
 __global__ void __launch_bounds__(kFftThreads)
-fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes, int field_type) {
-  extern __shared__ float2 buf[];
+fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes) {
+  constexpr int T = kFftThreads;
+  extern __shared__ float2 smem[];
   const int item = blockIdx.x;
   const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
   const int blk = item - P.row_begin;
@@ -190,51 +239,61 @@ fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes, int field_
   const int nrows = min(P.rb, H - i0);
   const float lam = P.lambda;
   const int tid = threadIdx.x;
+  float2* twS = smem;
+  float2* twR = smem + M;
+  float2* buf = smem + 2 * M + 1;
+  stage_twiddles<T>(twS, P.twM, M - 1);
+  stage_twiddles<T>(twR, P.twW, M + 1);
 
-  for (int idx = tid; idx < nrows * M; idx += kFftThreads) {
-    const int row = idx / M;
+  // right-hand side of the residual-form solve, packed two reals per complex
+  const FastDiv mdiv = P.m_div;
+  for (int idx = tid; idx < nrows * M; idx += T) {
+    const int row = static_cast<int>(fdiv(static_cast<uint32_t>(idx), mdiv));
     const int n = idx - row * M;
     const int i = i0 + row;
     const int im1 = i == 0 ? H - 1 : i - 1;
-    const int j0 = 2 * n, j1 = j0 + 1;
+    const int j0 = 2 * n;
     const int jm = j0 == 0 ? W - 1 : j0 - 1;
     const int64_t ri = static_cast<int64_t>(i) * W;
-    const int64_t rim1 = static_cast<int64_t>(im1) * W;
-    const float xm = load_field(P.rx, ri + jm, field_type);
-    const float x0 = load_field(P.rx, ri + j0, field_type);
-    const float x1 = load_field(P.rx, ri + j1, field_type);
-    const float y0m = load_field(P.ry, rim1 + j0, field_type);
-    const float y1m = load_field(P.ry, rim1 + j1, field_type);
-    const float y0 = load_field(P.ry, ri + j0, field_type);
-    const float y1 = load_field(P.ry, ri + j1, field_type);
-    const float c0 = lam * ((xm - x0) + (y0m - y0));
-    const float c1 = lam * ((x0 - x1) + (y1m - y1));
+    const float2 x = load_pair<FT>(P.rx, ri + j0);
+    const float2 y = load_pair<FT>(P.ry, ri + j0);
+    const float2 yp = load_pair<FT>(P.ry, static_cast<int64_t>(im1) * W + j0);
+    const float xm = load_one<FT>(P.rx, ri + jm);
+    const float c0 = lam * ((xm - x.x) + (yp.x - y.x));
+    const float c1 = lam * ((x.x - x.y) + (yp.y - y.y));
     buf[row * M + n] = make_float2(c0, c1);
   }
   __syncthreads();
-  lds_fft(buf, M, nrows, *P.szM, P.twM, -1.0f);
+  lds_fft<T>(buf, M, nrows, *P.szM, twS, -1.0f);
 
   // split step: X[k] = E[k] + exp(-2 pi i k/W) O[k], k = 0..M, Z[M] = Z[0]
   float2* spec = P.spec;
-  for (int idx = tid; idx < (M + 1) * nrows; idx += kFftThreads) {
-    const int k = idx / nrows;
-    const int row = idx - k * nrows;
+  for (int idx = tid; idx < (M + 1) * nrows; idx += T) {
+    int k, row;
+    if (nrows == P.rb) {
+      k = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.rb_div));
+      row = idx - k * nrows;
+    } else {
+      k = idx / nrows;
+      row = idx - k * nrows;
+    }
     const float2 zk = buf[row * M + (k == M ? 0 : k)];
     const float2 zm = buf[row * M + (k == 0 ? 0 : M - k)];
     const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     // o = (zk - conj(zm)) / (2i)
     const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-    const float2 x = cadd(e, cmul(P.twW[k], o));
-    spec[static_cast<int64_t>(k) * H + i0 + row] = x;
+    spec[static_cast<int64_t>(k) * H + i0 + row] = cadd(e, cmul(twR[k], o));
   }
 }
 
 // ---------------------------------------------------------------------------
 // Pass 2: per spectrum column, forward FFT over H, divide, inverse FFT over H
+// LDS: [stage twiddles of H: H][columns: cb x H]
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kFftThreads)
 fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes) {
-  extern __shared__ float2 buf[];
+  constexpr int T = kFftThreads;
+  extern __shared__ float2 smem[];
   const int item = blockIdx.x;
   const FftPlane& P = planes[find_fft_plane<true>(planes, nplanes, item)];
   const int blk = item - P.col_begin;
@@ -243,31 +302,34 @@ fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   const int k0 = blk * P.cb;
   const int ncols = min(P.cb, M + 1 - k0);
   const int tid = threadIdx.x;
+  float2* twS = smem;
+  float2* buf = smem + H;
   float2* spec = P.spec + static_cast<int64_t>(k0) * H;
-
-  for (int idx = tid; idx < ncols * H; idx += kFftThreads) buf[idx] = spec[idx];
+  stage_twiddles<T>(twS, P.twH, H - 1);
+  for (int idx = tid; idx < ncols * H; idx += T) buf[idx] = spec[idx];
   __syncthreads();
-  lds_fft(buf, H, ncols, *P.szH, P.twH, -1.0f);
+  lds_fft<T>(buf, H, ncols, *P.szH, twS, -1.0f);
   const float lam = P.lambda;
   const float inv_hw = 1.0f / (static_cast<float>(H) * static_cast<float>(W));
-  for (int idx = tid; idx < ncols * H; idx += kFftThreads) {
-    const int col = idx / H;
+  for (int idx = tid; idx < ncols * H; idx += T) {
+    const int col = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.h_div));
     const int ky = idx - col * H;
     const float den = fmaf(lam, P.sx[k0 + col] + P.sy[ky], 1.0f);
-    const float s = inv_hw / den;
-    buf[idx] = cscale(buf[idx], s);
+    buf[idx] = cscale(buf[idx], inv_hw / den);
   }
   __syncthreads();
-  lds_fft(buf, H, ncols, *P.szH, P.twH, 1.0f);
-  for (int idx = tid; idx < ncols * H; idx += kFftThreads) spec[idx] = buf[idx];
+  lds_fft<T>(buf, H, ncols, *P.szH, twS, 1.0f);
+  for (int idx = tid; idx < ncols * H; idx += T) spec[idx] = buf[idx];
 }
 
 // ---------------------------------------------------------------------------
 // Pass 3: complex-to-real inverse of each row, u = f + delta
+// LDS: [stage twiddles of W/2: M][split twiddles: M+1][rows: rb x (M+1)]
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kFftThreads)
 fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
-  extern __shared__ float2 buf[];
+  constexpr int T = kFftThreads;
+  extern __shared__ float2 smem[];
   const int item = blockIdx.x;
   const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
   const int blk = item - P.row_begin;
@@ -277,40 +339,48 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   const int i0 = blk * P.rb;
   const int nrows = min(P.rb, H - i0);
   const int tid = threadIdx.x;
+  float2* twS = smem;
+  float2* twR = smem + M;
+  float2* buf = smem + 2 * M + 1;
+  stage_twiddles<T>(twS, P.twM, M - 1);
+  stage_twiddles<T>(twR, P.twW, M + 1);
   const float2* spec = P.spec;
-
-  for (int idx = tid; idx < S * nrows; idx += kFftThreads) {
-    const int k = idx / nrows;
-    const int row = idx - k * nrows;
+  for (int idx = tid; idx < S * nrows; idx += T) {
+    int k, row;
+    if (nrows == P.rb) {
+      k = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.rb_div));
+      row = idx - k * nrows;
+    } else {
+      k = idx / nrows;
+      row = idx - k * nrows;
+    }
     buf[row * S + k] = spec[static_cast<int64_t>(k) * H + i0 + row];
   }
   __syncthreads();
   // Z[k] = (X[k] + conj X[M-k]) + i exp(2 pi i k/W) (X[k] - conj X[M-k]), k = 0..M-1;
   // one thread forms the pair (k, M-k) so the update is in place
   const int half = M / 2;
-  for (int idx = tid; idx < (half + 1) * nrows; idx += kFftThreads) {
-    const int k = idx / nrows;
-    const int row = idx - k * nrows;
+  for (int idx = tid; idx < (half + 1) * nrows; idx += T) {
+    const int row = idx / (half + 1);
+    const int k = idx - row * (half + 1);
     float2* X = buf + row * S;
     const float2 a = X[k], b = X[M - k];
-    const float2 wa = cconj(P.twW[k]);       // exp(+2 pi i k/W)
-    const float2 wb = cconj(P.twW[M - k]);
-    // Z[k]
+    const float2 wa = cconj(twR[k]);  // exp(+2 pi i k/W)
+    const float2 wb = cconj(twR[M - k]);
     const float2 sa = cadd(a, cconj(b)), da = csub(a, cconj(b));
     const float2 za = cadd(sa, cmul_isg(cmul(wa, da), 1.0f));
-    // Z[M-k]
     const float2 sb = cadd(b, cconj(a)), db = csub(b, cconj(a));
     const float2 zb = cadd(sb, cmul_isg(cmul(wb, db), 1.0f));
     X[k] = za;
     if (k != 0 && M - k != k) X[M - k] = zb;
   }
   __syncthreads();
-  lds_fft(buf, S, nrows, *P.szM, P.twM, 1.0f);
+  lds_fft<T>(buf, S, nrows, *P.szM, twS, 1.0f);
   const float* f = P.f;
   float* u = P.u;
   const int64_t pitch = P.pitch;
-  for (int idx = tid; idx < nrows * M; idx += kFftThreads) {
-    const int row = idx / M;
+  for (int idx = tid; idx < nrows * M; idx += T) {
+    const int row = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.m_div));
     const int n = idx - row * M;
     const int64_t o = static_cast<int64_t>(i0 + row) * pitch + 2 * n;
     const float2 z = buf[row * S + n];
@@ -322,11 +392,32 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+size_t fft_rows_lds_bytes(int M, int rb) { return static_cast<size_t>(2 * M + 1 + rb * (M + 1)) * sizeof(float2); }
+size_t fft_cols_lds_bytes(int H, int cb) { return static_cast<size_t>(H + cb * H) * sizeof(float2); }
+
+hipError_t fft_init_kernels() {
+  const int kMax = 160 * 1024;
+  const void* fns[] = {reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF32>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kBF16>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF16>),
+                       reinterpret_cast<const void*>(&fft_cols_kernel),
+                       reinterpret_cast<const void*>(&fft_rows_inv_kernel)};
+  for (const void* fn : fns) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMax);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_fft_rows_fwd(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
                                int field_type, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fft_rows_fwd_kernel, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes,
-                     field_type);
+  if (field_type == kF32)
+    hipLaunchKernelGGL(fft_rows_fwd_kernel<kF32>, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes);
+  else if (field_type == kBF16)
+    hipLaunchKernelGGL(fft_rows_fwd_kernel<kBF16>, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes);
+  else
+    hipLaunchKernelGGL(fft_rows_fwd_kernel<kF16>, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes);
   return hipGetLastError();
 }
 
