@@ -1,0 +1,49 @@
+"""Checks on the gfx950 code the library is built from (CPU: hipcc cross-compiles).
+
+* no packed FP32 instructions (the build disables them; hand-written ones are banned);
+* no scratch (private segment) and no register spills in any kernel;
+* the filter's inner loop spends one v_exp_f32 per tap.
+"""
+import os
+import re
+import shutil
+
+import pytest
+
+from paper_1812_07122_amd import build as b
+
+pytestmark = pytest.mark.skipif(shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"),
+                                reason="hipcc not available")
+
+SOURCES = [s for s in b.sources() if s.endswith(".hip")]
+
+
+@pytest.fixture(scope="module")
+def asm():
+    return {os.path.basename(s): b.device_asm(s) for s in SOURCES}
+
+
+def test_no_packed_fp32(asm):
+    for name, text in asm.items():
+        hits = re.findall(r"\bv_pk_(?:add|mul|fma|mov)_f32\b", text)
+        assert not hits, f"{name}: packed FP32 instructions {sorted(set(hits))}"
+
+
+def test_no_scratch_or_spills(asm):
+    for name, text in asm.items():
+        for m in re.finditer(r"\.private_segment_fixed_size:\s+(\d+)", text):
+            assert int(m.group(1)) == 0, f"{name}: kernel uses scratch"
+        for m in re.finditer(r"\.(?:v|s)gpr_spill_count:\s+(\d+)", text):
+            assert int(m.group(1)) == 0, f"{name}: register spills"
+
+
+def test_filter_one_exp_per_tap(asm):
+    text = asm["blf_kernel.hip"]
+    name = "_ZN5blfls16blf_field_kernelILi9ELi8ELi4ELb0EEEvPKNS_8BlfPlaneEii"
+    start = text.index(name + ":")
+    body = text[start:text.index("s_endpgm", start)]
+    # the runtime dx loop is the last loop of the kernel
+    head = [m.start() for m in re.finditer(r"; %bb\.\d+:.*Loop Header|Loop Header", body)][-1]
+    loop = body[head:]
+    exps = len(re.findall(r"\bv_exp_f32", loop))
+    assert exps == 8 * 19, exps  # K outputs x (2R+1) rows per column offset
