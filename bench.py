@@ -1,6 +1,6 @@
 """Benchmark of the BLF-LS hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rgb1024|uhd|serve|joint]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rgb1024|uhd|serve|joint|copy]
 
 A step is one whole BLF-LS pass (Eq. (1) on both gradient fields of every
 channel, then the Eq. (8) solve) over one image whose input already sits in
@@ -184,6 +184,11 @@ def main():
               "(independent images shard across GPUs without communication; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    state = None
+    if args.workload not in ("rgb1024", "copy"):
+        # CPU inputs and oracle worker processes start before anything touches the GPU
+        import bench_workloads
+        state = bench_workloads.prepare(args)
     import torch
     import paper_1812_07122_amd as blfls
     if not torch.cuda.is_available():
@@ -194,7 +199,7 @@ def main():
         out = run_rgb1024(args, torch, blfls)
     else:
         import bench_workloads
-        out = getattr(bench_workloads, "run_" + args.workload)(args, torch, blfls)
+        out = getattr(bench_workloads, "run_" + args.workload)(args, torch, blfls, state)
     print(json.dumps(out), flush=True)
 
 

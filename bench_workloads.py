@@ -2,13 +2,125 @@
 
 copy   a plain 1 GiB device copy (torch), the reference that scales the HBM
        byte counters rocprofv3 reports for the library's kernels
+uhd    3840x2160 RGB, sigma_s = 8 (r = 24), sigma_r = 0.05, lambda = 50: plain FP32
+       against BF16 and FP16 field storage; each compared with the FP64 oracle
+       over the whole image (oracle channels run in CPU worker processes started
+       before the GPU is touched)
+serve  requests of uneven sizes with Poisson arrivals through the continuous-
+       batching server: saturation rate, then open loop at 0.7 of it; p50/p99
+       latency; every result compared bitwise with the same request run alone
+joint  64 guided 2048x2048 pairs, FP16 field storage, lambda = 30, sigma_s = 4,
+       sigma_r = 0.08, through the server; 8 pairs checked against the oracle
+
+Oracle work for uhd/joint/serve is submitted by ``prepare(args)`` before any GPU
+call; ``run_*`` collects it at the end.
 """
 from __future__ import annotations
 
+import math
 import time
 
+import numpy as np
 
-def run_copy(args, torch, blfls):
+HBM_PEAK_GBS = 8000.0
+SERVE_SIZES = [(320, 480), (480, 640), (720, 1280), (1080, 1920), (1536, 2048)]  # (H, W)
+
+
+def _oracle_channel(job):
+    """Worker: FP64 oracle on one channel (inputs already rounded to FP32)."""
+    import oracle
+    f, guide, lam, ss, sr = job
+    return oracle.smooth(f, lam, ss, sr, guide=guide)
+
+
+def _pool(n):
+    import multiprocessing as mp
+    return mp.get_context("spawn").Pool(processes=n)
+
+
+def _psnr(a, b):
+    mse = float(np.mean((a - b) ** 2))
+    return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+# ---------------------------------------------------------------------------
+# workload inputs (numpy, CPU) and oracle submissions, before any GPU call
+# ---------------------------------------------------------------------------
+
+def prepare(args):
+    import synth
+    state = {}
+    if args.workload == "uhd":
+        f = synth.voronoi_rgb(2160, 3840, 2)
+        state["f"] = f.astype(np.float32)
+        if not args.no_cpu_baseline:
+            pool = _pool(3)
+            jobs = [(state["f"][c].astype(np.float64), None, 50.0, 8.0, 0.05) for c in range(3)]
+            state["t_oracle0"] = time.perf_counter()
+            state["oracle"] = pool.map_async(_oracle_channel, jobs)
+            state["pool"] = pool
+    elif args.workload == "joint":
+        pairs = [synth.joint_pair(2048, 2048, i) for i in range(64 if args.requests >= 64 else args.requests)]
+        state["pairs"] = [(t.astype(np.float32), g.astype(np.float32)) for t, g in pairs]
+        if not args.no_cpu_baseline:
+            pool = _pool(8)
+            jobs = [(t.astype(np.float64), g.astype(np.float64), 30.0, 4.0, 0.08) for t, g in state["pairs"][:8]]
+            state["t_oracle0"] = time.perf_counter()
+            state["oracle"] = pool.map_async(_oracle_channel, jobs)
+            state["pool"] = pool
+    elif args.workload == "serve":
+        rng = np.random.default_rng(3999)
+        n = args.requests
+        # a pool of 4 seeded images per size (seeds 3000 + 10 size + j), channels 1000-apart
+        images = {}
+        for si, (H, W) in enumerate(SERVE_SIZES):
+            for j in range(4):
+                base = 3000 + 10 * si + j
+                images[(si, j)] = np.stack([synth.voronoi_image(H, W, base + 1000 * c) for c in range(3)]).astype(np.float32)
+        reqs = []
+        for i in range(n):
+            r = np.random.default_rng(3000 + i)
+            si = int(r.integers(0, len(SERVE_SIZES)))
+            reqs.append(dict(img=(si, int(r.integers(0, 4))), lam=float(r.uniform(5, 100)),
+                             sigma_s=float(r.choice([2.0, 4.0, 8.0])), sigma_r=float(r.uniform(0.03, 0.2))))
+        state["images"] = images
+        state["reqs"] = reqs
+        state["gaps"] = rng.exponential(1.0, size=n)  # unit-rate inter-arrival times
+        if not args.no_cpu_baseline:
+            # oracle on a seeded sample of 8 requests of at most 1 MP (CPU minutes otherwise)
+            small = [i for i, q in enumerate(reqs) if SERVE_SIZES[q["img"][0]][0] * SERVE_SIZES[q["img"][0]][1] <= 1_000_000]
+            pick = sorted(np.random.default_rng(4242).choice(small, size=min(8, len(small)), replace=False).tolist())
+            jobs = []
+            for i in pick:
+                q = reqs[i]
+                jobs.append((images[q["img"]][0].astype(np.float64), None, q["lam"], q["sigma_s"], q["sigma_r"]))
+            pool = _pool(8)
+            state["oracle_pick"] = pick
+            state["oracle"] = pool.map_async(_oracle_channel, jobs)
+            state["pool"] = pool
+    return state
+
+
+def _collect(state):
+    if "oracle" not in state:
+        return None, None
+    import sys
+    t_wait = time.perf_counter()
+    while not state["oracle"].ready():
+        state["oracle"].wait(30.0)
+        if not state["oracle"].ready():
+            print(f"bench: waiting for the CPU oracle ({time.perf_counter() - t_wait:.0f} s)", file=sys.stderr,
+                  flush=True)
+    res = state["oracle"].get()
+    t = time.perf_counter() - state.get("t_oracle0", time.perf_counter())
+    state["pool"].close()
+    state["pool"].join()
+    return res, t
+
+
+# ---------------------------------------------------------------------------
+
+def run_copy(args, torch, blfls, state=None):
     nbytes = 1 << 30
     src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
@@ -27,3 +139,216 @@ def run_copy(args, torch, blfls):
             "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
             "higher_is_better": True, "config": {"workload": "copy 1 GiB float32 with torch copy_",
                                                  "bytes_read": nbytes, "bytes_written": nbytes}}
+
+
+def run_uhd(args, torch, blfls, state):
+    from bench import time_plan, fft_bytes, BLF_TAP_PEAK_T
+    H, W, C, r = 2160, 3840, 3, 24
+    prm = dict(lam=50.0, sigma_s=8.0, sigma_r=0.05)
+    f = torch.from_numpy(state["f"]).cuda()
+    u = torch.empty_like(f)
+    steps = max(1, min(args.steps, 10))
+    results, outs = {}, {}
+    for prec, fb in (("fp32", 4), ("bf16", 2), ("fp16", 2)):
+        plan = blfls.Plan(H, W, C, prec)
+        ms, stages = time_plan(plan, f, u, prm, steps, min(args.warmup, 2), torch, blfls)
+        outs[prec] = plan.smooth(f, **prm).cpu().numpy().astype(np.float64)
+        torch.cuda.synchronize()
+        blf_ms = stages["blf"][0] / max(stages["blf"][1], 1)
+        taps = C * H * W * 2 * (2 * r + 1) ** 2
+        rf, cl, ri = fft_bytes(H, W, C, fb)
+        fft_ms = sum(stages[k][0] / max(stages[k][1], 1) for k in ("rows_fwd", "cols", "rows_inv"))
+        fft = {}
+        for name, nbytes in (("rows_fwd", rf), ("cols", cl), ("rows_inv", ri)):
+            t = stages[name][0] / max(stages[name][1], 1)
+            fft[name] = {"ms": round(t, 4), "GB/s": round(nbytes / (t * 1e-3) / 1e9, 1),
+                         "frac": round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        results[prec] = {"MPix/s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
+                         "blf_ms": round(blf_ms, 4), "blf_Ttap_s": round(taps / (blf_ms * 1e-3) / 1e12, 4),
+                         "blf_frac": round(taps / (blf_ms * 1e-3) / 1e12 / BLF_TAP_PEAK_T, 4),
+                         "fft_ms": round(fft_ms, 4),
+                         "fft_GB/s": round((rf + cl + ri) / (fft_ms * 1e-3) / 1e9, 1),
+                         "fft_frac": round((rf + cl + ri) / (fft_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "fft_passes": fft}
+        plan.close()
+    for prec in ("bf16", "fp16"):
+        results[prec]["max_abs_vs_fp32_gpu"] = float(np.max(np.abs(outs[prec] - outs["fp32"])))
+    ref, t = _collect(state)
+    out = {"metric": "MPix/s BLF-LS at 1 GPU (plain FP32 vs mixed)", "value": results["fp32"]["MPix/s"],
+           "unit": "MPix/s", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 2),
+           "ms_per_step": results["fp32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "uhd: 3840x2160 RGB, lambda=50, sigma_s=8 (r=24), sigma_r=0.05, 1 iteration",
+                      "H": H, "W": W, "C": C},
+           "precisions": results}
+    if ref is not None:
+        refs = np.stack(ref)
+        for prec in results:
+            results[prec]["max_abs_vs_oracle"] = float(np.max(np.abs(outs[prec] - refs)))
+            results[prec]["psnr_vs_oracle_db"] = round(_psnr(outs[prec], refs), 2)
+        out["cpu_baseline"] = {"value": round(H * W / t / 1e6, 5), "unit": "MPix/s", "cores": 3, "kind": "oracle",
+                               "sample": f"whole image, 3 channels in 3 worker processes, {t:.0f} s wall "
+                                         "(includes time overlapped with the GPU runs)"}
+    return out
+
+
+def _serve(server, blfls, torch, items, gaps_s=None, timeout_s=600.0):
+    """Submit items (list of (f, guide, params, out)) with optional arrival gaps; wait for all."""
+    pending = {}
+    t0 = time.perf_counter()
+    next_t = t0
+    i = 0
+    n = len(items)
+    done = 0
+    deadline = t0 + timeout_s
+    while done < n:
+        now = time.perf_counter()
+        while i < n and (gaps_s is None or now >= next_t):
+            f, g, prm, out = items[i]
+            try:
+                t, _ = server.submit(f, guide=g, out=out, **prm)
+            except blfls.BlflsError as e:
+                if e.status == -4:  # queue full: retry later
+                    break
+                raise
+            pending[t] = i
+            i += 1
+            if gaps_s is not None:
+                next_t += gaps_s[i - 1] if i - 1 < len(gaps_s) else 0.0
+        for t in list(pending):
+            state, status = server.poll(t)
+            if state in (blfls.DONE, blfls.FAILED):
+                if state == blfls.FAILED or status != 0:
+                    raise RuntimeError(f"request {pending[t]} failed with status {status}")
+                del pending[t]
+                done += 1
+        if time.perf_counter() > deadline:
+            raise RuntimeError("serving run timed out")
+        time.sleep(0.0002)
+    return time.perf_counter() - t0
+
+
+def run_serve(args, torch, blfls, state):
+    images = {k: torch.from_numpy(v).cuda() for k, v in state["images"].items()}
+    reqs = state["reqs"]
+    n = len(reqs)
+    outs = [torch.empty_like(images[q["img"]]) for q in reqs]
+    items = [(images[q["img"]], None, dict(lam=q["lam"], sigma_s=q["sigma_s"], sigma_r=q["sigma_r"]), outs[i])
+             for i, q in enumerate(reqs)]
+    mpix = sum(images[q["img"]].shape[1] * images[q["img"]].shape[2] for q in reqs) / 1e6
+    arena = 24 << 30
+    # closed loop: everything queued at once -> saturation rate
+    srv = blfls.Server(arena, max_slots=64, queue_capacity=n + 8, precision="fp32")
+    _serve(srv, blfls, torch, items[: min(n, 64)])  # warm-up: plans and kernels
+    srv.close()
+    srv = blfls.Server(arena, max_slots=64, queue_capacity=n + 8, precision="fp32")
+    t_sat = _serve(srv, blfls, torch, items)
+    sat_stats = srv.stats()
+    srv.close()
+    r_sat = n / t_sat
+    # open loop at 0.7 of saturation (Poisson arrivals)
+    rate = 0.7 * r_sat
+    gaps = state["gaps"] / rate
+    srv = blfls.Server(arena, max_slots=64, queue_capacity=n + 8, precision="fp32")
+    t_open = _serve(srv, blfls, torch, items, gaps_s=gaps)
+    st = srv.stats()
+    srv.close()
+    torch.cuda.synchronize()
+    # the plain synchronous FP32 path on the same requests, one after another on one stream
+    plans = {}
+    for q in reqs[:64]:
+        img = images[q["img"]]
+        key = tuple(img.shape)
+        if key not in plans:
+            plans[key] = blfls.Plan(key[1], key[2], key[0], "fp32")
+        plans[key].smooth(img, out=outs[0].new_empty(img.shape), lam=q["lam"], sigma_s=q["sigma_s"], sigma_r=q["sigma_r"])
+    scratch = {k: torch.empty(k, dtype=torch.float32, device="cuda") for k in plans}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in reqs:
+        img = images[q["img"]]
+        key = tuple(img.shape)
+        plans[key].smooth(img, out=scratch[key], lam=q["lam"], sigma_s=q["sigma_s"], sigma_r=q["sigma_r"])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for p in plans.values():
+        p.close()
+    # every result equals the same request run alone
+    mismatches = 0
+    for i, q in enumerate(reqs):
+        alone = blfls.smooth(images[q["img"]], lam=q["lam"], sigma_s=q["sigma_s"], sigma_r=q["sigma_r"])
+        if not torch.equal(alone, outs[i]):
+            mismatches += 1
+    torch.cuda.synchronize()
+    out = {"metric": "MPix/s BLF-LS served + p50/p99 latency", "value": round(mpix / t_open, 2), "unit": "MPix/s",
+           "n_gpus": 1, "steps": n, "warmup": 64, "ms_per_step": round(1e3 * t_open / n, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"serve: {n} RGB requests, sizes uniform over {[(w, h) for h, w in SERVE_SIZES]} "
+                                  "(WxH), lambda~U[5,100], sigma_s in {2,4,8}, sigma_r~U[0.03,0.2], Poisson arrivals "
+                                  "at 0.7 x saturation", "requests": n},
+           "saturation": {"req_per_s": round(r_sat, 2), "MPix/s": round(mpix / t_sat, 2),
+                          "steps": sat_stats["steps"], "p50_ms": round(sat_stats["latency_p50_ms"], 3),
+                          "p99_ms": round(sat_stats["latency_p99_ms"], 3)},
+           "open_loop": {"req_per_s_offered": round(rate, 2), "p50_ms": round(st["latency_p50_ms"], 3),
+                         "p99_ms": round(st["latency_p99_ms"], 3), "max_ms": round(st["latency_max_ms"], 3),
+                         "steps": st["steps"], "mean_batch": round(n / max(st["steps"], 1), 2),
+                         "arena_peak_GB": round(st["arena_peak"] / 1e9, 3)},
+           "sequential_sync_MPix/s": round(mpix / t_seq, 2),
+           "alone_vs_mix_bitwise_mismatches": mismatches}
+    ref, t = _collect(state)
+    if ref is not None:
+        errs = []
+        for k, i in enumerate(state["oracle_pick"]):
+            errs.append(float(np.max(np.abs(outs[i][0].cpu().numpy().astype(np.float64) - ref[k]))))
+        out["oracle_sample"] = {"requests": state["oracle_pick"], "channel": 0, "max_abs": max(errs)}
+    return out
+
+
+def run_joint(args, torch, blfls, state):
+    pairs = state["pairs"]
+    n = len(pairs)
+    tg = [(torch.from_numpy(t).cuda(), torch.from_numpy(g).cuda()) for t, g in pairs]
+    outs = [torch.empty_like(t) for t, _ in tg]
+    prm = dict(lam=30.0, sigma_s=4.0, sigma_r=0.08)
+    items = [(t, g, prm, outs[i]) for i, (t, g) in enumerate(tg)]
+    arena = 16 << 30
+    srv = blfls.Server(arena, max_slots=64, queue_capacity=n + 8, precision="fp16")
+    _serve(srv, blfls, torch, items[:8])
+    srv.close()
+    srv = blfls.Server(arena, max_slots=64, queue_capacity=n + 8, precision="fp16")
+    t_run = _serve(srv, blfls, torch, items)
+    st = srv.stats()
+    srv.close()
+    # the same pairs through the synchronous FP16 path, one at a time
+    plan = blfls.Plan(2048, 2048, 1, "fp16")
+    u = torch.empty_like(tg[0][0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t, g in tg:
+        plan.smooth(t, guide=g, out=u, **prm)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    mism = 0
+    for i, (t, g) in enumerate(tg):
+        alone = plan.smooth(t, guide=g, **prm)
+        mism += 0 if torch.equal(alone, outs[i]) else 1
+    plan.close()
+    mpix = n * 2048 * 2048 / 1e6
+    out = {"metric": "MPix/s joint BLF-LS served (FP16 fields)", "value": round(mpix / t_run, 2), "unit": "MPix/s",
+           "n_gpus": 1, "steps": n, "warmup": 8, "ms_per_step": round(1e3 * t_run / n, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32 (fp16 fields)", "data": "synthetic",
+           "config": {"workload": f"joint: {n} pairs 2048x2048x1, target = guide + N(0,0.05^2), lambda=30, "
+                                  "sigma_s=4 (r=12), sigma_r=0.08, FP16 field storage, served", "pairs": n},
+           "served": {"p50_ms": round(st["latency_p50_ms"], 3), "p99_ms": round(st["latency_p99_ms"], 3),
+                      "steps": st["steps"]},
+           "sequential_sync_MPix/s": round(mpix / t_seq, 2),
+           "alone_vs_mix_bitwise_mismatches": mism}
+    ref, t = _collect(state)
+    if ref is not None:
+        errs, ps = [], []
+        for k in range(len(ref)):
+            o = outs[k].cpu().numpy().astype(np.float64)
+            errs.append(float(np.max(np.abs(o - ref[k]))))
+            ps.append(_psnr(o, ref[k]))
+        out["oracle_sample"] = {"pairs": len(ref), "max_abs": max(errs), "min_psnr_db": round(min(ps), 2)}
+    return out

@@ -149,7 +149,11 @@ typedef struct {
   uint64_t queued_now, running_now;
   uint64_t steps;               /* device steps launched */
   uint64_t arena_bytes, arena_in_use, arena_peak;
-  double step_ms_mean;          /* host-measured wall time per step */
+  double step_ms_mean;          /* host-measured wall time per step (launch to retire) */
+  uint64_t latency_samples;     /* completed requests with a latency sample */
+  double latency_p50_ms;        /* submit -> DONE, host steady clock, over all completed requests */
+  double latency_p99_ms;
+  double latency_max_ms;
 } blfls_stats;
 
 /* Create a server that runs requests on `stream` (void* hipStream_t).  `arena`

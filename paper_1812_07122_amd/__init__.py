@@ -72,6 +72,10 @@ class Stats(ctypes.Structure):
         ("steps", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
         ("arena_in_use", ctypes.c_uint64), ("arena_peak", ctypes.c_uint64),
         ("step_ms_mean", ctypes.c_double),
+        ("latency_samples", ctypes.c_uint64),
+        ("latency_p50_ms", ctypes.c_double),
+        ("latency_p99_ms", ctypes.c_double),
+        ("latency_max_ms", ctypes.c_double),
     ]
 
 

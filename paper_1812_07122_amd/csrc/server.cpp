@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -96,6 +97,7 @@ class Arena {
 
 struct Job {
   uint64_t id = 0;
+  double t_submit = 0.0;
   blfls_request req{};
   int radius = 0;
   blfls_plan_s* plan = nullptr;
@@ -139,6 +141,7 @@ struct blfls_server_s {
   Step steps[kDepth];
   blfls_stats stats{};
   double step_ms_total = 0.0;
+  std::vector<double> latencies;  // submit -> done, ms
   std::thread worker;
 
   void run();
@@ -295,7 +298,12 @@ void blfls_server_s::retire(Step& st) {
       it->second.first = e == hipSuccess ? BLFLS_DONE : BLFLS_FAILED;
       it->second.second = e == hipSuccess ? BLFLS_OK : BLFLS_E_HIP;
     }
-    if (e == hipSuccess) stats.completed++; else stats.failed++;
+    if (e == hipSuccess) {
+      stats.completed++;
+      latencies.push_back(now_ms() - jb->t_submit);
+    } else {
+      stats.failed++;
+    }
     arena_alloc.release(jb->ws_off, jb->plan->ws_bytes);
     running--;
     delete jb;
@@ -436,6 +444,7 @@ blfls_status blfls_submit(blfls_server_t s, const blfls_request* r, uint64_t* ti
   auto* jb = new (std::nothrow) Job();
   if (!jb) return set_error(BLFLS_E_NOMEM, "host allocation failed");
   jb->id = s->next_id++;
+  jb->t_submit = now_ms();
   jb->req = *r;
   jb->radius = radius;
   jb->plan = plan;
@@ -467,6 +476,19 @@ blfls_status blfls_server_stats(blfls_server_t s, blfls_stats* out) {
   out->arena_in_use = s->arena_alloc.used();
   out->arena_peak = s->arena_alloc.peak();
   out->step_ms_mean = s->stats.steps ? s->step_ms_total / static_cast<double>(s->stats.steps) : 0.0;
+  std::vector<double> lat = s->latencies;
+  out->latency_samples = lat.size();
+  out->latency_p50_ms = out->latency_p99_ms = out->latency_max_ms = 0.0;
+  if (!lat.empty()) {
+    std::sort(lat.begin(), lat.end());
+    auto pct = [&](double q) {
+      const size_t i = static_cast<size_t>(std::ceil(q * static_cast<double>(lat.size()))) - 1;
+      return lat[std::min(i, lat.size() - 1)];
+    };
+    out->latency_p50_ms = pct(0.50);
+    out->latency_p99_ms = pct(0.99);
+    out->latency_max_ms = lat.back();
+  }
   return BLFLS_OK;
 }
 
