@@ -55,7 +55,19 @@ FastDiv make_fastdiv(uint32_t d) {
 
 namespace {
 
-// Stage descriptors and FP64-built twiddles exp(-2 pi i t k / (Ns R)) of one length.
+// Two-level table of W_N = exp(-2 pi i / N) for exponents e < emax, built in FP64
+// and rounded once to FP32: lo[j] = W_N^j (j < 64), hi[j] = W_N^(64 j).
+std::vector<float2> two_level_table(int n, int emax) {
+  std::vector<float2> t(kTwLo + (emax + kTwLo - 1) / kTwLo);
+  for (size_t j = 0; j < t.size(); ++j) {
+    const double e = j < static_cast<size_t>(kTwLo) ? static_cast<double>(j) : static_cast<double>(kTwLo) * (j - kTwLo);
+    const double ang = -2.0 * M_PI * e / static_cast<double>(n);
+    t[j] = make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(std::sin(ang)));
+  }
+  return t;
+}
+
+// Stage descriptors of one transform length and its twiddle table.
 void build_fft_size(int n, FftSize* sz, std::vector<float2>* tw) {
   std::vector<int> rad;
   factorize(n, &rad);
@@ -63,24 +75,18 @@ void build_fft_size(int n, FftSize* sz, std::vector<float2>* tw) {
   sz->n = n;
   sz->nstages = static_cast<int>(rad.size());
   int ns = 1;
-  tw->clear();
   for (size_t s = 0; s < rad.size(); ++s) {
     const int R = rad[s];
     FftStage& S = sz->st[s];
     S.radix = R;
     S.ns = ns;
     S.per = n / R;
+    S.es = n / (ns * R);
     S.per_div = make_fastdiv(static_cast<uint32_t>(n / R));
     S.ns_div = make_fastdiv(static_cast<uint32_t>(ns));
-    S.tw_off = static_cast<int>(tw->size());
-    for (int k = 0; k < ns; ++k) {
-      for (int t = 1; t < R; ++t) {
-        const double ang = -2.0 * M_PI * static_cast<double>(t) * k / (static_cast<double>(ns) * R);
-        tw->push_back(make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(std::sin(ang))));
-      }
-    }
     ns *= R;
   }
+  *tw = two_level_table(n, n);
 }
 
 int floor_pow2(int v) {
@@ -150,11 +156,9 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   std::vector<float2> twM, twH;
   build_fft_size(M, &szM, &twM);
   build_fft_size(H, &szH, &twH);
-  std::vector<float2> twW(M + 1);
+  const std::vector<float2> twW = two_level_table(W, M + 1);
   std::vector<float> sx(M + 1), sy(H);
   for (int k = 0; k <= M; ++k) {
-    const double a = -2.0 * M_PI * k / static_cast<double>(W);
-    twW[k] = make_float2(static_cast<float>(std::cos(a)), static_cast<float>(std::sin(a)));
     const double s = std::sin(M_PI * k / static_cast<double>(W));
     sx[k] = static_cast<float>(4.0 * s * s);
   }
@@ -188,13 +192,17 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   p->twM = reinterpret_cast<const float2*>(base + o_twM);
   p->twH = reinterpret_cast<const float2*>(base + o_twH);
   p->twW = reinterpret_cast<const float2*>(base + o_twW);
+  p->ntwM = static_cast<int>(twM.size());
+  p->ntwH = static_cast<int>(twH.size());
+  p->ntwW = static_cast<int>(twW.size());
   p->sx = reinterpret_cast<const float*>(base + o_sx);
   p->sy = reinterpret_cast<const float*>(base + o_sy);
 
-  // FFT geometry: rows per row-pass workgroup (a power of two, rb * W/2 complex
-  // values in LDS) and spectrum columns per column-pass workgroup (cb * H),
-  // split further while the whole pass would not give every CU a workgroup
-  int rb = floor_pow2(std::min(16, std::max(1, kFftLdsComplex / M)));
+  // FFT geometry: rows per row-pass workgroup (a power of two, rb (W/2+1)
+  // complex values in LDS) and spectrum columns per column-pass workgroup
+  // (cb H), both within 64 KiB so two workgroups share a CU, split further
+  // while the whole pass would not give every CU a workgroup
+  int rb = floor_pow2(std::min(16, std::max(1, kFftLdsComplex / (M + 1))));
   while (rb > 4 && static_cast<long>(C) * ((H + rb - 1) / rb) < 256) rb /= 2;
   rb = std::min(rb, floor_pow2(H));
   int cb = std::min(16, std::max(1, kFftLdsComplex / H));
@@ -336,6 +344,7 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
     F.col_begin = ch * plan->col_blocks; F.col_count = plan->col_blocks;
     F.szM = plan->szM; F.szH = plan->szH;
     F.twM = plan->twM; F.twH = plan->twH; F.twW = plan->twW;
+    F.ntwM = plan->ntwM; F.ntwH = plan->ntwH; F.ntwW = plan->ntwW;
     F.sx = plan->sx; F.sy = plan->sy;
     F.m_div = make_fastdiv(static_cast<uint32_t>(M));
     F.h_div = make_fastdiv(static_cast<uint32_t>(H));

@@ -29,19 +29,24 @@ struct FastDiv {
 };
 
 // One radix stage of a Stockham transform: it combines `radix` sub-transforms
-// of length `ns`; per = N / radix butterflies per transform; its twiddles
-// start at tw_off in the transform's twiddle table, (radix-1) per k in [0, ns).
+// of length `ns`; per = N / radix butterflies per transform.  Its twiddles are
+// W_N^(t k es), W_N = exp(-2 pi i / N), es = N / (ns radix), t < radix, k < ns.
 struct FftStage {
-  int radix, ns, per, tw_off;
+  int radix, ns, per, es;
   FastDiv per_div, ns_div;
 };
 
-// One transform length N = prod of the stage radices.
+// One transform length N = prod of the stage radices.  Powers of W_N come from
+// a two-level table: W_N^e = hi[e >> 6] * lo[e & 63] (lo: W_N^j, j < 64;
+// hi: W_N^(64 j)); kTwLo + ceil(N / 64) entries in all.
 struct FftSize {
   int n;
   int nstages;
   FftStage st[kMaxStages];
 };
+
+constexpr int kTwLo = 64;
+constexpr int kTwMax = kTwLo + (kMaxFft * 2) / kTwLo + 1;  // entries of a two-level table (N <= 2 * kMaxFft)
 
 // One channel plane for the bilateral-filter kernel (Eq. (1) on both
 // gradient fields of one channel).
@@ -85,9 +90,10 @@ struct FftPlane {
   int col_begin, col_count;   // workgroups of the column pass
   const FftSize* szM;    // W/2 complex transform
   const FftSize* szH;    // H complex transform
-  const float2* twM;     // stage twiddles for W/2 (forward sign)
-  const float2* twH;     // stage twiddles for H
-  const float2* twW;     // exp(-2 pi i k / W), k in [0, W/2]
+  const float2* twM;     // two-level table of W_{W/2}
+  const float2* twH;     // two-level table of W_H
+  const float2* twW;     // two-level table of W_W (split step, exponents k in [0, W/2])
+  int ntwM, ntwH, ntwW;  // entries of the three tables
   const float* sx;       // 4 sin^2(pi k / W), k in [0, W/2]
   const float* sy;       // 4 sin^2(pi k / H), k in [0, H)
   FastDiv m_div;         // division by W/2

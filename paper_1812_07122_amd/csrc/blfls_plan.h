@@ -22,6 +22,7 @@ struct blfls_plan_s {
   const float2* twW = nullptr;
   const float* sx = nullptr;
   const float* sy = nullptr;
+  int ntwM = 0, ntwH = 0, ntwW = 0;
   // FFT pass geometry
   int rb = 1, cb = 1;
   int row_blocks = 0, col_blocks = 0;   // per channel

@@ -16,9 +16,12 @@
 //              1/(H W den), inverse FFT over H, all in LDS (one read, one write);
 //   rows_inv : complex-to-real inverse of each row, u = f + delta.
 // Transforms are in-place Stockham passes in LDS with radices 2, 3, 4, 5, 8.
-// Each workgroup first stages the twiddles of its transform length (FP64
-// host tables rounded to FP32) in LDS next to the data, so no stage waits on
-// global memory; index arithmetic uses precomputed multiply-shift division.
+// Each workgroup first stages two-level twiddle tables of its transform lengths
+// (FP64 host tables rounded to FP32, about 1.5 KiB) in LDS next to the data, so
+// no stage waits on global memory and two workgroups fit on a CU; index
+// arithmetic uses precomputed multiply-shift division; consecutive row blocks
+// are placed on the same XCD so partial lines of the transposed spectrum meet
+// in one L2.
 #include "blfls_internal.h"
 #include "blfls_launch.h"
 
@@ -38,6 +41,21 @@ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y
 
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) {
   return (__umulhi(n, d.mul) + n) >> d.shift;
+}
+
+// W_N^e from a two-level table in LDS (lo: W_N^j, j < 64; hi: W_N^(64 j)).
+__device__ __forceinline__ float2 twiddle(const float2* tab, int e) {
+  return cmul(tab[kTwLo + (e >> 6)], tab[e & (kTwLo - 1)]);
+}
+
+// Logical workgroup index such that consecutive logical indices run on the same
+// XCD (workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2): neighbouring row blocks then share the L2 lines of the transposed spectrum.
+__device__ __forceinline__ int xcd_remap(int b, int nblk) {
+  constexpr int kXcd = 8;
+  const int q = nblk / kXcd, rem = nblk % kXcd;
+  const int x = b % kXcd;
+  return x * q + min(x, rem) + b / kXcd;
 }
 
 // DFT of R points, A_k = sum_t a_t exp(sg * 2 pi i t k / R)
@@ -120,9 +138,10 @@ __device__ __forceinline__ void butterfly<8>(float2* a, float sg) {
 // buf[b * stride + n].  Input element j + t*N/R of a transform, output element
 // (j - k) * R + k + t * Ns with k = j mod Ns (decimation in time).  Inputs are
 // read into registers before the barrier, so the update is in place.  The
-// stage's twiddles exp(-2 pi i t k/(Ns R)) sit in LDS at tw[k (R-1) + t - 1].
+// stage's twiddles exp(-2 pi i t k/(Ns R)) = W_N^(t k es) come from the
+// transform's two-level table in LDS.
 template <int R, int T>
-__device__ void fft_stage(float2* buf, int stride, int batch, const FftStage& S, const float2* tw, float sg) {
+__device__ __forceinline__ void fft_stage(float2* buf, int stride, int batch, const FftStage& S, const float2* tw, float sg) {
   constexpr int kMaxB = (kFftLdsComplex / R + T - 1) / T;
   const int per = S.per;
   const int Ns = S.ns;
@@ -141,10 +160,10 @@ __device__ void fft_stage(float2* buf, int stride, int batch, const FftStage& S,
       const int k = j - static_cast<int>(fdiv(static_cast<uint32_t>(j), S.ns_div)) * Ns;
       out[m] = base + (j - k) * R + k;
       if (Ns > 1) {
-        const float2* w = tw + k * (R - 1);
+        const int ek = k * S.es;
 #pragma unroll
         for (int t = 1; t < R; ++t) {
-          float2 wt = w[t - 1];
+          float2 wt = twiddle(tw, t * ek);
           wt.y = sg > 0.0f ? -wt.y : wt.y;  // the inverse takes the conjugate
           a[m][t] = cmul(a[m][t], wt);
         }
@@ -166,16 +185,15 @@ __device__ void fft_stage(float2* buf, int stride, int batch, const FftStage& S,
 
 // Full transform: forward (sg = -1) or inverse without scaling (sg = +1).
 template <int T>
-__device__ void lds_fft(float2* buf, int stride, int batch, const FftSize& sz, const float2* tw, float sg) {
+__device__ __forceinline__ void lds_fft(float2* buf, int stride, int batch, const FftSize& sz, const float2* tw, float sg) {
   for (int s = 0; s < sz.nstages; ++s) {
     const FftStage& S = sz.st[s];
-    const float2* w = tw + S.tw_off;
     switch (S.radix) {
-      case 2: fft_stage<2, T>(buf, stride, batch, S, w, sg); break;
-      case 3: fft_stage<3, T>(buf, stride, batch, S, w, sg); break;
-      case 4: fft_stage<4, T>(buf, stride, batch, S, w, sg); break;
-      case 5: fft_stage<5, T>(buf, stride, batch, S, w, sg); break;
-      default: fft_stage<8, T>(buf, stride, batch, S, w, sg); break;
+      case 2: fft_stage<2, T>(buf, stride, batch, S, tw, sg); break;
+      case 3: fft_stage<3, T>(buf, stride, batch, S, tw, sg); break;
+      case 4: fft_stage<4, T>(buf, stride, batch, S, tw, sg); break;
+      case 5: fft_stage<5, T>(buf, stride, batch, S, tw, sg); break;
+      default: fft_stage<8, T>(buf, stride, batch, S, tw, sg); break;
     }
   }
 }
@@ -223,14 +241,14 @@ __device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __rest
 
 // ---------------------------------------------------------------------------
 // Pass 1: c = lam (D_x^T r_x + D_y^T r_y), real FFT of each row, transposed store
-// LDS: [stage twiddles of W/2: M][split twiddles: M+1][rows: rb x (M+1)]
+// LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1)]
 // ---------------------------------------------------------------------------
 template <int FT>
-__global__ void __launch_bounds__(kFftThreads)
+__global__ void __launch_bounds__(kFftThreads, 4)
 fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   constexpr int T = kFftThreads;
   extern __shared__ float2 smem[];
-  const int item = blockIdx.x;
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
   const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
   const int blk = item - P.row_begin;
   if (blk >= P.row_count) return;
@@ -240,10 +258,10 @@ fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   const float lam = P.lambda;
   const int tid = threadIdx.x;
   float2* twS = smem;
-  float2* twR = smem + M;
-  float2* buf = smem + 2 * M + 1;
-  stage_twiddles<T>(twS, P.twM, M - 1);
-  stage_twiddles<T>(twR, P.twW, M + 1);
+  float2* twR = smem + kTwMax;
+  float2* buf = smem + 2 * kTwMax;
+  stage_twiddles<T>(twS, P.twM, P.ntwM);
+  stage_twiddles<T>(twR, P.twW, P.ntwW);
 
   // right-hand side of the residual-form solve, packed two reals per complex
   const FastDiv mdiv = P.m_div;
@@ -282,19 +300,19 @@ fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes) {
     const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     // o = (zk - conj(zm)) / (2i)
     const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-    spec[static_cast<int64_t>(k) * H + i0 + row] = cadd(e, cmul(twR[k], o));
+    spec[static_cast<int64_t>(k) * H + i0 + row] = cadd(e, cmul(twiddle(twR, k), o));
   }
 }
 
 // ---------------------------------------------------------------------------
 // Pass 2: per spectrum column, forward FFT over H, divide, inverse FFT over H
-// LDS: [stage twiddles of H: H][columns: cb x H]
+// LDS: [table of W_H: kTwMax][columns: cb x H]
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kFftThreads)
+__global__ void __launch_bounds__(kFftThreads, 4)
 fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   constexpr int T = kFftThreads;
   extern __shared__ float2 smem[];
-  const int item = blockIdx.x;
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
   const FftPlane& P = planes[find_fft_plane<true>(planes, nplanes, item)];
   const int blk = item - P.col_begin;
   if (blk >= P.col_count) return;
@@ -303,9 +321,9 @@ fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   const int ncols = min(P.cb, M + 1 - k0);
   const int tid = threadIdx.x;
   float2* twS = smem;
-  float2* buf = smem + H;
+  float2* buf = smem + kTwMax;
   float2* spec = P.spec + static_cast<int64_t>(k0) * H;
-  stage_twiddles<T>(twS, P.twH, H - 1);
+  stage_twiddles<T>(twS, P.twH, P.ntwH);
   for (int idx = tid; idx < ncols * H; idx += T) buf[idx] = spec[idx];
   __syncthreads();
   lds_fft<T>(buf, H, ncols, *P.szH, twS, -1.0f);
@@ -324,13 +342,13 @@ fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes) {
 
 // ---------------------------------------------------------------------------
 // Pass 3: complex-to-real inverse of each row, u = f + delta
-// LDS: [stage twiddles of W/2: M][split twiddles: M+1][rows: rb x (M+1)]
+// LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1)]
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kFftThreads)
+__global__ void __launch_bounds__(kFftThreads, 4)
 fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   constexpr int T = kFftThreads;
   extern __shared__ float2 smem[];
-  const int item = blockIdx.x;
+  const int item = xcd_remap(blockIdx.x, gridDim.x);
   const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
   const int blk = item - P.row_begin;
   if (blk >= P.row_count) return;
@@ -340,10 +358,10 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   const int nrows = min(P.rb, H - i0);
   const int tid = threadIdx.x;
   float2* twS = smem;
-  float2* twR = smem + M;
-  float2* buf = smem + 2 * M + 1;
-  stage_twiddles<T>(twS, P.twM, M - 1);
-  stage_twiddles<T>(twR, P.twW, M + 1);
+  float2* twR = smem + kTwMax;
+  float2* buf = smem + 2 * kTwMax;
+  stage_twiddles<T>(twS, P.twM, P.ntwM);
+  stage_twiddles<T>(twR, P.twW, P.ntwW);
   const float2* spec = P.spec;
   for (int idx = tid; idx < S * nrows; idx += T) {
     int k, row;
@@ -365,8 +383,8 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
     const int k = idx - row * (half + 1);
     float2* X = buf + row * S;
     const float2 a = X[k], b = X[M - k];
-    const float2 wa = cconj(twR[k]);  // exp(+2 pi i k/W)
-    const float2 wb = cconj(twR[M - k]);
+    const float2 wa = cconj(twiddle(twR, k));  // exp(+2 pi i k/W)
+    const float2 wb = cconj(twiddle(twR, M - k));
     const float2 sa = cadd(a, cconj(b)), da = csub(a, cconj(b));
     const float2 za = cadd(sa, cmul_isg(cmul(wa, da), 1.0f));
     const float2 sb = cadd(b, cconj(a)), db = csub(b, cconj(a));
@@ -392,8 +410,8 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-size_t fft_rows_lds_bytes(int M, int rb) { return static_cast<size_t>(2 * M + 1 + rb * (M + 1)) * sizeof(float2); }
-size_t fft_cols_lds_bytes(int H, int cb) { return static_cast<size_t>(H + cb * H) * sizeof(float2); }
+size_t fft_rows_lds_bytes(int M, int rb) { return static_cast<size_t>(2 * kTwMax + rb * (M + 1)) * sizeof(float2); }
+size_t fft_cols_lds_bytes(int H, int cb) { return static_cast<size_t>(kTwMax + cb * H) * sizeof(float2); }
 
 hipError_t fft_init_kernels() {
   const int kMax = 160 * 1024;
