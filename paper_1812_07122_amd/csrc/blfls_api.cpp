@@ -456,7 +456,7 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   if (e != hipSuccess) return hip_error(e, "hipGetDevice");
   if (dev != plan->device) return set_error(BLFLS_E_INVALID, "the current device differs from the plan's device");
 
-  // descriptors: tables, then each array, 256-byte aligned, in the workspace
+  // descriptors: tables, then each array, 16-byte aligned, in the workspace
   RequestDesc rd;
   uint8_t* ws = static_cast<uint8_t*>(workspace);
   uint8_t* dbase = ws + plan->off_desc;
@@ -464,7 +464,7 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   std::vector<uint8_t> blob;
   blob.reserve(8192);
   auto place = [&](const void* src, size_t n) {
-    const size_t off = align_up(blob.size(), 256);
+    const size_t off = align_up(blob.size(), 16);
     blob.resize(off + n);
     std::memcpy(blob.data() + off, src, n);
     return off;
