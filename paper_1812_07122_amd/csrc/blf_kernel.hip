@@ -116,20 +116,42 @@ blf_field_kernel(const BlfPlane* __restrict__ planes, int nplanes, int field_typ
   const float* __restrict__ g = P.g ? P.g : P.f;
   const int64_t pitch = P.pitch;
   const int64_t gpitch = P.g ? P.gpitch : P.pitch;
-  for (int idx = tid; idx < LH * LW; idx += T) {
-    const int a = idx / LW;
-    const int b = idx - a * LW;
-    const int ra = rowmap[a];
-    const int c0 = colmap[b];
-    // neighbour along the field's axis
-    const int rn = field ? rowmap[a + 1] : ra;
-    const int c1 = field ? c0 : colmap[b + 1];
-    const float pv = f[rn * pitch + c1] - f[ra * pitch + c0];
-    if (JOINT) {
-      p_lds[idx] = pv;
-      q_lds[idx] = c * (g[rn * gpitch + c1] - g[ra * gpitch + c0]);
-    } else {
-      q_lds[idx] = c * pv;
+  // gradients of the halo tile; each thread issues kFill element loads before
+  // writing any of them to LDS, so one memory round trip covers kFill elements
+  constexpr int kFill = 4;
+  for (int base = tid; base < LH * LW; base += T * kFill) {
+    float f0[kFill], f1[kFill], g0[kFill], g1[kFill];
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const int idx = base + u * T;
+      if (idx < LH * LW) {
+        const int a = idx / LW;
+        const int b = idx - a * LW;
+        const int ra = rowmap[a];
+        const int c0 = colmap[b];
+        // neighbour along the field's axis
+        const int rn = field ? rowmap[a + 1] : ra;
+        const int c1 = field ? c0 : colmap[b + 1];
+        f0[u] = f[ra * pitch + c0];
+        f1[u] = f[rn * pitch + c1];
+        if (JOINT) {
+          g0[u] = g[ra * gpitch + c0];
+          g1[u] = g[rn * gpitch + c1];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kFill; ++u) {
+      const int idx = base + u * T;
+      if (idx < LH * LW) {
+        const float pv = f1[u] - f0[u];
+        if (JOINT) {
+          p_lds[idx] = pv;
+          q_lds[idx] = c * (g1[u] - g0[u]);
+        } else {
+          q_lds[idx] = c * pv;
+        }
+      }
     }
   }
   __syncthreads();

@@ -237,6 +237,10 @@ __device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __rest
   for (int i = threadIdx.x; i < n; i += T) dst[i] = src[i];
 }
 
+// Global -> LDS copies issue kLoadBatch loads per thread before storing any of
+// them, so one memory round trip covers kLoadBatch elements instead of one.
+constexpr int kLoadBatch = 8;
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -265,21 +269,36 @@ fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes) {
 
   // right-hand side of the residual-form solve, packed two reals per complex
   const FastDiv mdiv = P.m_div;
-  for (int idx = tid; idx < nrows * M; idx += T) {
-    const int row = static_cast<int>(fdiv(static_cast<uint32_t>(idx), mdiv));
-    const int n = idx - row * M;
-    const int i = i0 + row;
-    const int im1 = i == 0 ? H - 1 : i - 1;
-    const int j0 = 2 * n;
-    const int jm = j0 == 0 ? W - 1 : j0 - 1;
-    const int64_t ri = static_cast<int64_t>(i) * W;
-    const float2 x = load_pair<FT>(P.rx, ri + j0);
-    const float2 y = load_pair<FT>(P.ry, ri + j0);
-    const float2 yp = load_pair<FT>(P.ry, static_cast<int64_t>(im1) * W + j0);
-    const float xm = load_one<FT>(P.rx, ri + jm);
-    const float c0 = lam * ((xm - x.x) + (yp.x - y.x));
-    const float c1 = lam * ((x.x - x.y) + (yp.y - y.y));
-    buf[row * M + n] = make_float2(c0, c1);
+  const int ntot = nrows * M;
+  for (int base = tid; base < ntot; base += T * kLoadBatch) {
+    float2 x[kLoadBatch], y[kLoadBatch], yp[kLoadBatch];
+    float xm[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int idx = base + u * T;
+      if (idx < ntot) {
+        const int row = static_cast<int>(fdiv(static_cast<uint32_t>(idx), mdiv));
+        const int n = idx - row * M;
+        const int i = i0 + row;
+        const int im1 = i == 0 ? H - 1 : i - 1;
+        const int j0 = 2 * n;
+        const int jm = j0 == 0 ? W - 1 : j0 - 1;
+        const int64_t ri = static_cast<int64_t>(i) * W;
+        x[u] = load_pair<FT>(P.rx, ri + j0);
+        y[u] = load_pair<FT>(P.ry, ri + j0);
+        yp[u] = load_pair<FT>(P.ry, static_cast<int64_t>(im1) * W + j0);
+        xm[u] = load_one<FT>(P.rx, ri + jm);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int idx = base + u * T;
+      if (idx < ntot) {
+        const float c0 = lam * ((xm[u] - x[u].x) + (yp[u].x - y[u].x));
+        const float c1 = lam * ((x[u].x - x[u].y) + (yp[u].y - y[u].y));
+        buf[idx] = make_float2(c0, c1);  // row * M + n == idx
+      }
+    }
   }
   __syncthreads();
   lds_fft<T>(buf, M, nrows, *P.szM, twS, -1.0f);
@@ -324,7 +343,16 @@ fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   float2* buf = smem + kTwMax;
   float2* spec = P.spec + static_cast<int64_t>(k0) * H;
   stage_twiddles<T>(twS, P.twH, P.ntwH);
-  for (int idx = tid; idx < ncols * H; idx += T) buf[idx] = spec[idx];
+  const int n = ncols * H;
+  for (int base = tid; base < n; base += T * kLoadBatch) {
+    float2 v[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u)
+      if (base + u * T < n) v[u] = spec[base + u * T];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u)
+      if (base + u * T < n) buf[base + u * T] = v[u];
+  }
   __syncthreads();
   lds_fft<T>(buf, H, ncols, *P.szH, twS, -1.0f);
   const float lam = P.lambda;
@@ -363,16 +391,29 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   stage_twiddles<T>(twS, P.twM, P.ntwM);
   stage_twiddles<T>(twR, P.twW, P.ntwW);
   const float2* spec = P.spec;
-  for (int idx = tid; idx < S * nrows; idx += T) {
-    int k, row;
-    if (nrows == P.rb) {
-      k = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.rb_div));
-      row = idx - k * nrows;
-    } else {
-      k = idx / nrows;
-      row = idx - k * nrows;
+  const int ntot = S * nrows;
+  for (int base = tid; base < ntot; base += T * kLoadBatch) {
+    float2 v[kLoadBatch];
+    int dst[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int idx = base + u * T;
+      if (idx < ntot) {
+        int k, row;
+        if (nrows == P.rb) {
+          k = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.rb_div));
+          row = idx - k * nrows;
+        } else {
+          k = idx / nrows;
+          row = idx - k * nrows;
+        }
+        v[u] = spec[static_cast<int64_t>(k) * H + i0 + row];
+        dst[u] = row * S + k;
+      }
     }
-    buf[row * S + k] = spec[static_cast<int64_t>(k) * H + i0 + row];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u)
+      if (base + u * T < ntot) buf[dst[u]] = v[u];
   }
   __syncthreads();
   // Z[k] = (X[k] + conj X[M-k]) + i exp(2 pi i k/W) (X[k] - conj X[M-k]), k = 0..M-1;
@@ -395,15 +436,33 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   __syncthreads();
   lds_fft<T>(buf, S, nrows, *P.szM, twS, 1.0f);
   const float* f = P.f;
-  float* u = P.u;
+  float* uout = P.u;
   const int64_t pitch = P.pitch;
-  for (int idx = tid; idx < nrows * M; idx += T) {
-    const int row = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.m_div));
-    const int n = idx - row * M;
-    const int64_t o = static_cast<int64_t>(i0 + row) * pitch + 2 * n;
-    const float2 z = buf[row * S + n];
-    u[o] = f[o] + z.x;
-    u[o + 1] = f[o + 1] + z.y;
+  const int nout = nrows * M;
+  for (int base = tid; base < nout; base += T * kLoadBatch) {
+    float fv0[kLoadBatch], fv1[kLoadBatch];
+    int64_t off[kLoadBatch];
+    int li[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int idx = base + u * T;
+      if (idx < nout) {
+        const int row = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.m_div));
+        const int n = idx - row * M;
+        off[u] = static_cast<int64_t>(i0 + row) * pitch + 2 * n;
+        li[u] = row * S + n;
+        fv0[u] = f[off[u]];
+        fv1[u] = f[off[u] + 1];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      if (base + u * T < nout) {
+        const float2 z = buf[li[u]];
+        uout[off[u]] = fv0[u] + z.x;
+        uout[off[u] + 1] = fv1[u] + z.y;
+      }
+    }
   }
 }
 
