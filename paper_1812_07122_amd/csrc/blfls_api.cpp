@@ -28,11 +28,15 @@ thread_local std::string g_last_error;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Factor n into radices 8, 4, 2, 3, 5 (powers of two as 8s, then one 4 or 2);
-// false if another prime divides n.
-bool factorize(int n, std::vector<int>* radices) {
+// Factor n into radices up to max_pow2 (16 or 8) for the powers of two, then one
+// 8, 4 or 2, then 3s and 5s; false if another prime divides n.  Row transforms
+// use at most radix 8 (their first stage reads HBM and needs enough butterflies
+// to occupy the workgroup), column transforms radix 16 (fewer barriers).
+bool factorize(int n, std::vector<int>* radices, int max_pow2 = 16) {
   radices->clear();
   int m = n;
+  if (max_pow2 >= 16)
+    while (m % 16 == 0) { radices->push_back(16); m /= 16; }
   while (m % 8 == 0) { radices->push_back(8); m /= 8; }
   if (m % 4 == 0) { radices->push_back(4); m /= 4; }
   if (m % 2 == 0) { radices->push_back(2); m /= 2; }
@@ -68,9 +72,9 @@ std::vector<float2> two_level_table(int n, int emax) {
 }
 
 // Stage descriptors of one transform length and its twiddle table.
-void build_fft_size(int n, FftSize* sz, std::vector<float2>* tw) {
+void build_fft_size(int n, FftSize* sz, std::vector<float2>* tw, int max_pow2) {
   std::vector<int> rad;
-  factorize(n, &rad);
+  factorize(n, &rad, max_pow2);
   std::memset(sz, 0, sizeof(*sz));
   sz->n = n;
   sz->nstages = static_cast<int>(rad.size());
@@ -154,8 +158,8 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   // tables, built in FP64 and rounded once to FP32
   FftSize szM, szH;
   std::vector<float2> twM, twH;
-  build_fft_size(M, &szM, &twM);
-  build_fft_size(H, &szH, &twH);
+  build_fft_size(M, &szM, &twM, 8);
+  build_fft_size(H, &szH, &twH, 16);
   const std::vector<float2> twW = two_level_table(W, M + 1);
   std::vector<float> sx(M + 1), sy(H);
   for (int k = 0; k <= M; ++k) {

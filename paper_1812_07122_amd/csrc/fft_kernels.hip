@@ -134,31 +134,76 @@ __device__ __forceinline__ void butterfly<8>(float2* a, float sg) {
   }
 }
 
-// One in-place Stockham stage over `batch` transforms of length N at
-// buf[b * stride + n].  Input element j + t*N/R of a transform, output element
-// (j - k) * R + k + t * Ns with k = j mod Ns (decimation in time).  Inputs are
-// read into registers before the barrier, so the update is in place.  The
-// stage's twiddles exp(-2 pi i t k/(Ns R)) = W_N^(t k es) come from the
-// transform's two-level table in LDS.
-template <int R, int T>
-__device__ __forceinline__ void fft_stage(float2* buf, int stride, int batch, const FftStage& S, const float2* tw, float sg) {
-  constexpr int kMaxB = (kFftLdsComplex / R + T - 1) / T;
+// Radix 16 as 4 x 4: with t = t1 + 4 t2 and k = 4 k1 + k2,
+// A_{4k1+k2} = sum_{t1} w4^{t1 k1} [ w16^{t1 k2} sum_{t2} a_{t1+4t2} w4^{t2 k2} ].
+template <>
+__device__ __forceinline__ void butterfly<16>(float2* a, float sg) {
+  // cos and sin of 2 pi m / 16, m = 0..3
+  constexpr float kC[4] = {1.0f, 0.92387953251128675613f, 0.70710678118654752440f, 0.38268343236508977173f};
+  constexpr float kS[4] = {0.0f, 0.38268343236508977173f, 0.70710678118654752440f, 0.92387953251128675613f};
+  float2 b[4][4];
+#pragma unroll
+  for (int t1 = 0; t1 < 4; ++t1) {
+    float2 c[4] = {a[t1], a[t1 + 4], a[t1 + 8], a[t1 + 12]};
+    butterfly<4>(c, sg);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      const int m = t1 * k2;  // w16^m, m <= 9
+      float2 w;
+      if (m < 4) w = make_float2(kC[m], sg * kS[m]);
+      else if (m < 8) w = make_float2(-kS[m - 4], sg * kC[m - 4]);  // exp(i (pi/2 + x))
+      else w = make_float2(-kC[m - 8], -sg * kS[m - 8]);           // exp(i (pi + x))
+      b[k2][t1] = m == 0 ? c[k2] : cmul(c[k2], w);
+    }
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < 4; ++k2) {
+    butterfly<4>(b[k2], sg);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) a[4 * k1 + k2] = b[k2][k1];
+  }
+}
+
+// Padded LDS index: one spare slot per 16 complex values, so the stride-R
+// writes of the early Stockham stages spread over the LDS banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
+
+// Element sources and destinations of a stage; b is the transform, n the element.
+struct LdsIO {  // in-place LDS buffer (padded layout)
+  static constexpr bool kLds = true;
+  float2* buf;
+  int stride;
+  __device__ __forceinline__ float2 load(int b, int n) const { return buf[pad(b * stride + n)]; }
+  __device__ __forceinline__ void store(int b, int n, float2 v) const { buf[pad(b * stride + n)] = v; }
+};
+
+// One Stockham stage over `batch` transforms of length N.  Input element
+// j + t*N/R of a transform, output element (j - k) R + k + t Ns with
+// k = j mod Ns (decimation in time).  The stage's twiddles
+// exp(-2 pi i t k/(Ns R)) = W_N^(t k es) come from the transform's two-level
+// table in LDS.  When both ends are the same LDS buffer the inputs are read
+// into registers before a barrier, so the update is in place; a barrier
+// follows any stage that writes LDS.
+template <int R, int T, int MAXE, class SRC, class DST>
+__device__ __forceinline__ void fft_stage(const SRC& src, const DST& dst, int batch, const FftStage& S,
+                                          const float2* tw, float sg) {
+  constexpr int kMaxB = (MAXE / R + T - 1) / T;
   const int per = S.per;
   const int Ns = S.ns;
   const int total = per * batch;
   float2 a[kMaxB][R];
-  int out[kMaxB];
+  int outb[kMaxB], outn[kMaxB];
 #pragma unroll
   for (int m = 0; m < kMaxB; ++m) {
     const int g = threadIdx.x + m * T;
     if (g < total) {
       const int b = static_cast<int>(fdiv(static_cast<uint32_t>(g), S.per_div));
       const int j = g - b * per;
-      const int base = b * stride;
 #pragma unroll
-      for (int t = 0; t < R; ++t) a[m][t] = buf[base + j + t * per];
+      for (int t = 0; t < R; ++t) a[m][t] = src.load(b, j + t * per);
       const int k = j - static_cast<int>(fdiv(static_cast<uint32_t>(j), S.ns_div)) * Ns;
-      out[m] = base + (j - k) * R + k;
+      outb[m] = b;
+      outn[m] = (j - k) * R + k;
       if (Ns > 1) {
         const int ek = k * S.es;
 #pragma unroll
@@ -170,32 +215,51 @@ __device__ __forceinline__ void fft_stage(float2* buf, int stride, int batch, co
       }
     }
   }
-  __syncthreads();
+  if (SRC::kLds && DST::kLds) __syncthreads();
 #pragma unroll
   for (int m = 0; m < kMaxB; ++m) {
     const int g = threadIdx.x + m * T;
     if (g < total) {
       butterfly<R>(a[m], sg);
 #pragma unroll
-      for (int t = 0; t < R; ++t) buf[out[m] + t * Ns] = a[m][t];
+      for (int t = 0; t < R; ++t) dst.store(outb[m], outn[m] + t * Ns, a[m][t]);
     }
   }
-  __syncthreads();
+  if (DST::kLds) __syncthreads();
 }
 
-// Full transform: forward (sg = -1) or inverse without scaling (sg = +1).
-template <int T>
-__device__ __forceinline__ void lds_fft(float2* buf, int stride, int batch, const FftSize& sz, const float2* tw, float sg) {
-  for (int s = 0; s < sz.nstages; ++s) {
-    const FftStage& S = sz.st[s];
-    switch (S.radix) {
-      case 2: fft_stage<2, T>(buf, stride, batch, S, tw, sg); break;
-      case 3: fft_stage<3, T>(buf, stride, batch, S, tw, sg); break;
-      case 4: fft_stage<4, T>(buf, stride, batch, S, tw, sg); break;
-      case 5: fft_stage<5, T>(buf, stride, batch, S, tw, sg); break;
-      default: fft_stage<8, T>(buf, stride, batch, S, tw, sg); break;
-    }
+template <int T, int MAXE, class SRC, class DST>
+__device__ __forceinline__ void fft_stage_r(const SRC& src, const DST& dst, int batch, const FftStage& S,
+                                            const float2* tw, float sg) {
+  switch (S.radix) {
+    case 2: fft_stage<2, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    case 3: fft_stage<3, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    case 4: fft_stage<4, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    case 5: fft_stage<5, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    case 8: fft_stage<8, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    default: fft_stage<16, T, MAXE>(src, dst, batch, S, tw, sg); break;
   }
+}
+
+// Whole transform, forward (sg = -1) or inverse without scaling (sg = +1): the
+// first stage reads `src`, the last writes `dst`, the others work in place in
+// `lds`.  A length-1 transform copies.
+template <int T, int MAXE, class SRC, class DST>
+__device__ __forceinline__ void fft_run(const FftSize& sz, const float2* tw, float sg, int batch, const SRC& src,
+                                        const LdsIO& lds, const DST& dst) {
+  const int n = sz.nstages;
+  if (n == 0) {
+    for (int b = threadIdx.x; b < batch; b += T) dst.store(b, 0, src.load(b, 0));
+    if (DST::kLds) __syncthreads();
+    return;
+  }
+  if (n == 1) {
+    fft_stage_r<T, MAXE>(src, dst, batch, sz.st[0], tw, sg);
+    return;
+  }
+  fft_stage_r<T, MAXE>(src, lds, batch, sz.st[0], tw, sg);
+  for (int s = 1; s < n - 1; ++s) fft_stage_r<T, MAXE>(lds, lds, batch, sz.st[s], tw, sg);
+  fft_stage_r<T, MAXE>(lds, dst, batch, sz.st[n - 1], tw, sg);
 }
 
 // Two consecutive field values at an even index, as FP32.
@@ -244,8 +308,72 @@ constexpr int kLoadBatch = 8;
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Stage sources and destinations of the three passes
+// ---------------------------------------------------------------------------
+
+// Right-hand side of the residual-form solve for row i0 + b, two reals per
+// complex: c(i, j) = lam ((r_x(i, j-1) - r_x(i, j)) + (r_y(i-1, j) - r_y(i, j))).
+template <int FT>
+struct RhsSrc {
+  static constexpr bool kLds = false;
+  const void* rx;
+  const void* ry;
+  int i0, H, W;
+  float lam;
+  __device__ __forceinline__ float2 load(int b, int n) const {
+    const int i = i0 + b;
+    const int im1 = i == 0 ? H - 1 : i - 1;
+    const int j0 = 2 * n;
+    const int jm = j0 == 0 ? W - 1 : j0 - 1;
+    const int64_t ri = static_cast<int64_t>(i) * W;
+    const float2 x = load_pair<FT>(rx, ri + j0);
+    const float2 y = load_pair<FT>(ry, ri + j0);
+    const float2 yp = load_pair<FT>(ry, static_cast<int64_t>(im1) * W + j0);
+    const float xm = load_one<FT>(rx, ri + jm);
+    return make_float2(lam * ((xm - x.x) + (yp.x - y.x)), lam * ((x.x - x.y) + (yp.y - y.y)));
+  }
+};
+
+// Spectrum columns in HBM ([W/2+1][H] layout, column b of the block).
+struct ColIO {
+  static constexpr bool kLds = false;
+  float2* spec;
+  int H;
+  __device__ __forceinline__ float2 load(int b, int n) const { return spec[static_cast<int64_t>(b) * H + n]; }
+  __device__ __forceinline__ void store(int b, int n, float2 v) const { spec[static_cast<int64_t>(b) * H + n] = v; }
+};
+
+// LDS destination that applies the Eq. (8) divide, 1 / (H W (1 + lam (sx + sy))).
+struct ScaledLds {
+  static constexpr bool kLds = true;
+  float2* buf;
+  int H, k0;
+  const float* sx;
+  const float* sy;
+  float lam, inv_hw;
+  __device__ __forceinline__ void store(int b, int n, float2 v) const {
+    const float den = fmaf(lam, sx[k0 + b] + sy[n], 1.0f);
+    buf[pad(b * H + n)] = cscale(v, inv_hw / den);
+  }
+};
+
+// u = f + delta for row i0 + b; element n holds the reals at columns 2n, 2n+1.
+struct OutDst {
+  static constexpr bool kLds = false;
+  const float* __restrict__ f;
+  float* __restrict__ u;
+  int64_t pitch;
+  int i0;
+  __device__ __forceinline__ void store(int b, int n, float2 v) const {
+    const int64_t o = static_cast<int64_t>(i0 + b) * pitch + 2 * n;
+    u[o] = f[o] + v.x;
+    u[o + 1] = f[o + 1] + v.y;
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Pass 1: c = lam (D_x^T r_x + D_y^T r_y), real FFT of each row, transposed store
-// LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1)]
+// LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1), padded]
 // ---------------------------------------------------------------------------
 template <int FT>
 __global__ void __launch_bounds__(kFftThreads, 4)
@@ -259,49 +387,16 @@ fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   const int H = P.H, W = P.W, M = W >> 1;
   const int i0 = blk * P.rb;
   const int nrows = min(P.rb, H - i0);
-  const float lam = P.lambda;
   const int tid = threadIdx.x;
   float2* twS = smem;
   float2* twR = smem + kTwMax;
   float2* buf = smem + 2 * kTwMax;
   stage_twiddles<T>(twS, P.twM, P.ntwM);
   stage_twiddles<T>(twR, P.twW, P.ntwW);
-
-  // right-hand side of the residual-form solve, packed two reals per complex
-  const FastDiv mdiv = P.m_div;
-  const int ntot = nrows * M;
-  for (int base = tid; base < ntot; base += T * kLoadBatch) {
-    float2 x[kLoadBatch], y[kLoadBatch], yp[kLoadBatch];
-    float xm[kLoadBatch];
-#pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u) {
-      const int idx = base + u * T;
-      if (idx < ntot) {
-        const int row = static_cast<int>(fdiv(static_cast<uint32_t>(idx), mdiv));
-        const int n = idx - row * M;
-        const int i = i0 + row;
-        const int im1 = i == 0 ? H - 1 : i - 1;
-        const int j0 = 2 * n;
-        const int jm = j0 == 0 ? W - 1 : j0 - 1;
-        const int64_t ri = static_cast<int64_t>(i) * W;
-        x[u] = load_pair<FT>(P.rx, ri + j0);
-        y[u] = load_pair<FT>(P.ry, ri + j0);
-        yp[u] = load_pair<FT>(P.ry, static_cast<int64_t>(im1) * W + j0);
-        xm[u] = load_one<FT>(P.rx, ri + jm);
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u) {
-      const int idx = base + u * T;
-      if (idx < ntot) {
-        const float c0 = lam * ((xm[u] - x[u].x) + (yp[u].x - y[u].x));
-        const float c1 = lam * ((x[u].x - x[u].y) + (yp[u].y - y[u].y));
-        buf[idx] = make_float2(c0, c1);  // row * M + n == idx
-      }
-    }
-  }
   __syncthreads();
-  lds_fft<T>(buf, M, nrows, *P.szM, twS, -1.0f);
+  // the first stage forms the right-hand side straight from the residual fields
+  const LdsIO lds{buf, M};
+  fft_run<T, kFftLdsComplex>(*P.szM, twS, -1.0f, nrows, RhsSrc<FT>{P.rx, P.ry, i0, H, W, P.lambda}, lds, lds);
 
   // split step: X[k] = E[k] + exp(-2 pi i k/W) O[k], k = 0..M, Z[M] = Z[0]
   float2* spec = P.spec;
@@ -314,8 +409,8 @@ fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes) {
       k = idx / nrows;
       row = idx - k * nrows;
     }
-    const float2 zk = buf[row * M + (k == M ? 0 : k)];
-    const float2 zm = buf[row * M + (k == 0 ? 0 : M - k)];
+    const float2 zk = buf[pad(row * M + (k == M ? 0 : k))];
+    const float2 zm = buf[pad(row * M + (k == 0 ? 0 : M - k))];
     const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     // o = (zk - conj(zm)) / (2i)
     const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
@@ -324,8 +419,10 @@ fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes) {
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2: per spectrum column, forward FFT over H, divide, inverse FFT over H
-// LDS: [table of W_H: kTwMax][columns: cb x H]
+// Pass 2: per spectrum column, forward FFT over H, divide, inverse FFT over H.
+// The forward transform reads the columns from HBM in its first stage and
+// applies the divide in its last; the inverse writes HBM in its last stage.
+// LDS: [table of W_H: kTwMax][columns: cb x H, padded]
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kFftThreads, 4)
 fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes) {
@@ -338,39 +435,22 @@ fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   const int H = P.H, W = P.W, M = W >> 1;
   const int k0 = blk * P.cb;
   const int ncols = min(P.cb, M + 1 - k0);
-  const int tid = threadIdx.x;
   float2* twS = smem;
   float2* buf = smem + kTwMax;
-  float2* spec = P.spec + static_cast<int64_t>(k0) * H;
   stage_twiddles<T>(twS, P.twH, P.ntwH);
-  const int n = ncols * H;
-  for (int base = tid; base < n; base += T * kLoadBatch) {
-    float2 v[kLoadBatch];
-#pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u)
-      if (base + u * T < n) v[u] = spec[base + u * T];
-#pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u)
-      if (base + u * T < n) buf[base + u * T] = v[u];
-  }
   __syncthreads();
-  lds_fft<T>(buf, H, ncols, *P.szH, twS, -1.0f);
-  const float lam = P.lambda;
-  const float inv_hw = 1.0f / (static_cast<float>(H) * static_cast<float>(W));
-  for (int idx = tid; idx < ncols * H; idx += T) {
-    const int col = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.h_div));
-    const int ky = idx - col * H;
-    const float den = fmaf(lam, P.sx[k0 + col] + P.sy[ky], 1.0f);
-    buf[idx] = cscale(buf[idx], inv_hw / den);
-  }
-  __syncthreads();
-  lds_fft<T>(buf, H, ncols, *P.szH, twS, 1.0f);
-  for (int idx = tid; idx < ncols * H; idx += T) spec[idx] = buf[idx];
+  const ColIO col{P.spec + static_cast<int64_t>(k0) * H, H};
+  const LdsIO lds{buf, H};
+  const ScaledLds scaled{buf, H, k0, P.sx, P.sy, P.lambda,
+                         1.0f / (static_cast<float>(H) * static_cast<float>(W))};
+  fft_run<T, kFftLdsComplex>(*P.szH, twS, -1.0f, ncols, col, lds, scaled);
+  fft_run<T, kFftLdsComplex>(*P.szH, twS, 1.0f, ncols, lds, lds, col);
 }
 
 // ---------------------------------------------------------------------------
-// Pass 3: complex-to-real inverse of each row, u = f + delta
-// LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1)]
+// Pass 3: complex-to-real inverse of each row, u = f + delta (written by the
+// last stage of the inverse transform)
+// LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1), padded]
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kFftThreads, 4)
 fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
@@ -408,7 +488,7 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
           row = idx - k * nrows;
         }
         v[u] = spec[static_cast<int64_t>(k) * H + i0 + row];
-        dst[u] = row * S + k;
+        dst[u] = pad(row * S + k);
       }
     }
 #pragma unroll
@@ -422,55 +502,28 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
   for (int idx = tid; idx < (half + 1) * nrows; idx += T) {
     const int row = idx / (half + 1);
     const int k = idx - row * (half + 1);
-    float2* X = buf + row * S;
-    const float2 a = X[k], b = X[M - k];
+    const int ia = pad(row * S + k), ib = pad(row * S + M - k);
+    const float2 a = buf[ia], b = buf[ib];
     const float2 wa = cconj(twiddle(twR, k));  // exp(+2 pi i k/W)
     const float2 wb = cconj(twiddle(twR, M - k));
     const float2 sa = cadd(a, cconj(b)), da = csub(a, cconj(b));
     const float2 za = cadd(sa, cmul_isg(cmul(wa, da), 1.0f));
     const float2 sb = cadd(b, cconj(a)), db = csub(b, cconj(a));
     const float2 zb = cadd(sb, cmul_isg(cmul(wb, db), 1.0f));
-    X[k] = za;
-    if (k != 0 && M - k != k) X[M - k] = zb;
+    buf[ia] = za;
+    if (k != 0 && M - k != k) buf[ib] = zb;
   }
   __syncthreads();
-  lds_fft<T>(buf, S, nrows, *P.szM, twS, 1.0f);
-  const float* f = P.f;
-  float* uout = P.u;
-  const int64_t pitch = P.pitch;
-  const int nout = nrows * M;
-  for (int base = tid; base < nout; base += T * kLoadBatch) {
-    float fv0[kLoadBatch], fv1[kLoadBatch];
-    int64_t off[kLoadBatch];
-    int li[kLoadBatch];
-#pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u) {
-      const int idx = base + u * T;
-      if (idx < nout) {
-        const int row = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.m_div));
-        const int n = idx - row * M;
-        off[u] = static_cast<int64_t>(i0 + row) * pitch + 2 * n;
-        li[u] = row * S + n;
-        fv0[u] = f[off[u]];
-        fv1[u] = f[off[u] + 1];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kLoadBatch; ++u) {
-      if (base + u * T < nout) {
-        const float2 z = buf[li[u]];
-        uout[off[u]] = fv0[u] + z.x;
-        uout[off[u] + 1] = fv1[u] + z.y;
-      }
-    }
-  }
+  const LdsIO lds{buf, S};
+  fft_run<T, kFftLdsComplex>(*P.szM, twS, 1.0f, nrows, lds, lds, OutDst{P.f, P.u, P.pitch, i0});
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-size_t fft_rows_lds_bytes(int M, int rb) { return static_cast<size_t>(2 * kTwMax + rb * (M + 1)) * sizeof(float2); }
-size_t fft_cols_lds_bytes(int H, int cb) { return static_cast<size_t>(kTwMax + cb * H) * sizeof(float2); }
+static size_t padded(int n) { return static_cast<size_t>(n) + static_cast<size_t>(n) / 16 + 1; }
+size_t fft_rows_lds_bytes(int M, int rb) { return (2 * kTwMax + padded(rb * (M + 1))) * sizeof(float2); }
+size_t fft_cols_lds_bytes(int H, int cb) { return (kTwMax + padded(cb * H)) * sizeof(float2); }
 
 hipError_t fft_init_kernels() {
   const int kMax = 160 * 1024;
