@@ -8,6 +8,7 @@
 //    guidance extension (Section III-D), as two separable passes.
 #include "blfls_internal.h"
 #include "blfls_launch.h"
+#include "blfls_work.h"
 
 namespace blfls {
 
@@ -33,12 +34,12 @@ hipError_t launch_desc_copy(const void* host_src, size_t bytes, void* dev_dst, h
 }
 
 // partial[b] = (min D_x, max D_x, min D_y, max D_y) over the elements of block b
-__global__ void __launch_bounds__(256) minmax_kernel(const AuxPlane* __restrict__ planes) {
-  const AuxPlane& P = planes[blockIdx.y];
+// (kMinmaxBlocks blocks per plane, elements strided over the blocks).
+__device__ __forceinline__ void minmax_item(const AuxPlane& P, int blk) {
   const int H = P.H, W = P.W;
   const int64_t n = static_cast<int64_t>(H) * W;
   float lx = INFINITY, hx = -INFINITY, ly = INFINITY, hy = -INFINITY;
-  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; idx < n;
+  for (int64_t idx = static_cast<int64_t>(blk) * 256 + threadIdx.x; idx < n;
        idx += static_cast<int64_t>(kMinmaxBlocks) * 256) {
     const int i = static_cast<int>(idx / W);
     const int j = static_cast<int>(idx - static_cast<int64_t>(i) * W);
@@ -69,24 +70,48 @@ __global__ void __launch_bounds__(256) minmax_kernel(const AuxPlane* __restrict_
       o0 = fminf(o0, red[w][0]); o1 = fmaxf(o1, red[w][1]);
       o2 = fminf(o2, red[w][2]); o3 = fmaxf(o3, red[w][3]);
     }
-    float* out = P.partial + blockIdx.x * 4;
+    float* out = P.partial + blk * 4;
     out[0] = o0; out[1] = o1; out[2] = o2; out[3] = o3;
+  }
+  __syncthreads();
+}
+
+// work == nullptr: grid (kMinmaxBlocks, planes); else a fixed grid strides over
+// the work header's planes x kMinmaxBlocks items.
+__global__ void __launch_bounds__(256) minmax_kernel(const AuxPlane* __restrict__ planes,
+                                                     WorkHeader* __restrict__ work) {
+  if (work == nullptr) {
+    minmax_item(planes[blockIdx.y], blockIdx.x);
+    return;
+  }
+  const AuxPlane* pl = static_cast<const AuxPlane*>(work->planes);
+  const int total = work->items;
+  for (;;) {
+    const int it = grab_item(work->next[0], total, false);
+    if (it >= total) break;
+    minmax_item(pl[it / kMinmaxBlocks], it % kMinmaxBlocks);
   }
 }
 
-hipError_t launch_minmax(const AuxPlane* planes, int nplanes, hipStream_t s) {
+hipError_t launch_minmax(const AuxPlane* planes, int nplanes, hipStream_t s, WorkHeader* work, int grid) {
+  if (work != nullptr) {
+    hipLaunchKernelGGL(minmax_kernel, dim3(grid), dim3(256), 0, s, planes, work);
+    return hipGetLastError();
+  }
   if (nplanes <= 0) return hipSuccess;
-  hipLaunchKernelGGL(minmax_kernel, dim3(kMinmaxBlocks, nplanes), dim3(256), 0, s, planes);
+  hipLaunchKernelGGL(minmax_kernel, dim3(kMinmaxBlocks, nplanes), dim3(256), 0, s, planes, work);
   return hipGetLastError();
 }
 
-// separable circular Gaussian: pass 0 rows (src -> tmp), pass 1 columns (tmp -> dst)
-__global__ void __launch_bounds__(256) gauss_kernel(const AuxPlane* __restrict__ planes, int pass) {
-  const AuxPlane& P = planes[blockIdx.y];
+// Separable circular Gaussian: pass 0 rows (src -> tmp), pass 1 columns (tmp -> dst).
+// Item (plane, chunk): chunk c of kGaussChunks covers pixels c*256 + k*kGaussChunks*256.
+constexpr int kGaussChunks = 256;
+
+__device__ __forceinline__ void gauss_item(const AuxPlane& P, int chunk, int pass) {
   const int H = P.H, W = P.W, rg = P.rg;
   const int64_t n = static_cast<int64_t>(H) * W;
-  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; idx < n;
-       idx += static_cast<int64_t>(gridDim.x) * 256) {
+  for (int64_t idx = static_cast<int64_t>(chunk) * 256 + threadIdx.x; idx < n;
+       idx += static_cast<int64_t>(kGaussChunks) * 256) {
     const int i = static_cast<int>(idx / W);
     const int j = static_cast<int>(idx - static_cast<int64_t>(i) * W);
     float acc = 0.0f;
@@ -109,16 +134,36 @@ __global__ void __launch_bounds__(256) gauss_kernel(const AuxPlane* __restrict__
   }
 }
 
-hipError_t launch_gauss(const AuxPlane* planes, int nplanes, int64_t max_pixels, hipStream_t s) {
-  if (nplanes <= 0) return hipSuccess;
-  int64_t blocks = (max_pixels + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+__global__ void __launch_bounds__(256) gauss_kernel(const AuxPlane* __restrict__ planes, int pass,
+                                                    WorkHeader* __restrict__ work) {
+  if (work == nullptr) {
+    gauss_item(planes[blockIdx.y], blockIdx.x, pass);
+    return;
+  }
+  const AuxPlane* pl = static_cast<const AuxPlane*>(work->planes);
+  const int total = work->items;
+  for (;;) {
+    // pass 0 draws from counter [1], pass 1 from [2]: both start at zero
+    const int it = grab_item(work->next[1 + pass], total, false);
+    if (it >= total) break;
+    gauss_item(pl[it / kGaussChunks], it % kGaussChunks, pass);
+  }
+}
+
+hipError_t launch_gauss(const AuxPlane* planes, int nplanes, int64_t max_pixels, hipStream_t s,
+                        WorkHeader* work, int grid) {
+  (void)max_pixels;
   for (int pass = 0; pass < 2; ++pass) {
-    hipLaunchKernelGGL(gauss_kernel, dim3(static_cast<unsigned>(blocks), nplanes), dim3(256), 0, s, planes, pass);
+    if (work != nullptr)
+      hipLaunchKernelGGL(gauss_kernel, dim3(grid), dim3(256), 0, s, planes, pass, work);
+    else if (nplanes > 0)
+      hipLaunchKernelGGL(gauss_kernel, dim3(kGaussChunks, nplanes), dim3(256), 0, s, planes, pass, work);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
+
+int gauss_chunks() { return kGaussChunks; }
 
 }  // namespace blfls

@@ -24,6 +24,7 @@
 // kernel off) keep p and q and form sum w*p / sum w - p_s.
 #include "blfls_internal.h"
 #include "blfls_launch.h"
+#include "blfls_work.h"
 
 namespace blfls {
 
@@ -76,9 +77,10 @@ __device__ __forceinline__ int find_plane(const BlfPlane* planes, int nplanes, i
 
 }  // namespace
 
+// One work item: one gradient field of one tile of one plane.
 template <int R, int K, int WAVES, bool JOINT>
-__global__ void __launch_bounds__(64 * WAVES)
-blf_field_kernel(const BlfPlane* __restrict__ planes, int nplanes, int field_type) {
+__device__ __forceinline__ void blf_item(const BlfPlane* __restrict__ planes, int nplanes, int field_type,
+                                         int item) {
   constexpr int TW = 64;
   constexpr int TH = WAVES * K;
   constexpr int LW = TW + 2 * R;
@@ -89,11 +91,10 @@ blf_field_kernel(const BlfPlane* __restrict__ planes, int nplanes, int field_typ
   __shared__ int rowmap[LH + 1];
   __shared__ int colmap[LW + 1];
 
-  const int item = blockIdx.x;
   const int pi = find_plane(planes, nplanes, item);
   const BlfPlane& P = planes[pi];
   const int local = item - 2 * P.tile_begin;
-  if (local >= 2 * P.tile_count) return;  // uniform: grid larger than the work
+  if (local >= 2 * P.tile_count) return;  // uniform: more items than work
   const int field = local >= P.tile_count ? 1 : 0;
   const int tile = local - field * P.tile_count;
   const int H = P.H, W = P.W;
@@ -221,6 +222,29 @@ blf_field_kernel(const BlfPlane* __restrict__ planes, int nplanes, int field_typ
   }
 }
 
+// Kernel: with work == nullptr the grid has exactly one workgroup per item;
+// otherwise (persistent launch from a captured graph) the work header in
+// device memory gives the items and the plane array, and the workgroups of a
+// fixed grid draw items from its counter.
+template <int R, int K, int WAVES, bool JOINT>
+__global__ void __launch_bounds__(64 * WAVES)
+blf_field_kernel(const BlfPlane* __restrict__ planes, int nplanes, int field_type,
+                 WorkHeader* __restrict__ work) {
+  if (work == nullptr) {
+    blf_item<R, K, WAVES, JOINT>(planes, nplanes, field_type, blockIdx.x);
+    return;
+  }
+  const int total = work->items;
+  const int np = work->nplanes;
+  const BlfPlane* pl = static_cast<const BlfPlane*>(work->planes);
+  for (;;) {
+    const int item = grab_item(work->next[0], total, false);
+    if (item >= total) break;
+    blf_item<R, K, WAVES, JOINT>(pl, np, field_type, item);
+    __syncthreads();  // the next item refills the LDS tile
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Launch: radius classes and tile shape
 // ---------------------------------------------------------------------------
@@ -231,13 +255,13 @@ constexpr int kWaves = 4;
 constexpr int kRadii[] = {1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 14, 16, 20, 24, 28, 32};
 
 template <int R>
-hipError_t launch_r(const BlfPlane* planes, int nplanes, int total_items, bool joint, int ft,
+hipError_t launch_r(const BlfPlane* planes, int nplanes, int total_items, bool joint, int ft, WorkHeader* work,
                     hipStream_t s) {
   dim3 grid(total_items), block(64 * kWaves);
   if (joint)
-    hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, true>), grid, block, 0, s, planes, nplanes, ft);
+    hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, true>), grid, block, 0, s, planes, nplanes, ft, work);
   else
-    hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, false>), grid, block, 0, s, planes, nplanes, ft);
+    hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, false>), grid, block, 0, s, planes, nplanes, ft, work);
   return hipGetLastError();
 }
 }  // namespace
@@ -252,10 +276,10 @@ int blf_tile_w() { return 64; }
 int blf_tile_h() { return kK * kWaves; }
 
 hipError_t launch_blf(int R, const BlfPlane* planes, int nplanes, int total_items, bool joint,
-                      int field_type, hipStream_t s) {
+                      int field_type, hipStream_t s, WorkHeader* work) {
   if (total_items <= 0) return hipSuccess;
   switch (R) {
-#define BLFLS_CASE(RR) case RR: return launch_r<RR>(planes, nplanes, total_items, joint, field_type, s);
+#define BLFLS_CASE(RR) case RR: return launch_r<RR>(planes, nplanes, total_items, joint, field_type, work, s);
     BLFLS_CASE(1) BLFLS_CASE(2) BLFLS_CASE(3) BLFLS_CASE(4) BLFLS_CASE(5) BLFLS_CASE(6)
     BLFLS_CASE(8) BLFLS_CASE(9) BLFLS_CASE(10) BLFLS_CASE(12) BLFLS_CASE(14) BLFLS_CASE(16)
     BLFLS_CASE(20) BLFLS_CASE(24) BLFLS_CASE(28) BLFLS_CASE(32)

@@ -188,8 +188,14 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   std::memcpy(blob.data() + o_sy, sy.data(), sy.size() * sizeof(float));
   e = hipMalloc(&p->dev_tables, off);
   if (e != hipSuccess) { delete p; return set_error(BLFLS_E_NOMEM, "hipMalloc of plan tables failed"); }
-  e = hipMemcpy(p->dev_tables, blob.data(), off, hipMemcpyHostToDevice);
-  if (e != hipSuccess) { (void)hipFree(p->dev_tables); delete p; return hip_error(e, "hipMemcpy plan tables"); }
+  // upload on a private non-blocking stream: a copy on the legacy stream would
+  // have to order itself against streams another thread may be capturing
+  hipStream_t up = nullptr;
+  e = hipStreamCreateWithFlags(&up, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMemcpyAsync(p->dev_tables, blob.data(), off, hipMemcpyHostToDevice, up);
+  if (e == hipSuccess) e = hipStreamSynchronize(up);
+  if (up) (void)hipStreamDestroy(up);
+  if (e != hipSuccess) { (void)hipFree(p->dev_tables); delete p; return hip_error(e, "plan table upload"); }
   uint8_t* base = static_cast<uint8_t*>(p->dev_tables);
   p->szM = reinterpret_cast<const FftSize*>(base + o_szM);
   p->szH = reinterpret_cast<const FftSize*>(base + o_szH);

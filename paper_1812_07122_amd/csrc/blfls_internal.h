@@ -114,4 +114,21 @@ struct AuxPlane {
   const float* gw;       // RequestTables::gw
 };
 
+// Work of one kernel family in a persistent launch, read from device memory
+// when the kernel runs (so a captured graph replays with new work): item
+// counts, plane counts, the plane descriptor array, and the item counters the
+// workgroups draw from (zero when uploaded; one per XCD for the FFT passes so
+// consecutive row blocks stay on one XCD).
+constexpr int kXcds = 8;
+struct WorkHeader {
+  int items;         // work items (FFT: row blocks)
+  int nplanes;
+  int items2;        // FFT column blocks
+  int pad_;
+  const void* planes;
+  int next[3][kXcds];  // counters: [0] filter / rows_fwd / aux, [1] cols, [2] rows_inv
+  uint64_t pad2_;
+};
+static_assert(sizeof(WorkHeader) == 128, "work header size");
+
 }  // namespace blfls

@@ -21,17 +21,25 @@ int blf_tile_w();
 int blf_tile_h();
 
 hipError_t launch_desc_copy(const void* host_src, size_t bytes, void* dev_dst, hipStream_t s);
+// work == nullptr: one workgroup per item (grid = total_items).  Otherwise a
+// persistent launch: grid = total_items workgroups stride over the items of
+// the work header (items, planes, descriptor array), read from device memory
+// when the kernel runs.
 hipError_t launch_blf(int R, const BlfPlane* planes, int nplanes, int total_items, bool joint,
-                      int field_type, hipStream_t s);
+                      int field_type, hipStream_t s, WorkHeader* work = nullptr);
 size_t fft_rows_lds_bytes(int M, int rb);
 size_t fft_cols_lds_bytes(int H, int cb);
 hipError_t fft_init_kernels();
 hipError_t launch_fft_rows_fwd(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
-                               int field_type, hipStream_t s);
-hipError_t launch_fft_cols(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes, hipStream_t s);
+                               int field_type, hipStream_t s, WorkHeader* work = nullptr);
+hipError_t launch_fft_cols(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes, hipStream_t s,
+                           WorkHeader* work = nullptr);
 hipError_t launch_fft_rows_inv(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
-                               hipStream_t s);
-hipError_t launch_minmax(const AuxPlane* planes, int nplanes, hipStream_t s);
-hipError_t launch_gauss(const AuxPlane* planes, int nplanes, int64_t max_pixels, hipStream_t s);
+                               hipStream_t s, WorkHeader* work = nullptr);
+hipError_t launch_minmax(const AuxPlane* planes, int nplanes, hipStream_t s, WorkHeader* work = nullptr,
+                         int grid = 0);
+hipError_t launch_gauss(const AuxPlane* planes, int nplanes, int64_t max_pixels, hipStream_t s,
+                        WorkHeader* work = nullptr, int grid = 0);
+int gauss_chunks();  // items per plane of the Gaussian passes
 
 }  // namespace blfls

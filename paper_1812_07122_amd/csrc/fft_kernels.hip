@@ -24,6 +24,7 @@
 // in one L2.
 #include "blfls_internal.h"
 #include "blfls_launch.h"
+#include "blfls_work.h"
 
 namespace blfls {
 
@@ -376,11 +377,9 @@ struct OutDst {
 // LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1), padded]
 // ---------------------------------------------------------------------------
 template <int FT>
-__global__ void __launch_bounds__(kFftThreads, 4)
-fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes) {
+__device__ __forceinline__ void rows_fwd_item(const FftPlane* __restrict__ planes, int nplanes, int item,
+                                              float2* smem) {
   constexpr int T = kFftThreads;
-  extern __shared__ float2 smem[];
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
   const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
   const int blk = item - P.row_begin;
   if (blk >= P.row_count) return;
@@ -424,11 +423,9 @@ fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes) {
 // applies the divide in its last; the inverse writes HBM in its last stage.
 // LDS: [table of W_H: kTwMax][columns: cb x H, padded]
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kFftThreads, 4)
-fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes) {
+__device__ __forceinline__ void cols_item(const FftPlane* __restrict__ planes, int nplanes, int item,
+                                          float2* smem) {
   constexpr int T = kFftThreads;
-  extern __shared__ float2 smem[];
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
   const FftPlane& P = planes[find_fft_plane<true>(planes, nplanes, item)];
   const int blk = item - P.col_begin;
   if (blk >= P.col_count) return;
@@ -452,11 +449,9 @@ fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes) {
 // last stage of the inverse transform)
 // LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1), padded]
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kFftThreads, 4)
-fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
+__device__ __forceinline__ void rows_inv_item(const FftPlane* __restrict__ planes, int nplanes, int item,
+                                              float2* smem) {
   constexpr int T = kFftThreads;
-  extern __shared__ float2 smem[];
-  const int item = xcd_remap(blockIdx.x, gridDim.x);
   const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
   const int blk = item - P.row_begin;
   if (blk >= P.row_count) return;
@@ -519,6 +514,64 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes) {
 }
 
 // ---------------------------------------------------------------------------
+// Kernels: with work == nullptr one workgroup per item; otherwise a fixed
+// (persistent) grid draws the items of the work header, read from device
+// memory when the kernel runs (launches captured in a graph), from one counter
+// per XCD.  Either way consecutive row blocks run on the same XCD.
+// ---------------------------------------------------------------------------
+template <int FT>
+__global__ void __launch_bounds__(kFftThreads, 4)
+fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
+  extern __shared__ float2 smem[];
+  if (work == nullptr) {
+    rows_fwd_item<FT>(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
+    return;
+  }
+  const int total = work->items, np = work->nplanes;
+  const FftPlane* pl = static_cast<const FftPlane*>(work->planes);
+  for (;;) {
+    const int item = grab_item(work->next[0], total, true);
+    if (item >= total) break;
+    rows_fwd_item<FT>(pl, np, item, smem);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kFftThreads, 4)
+fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
+  extern __shared__ float2 smem[];
+  if (work == nullptr) {
+    cols_item(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
+    return;
+  }
+  const int total = work->items2, np = work->nplanes;
+  const FftPlane* pl = static_cast<const FftPlane*>(work->planes);
+  for (;;) {
+    const int item = grab_item(work->next[1], total, true);
+    if (item >= total) break;
+    cols_item(pl, np, item, smem);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kFftThreads, 4)
+fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
+  extern __shared__ float2 smem[];
+  if (work == nullptr) {
+    rows_inv_item(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
+    return;
+  }
+  const int total = work->items, np = work->nplanes;
+  const FftPlane* pl = static_cast<const FftPlane*>(work->planes);
+  for (;;) {
+    const int item = grab_item(work->next[2], total, true);
+    if (item >= total) break;
+    rows_inv_item(pl, np, item, smem);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 static size_t padded(int n) { return static_cast<size_t>(n) + static_cast<size_t>(n) / 16 + 1; }
@@ -526,7 +579,7 @@ size_t fft_rows_lds_bytes(int M, int rb) { return (2 * kTwMax + padded(rb * (M +
 size_t fft_cols_lds_bytes(int H, int cb) { return (kTwMax + padded(cb * H)) * sizeof(float2); }
 
 hipError_t fft_init_kernels() {
-  const int kMax = 160 * 1024;
+  const int kMax = 128 * 1024;  // largest need is about 73 KiB; static LDS comes on top
   const void* fns[] = {reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF32>),
                        reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kBF16>),
                        reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF16>),
@@ -540,27 +593,29 @@ hipError_t fft_init_kernels() {
 }
 
 hipError_t launch_fft_rows_fwd(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
-                               int field_type, hipStream_t s) {
+                               int field_type, hipStream_t s, WorkHeader* work) {
   if (blocks <= 0) return hipSuccess;
+  const dim3 g(blocks), b(kFftThreads);
   if (field_type == kF32)
-    hipLaunchKernelGGL(fft_rows_fwd_kernel<kF32>, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes);
+    hipLaunchKernelGGL(fft_rows_fwd_kernel<kF32>, g, b, lds_bytes, s, planes, nplanes, work);
   else if (field_type == kBF16)
-    hipLaunchKernelGGL(fft_rows_fwd_kernel<kBF16>, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes);
+    hipLaunchKernelGGL(fft_rows_fwd_kernel<kBF16>, g, b, lds_bytes, s, planes, nplanes, work);
   else
-    hipLaunchKernelGGL(fft_rows_fwd_kernel<kF16>, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes);
+    hipLaunchKernelGGL(fft_rows_fwd_kernel<kF16>, g, b, lds_bytes, s, planes, nplanes, work);
   return hipGetLastError();
 }
 
-hipError_t launch_fft_cols(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_fft_cols(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes, hipStream_t s,
+                           WorkHeader* work) {
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fft_cols_kernel, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes);
+  hipLaunchKernelGGL(fft_cols_kernel, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes, work);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_rows_inv(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
-                               hipStream_t s) {
+                               hipStream_t s, WorkHeader* work) {
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fft_rows_inv_kernel, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes);
+  hipLaunchKernelGGL(fft_rows_inv_kernel, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes, work);
   return hipGetLastError();
 }
 

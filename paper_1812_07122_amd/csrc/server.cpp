@@ -98,11 +98,24 @@ class Arena {
 struct Job {
   uint64_t id = 0;
   double t_submit = 0.0;
+  size_t desc_bytes = 0;  // staging bytes of this request's tables and descriptors
   blfls_request req{};
   int radius = 0;
   blfls_plan_s* plan = nullptr;
   size_t ws_off = 0;
   RequestDesc rd;
+};
+
+// One launch group of a step: a kernel family over an array of plane descriptors.
+struct Group {
+  int kind;  // 0 gauss, 1 minmax, 2 blf, 3 fft
+  int R = 0;
+  bool joint = false;
+  std::vector<uint8_t> planes;  // descriptor array bytes
+  int n = 0;                    // planes
+  int items = 0, items2 = 0;    // work items (fft: rows, cols)
+  size_t lds_rows = 0, lds_cols = 0;
+  int64_t max_pix = 0;
 };
 
 struct Step {
@@ -144,145 +157,227 @@ struct blfls_server_s {
   std::vector<double> latencies;  // submit -> done, ms
   std::thread worker;
 
+  // staging layout of one slot: [work header][request tables][descriptor arrays]
+  static constexpr size_t kHeaderBytes = 16384;
+  static constexpr int kMaxGroups = static_cast<int>(kHeaderBytes / sizeof(WorkHeader));
+  static constexpr int kBlfGrid = 2048;  // persistent grids of the captured kernels
+  static constexpr int kFftGrid = 1024;
+  static constexpr int kAuxGrid = 1024;
+  size_t stage_bytes = 0;
+  size_t kFftLdsMax = 0;
+  hipStream_t capture_stream = nullptr;
+  std::map<std::pair<std::vector<int>, int>, hipGraphExec_t> graphs;
+  uint64_t stats_graph_steps = 0, stats_direct_steps = 0;
+
   void run();
   void retire(Step& st);
   void admit(std::vector<Job*>* admitted);
   hipError_t launch_step(Step& st, int slot);
+  hipError_t launch_direct(std::vector<Group>& groups, int slot, int ft, size_t tables_used);
+  hipError_t build_graph(const std::vector<Group>& groups, int slot, int ft, hipGraphExec_t* out);
 };
 
-namespace {
 
-// Append `n` bytes to the staging buffer at 256-byte alignment; returns the offset.
-struct Stager {
-  uint8_t* host;
-  uint8_t* dev;
-  size_t cap;
-  size_t used = 0;
-  bool overflow = false;
-  size_t put(const void* src, size_t n) {
-    const size_t off = align_up(used, 256);
-    if (off + n > cap) {
-      overflow = true;
-      return 0;
-    }
-    std::memcpy(host + off, src, n);
-    used = off + n;
-    return off;
-  }
-  size_t reserve(size_t n) {
-    const size_t off = align_up(used, 256);
-    if (off + n > cap) {
-      overflow = true;
-      return 0;
-    }
-    used = off + n;
-    return off;
-  }
-};
+template <class D>
+static void push_desc(Group& g, const D& d) {
+  const size_t off = g.planes.size();
+  g.planes.resize(off + sizeof(D));
+  std::memcpy(g.planes.data() + off, &d, sizeof(D));
+  g.n++;
+}
 
-}  // namespace
-
-hipError_t blfls_server_s::launch_step(Step& st, int slot) {
-  const int ft = precision == BLFLS_FP32 ? kF32 : precision == BLFLS_MIXED_BF16 ? kBF16 : kF16;
-  Stager sg{staging[slot], arena + slot * kStageBytes, kStageBytes};
-  // request tables first: the BLF and Gaussian descriptors point at them
-  std::vector<size_t> tab_off(st.jobs.size());
-  for (size_t j = 0; j < st.jobs.size(); ++j) tab_off[j] = sg.reserve(sizeof(RequestTables));
+static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
+  std::vector<Group> groups;
   int max_iter = 0;
-  for (size_t j = 0; j < st.jobs.size(); ++j) {
-    Job* jb = st.jobs[j];
-    const blfls_request& q = jb->req;
-    build_request(jb->plan, q.params, jb->radius, q.f, q.guide, q.u, q.pitch, arena + jb->ws_off,
-                  sg.dev + tab_off[j], &jb->rd);
-    std::memcpy(sg.host + tab_off[j], &jb->rd.tables, sizeof(RequestTables));
-    max_iter = std::max(max_iter, jb->rd.iterations);
-  }
-  hipError_t e = hipSuccess;
-  struct Launch {
-    int kind;  // 0 gauss, 1 minmax, 2 blf, 3 fft
-    int R;
-    bool joint;
-    size_t off;
-    int n;
-    int items;
-    int rows, cols;
-    size_t lds_rows, lds_cols;
-    int64_t max_pix;
-  };
-  std::vector<Launch> launches;
-  // Gaussian guide smoothing (before the first iteration)
+  for (Job* jb : jobs) max_iter = std::max(max_iter, jb->rd.iterations);
   {
-    std::vector<AuxPlane> g;
-    int64_t max_pix = 0;
-    for (Job* jb : st.jobs)
+    Group g{0};
+    for (Job* jb : jobs)
       if (jb->rd.smooth_guide)
         for (auto& a : jb->rd.gauss) {
-          g.push_back(a);
-          max_pix = std::max<int64_t>(max_pix, static_cast<int64_t>(a.H) * a.W);
+          push_desc(g, a);
+          g.max_pix = std::max<int64_t>(g.max_pix, static_cast<int64_t>(a.H) * a.W);
         }
-    if (!g.empty()) launches.push_back({0, 0, false, sg.put(g.data(), g.size() * sizeof(AuxPlane)),
-                                        static_cast<int>(g.size()), 0, 0, 0, 0, 0, max_pix});
+    g.items = g.n * gauss_chunks();
+    if (g.n) groups.push_back(std::move(g));
   }
   for (int it = 0; it < max_iter; ++it) {
     const bool first = it == 0;
-    std::vector<AuxPlane> mm;
-    std::map<std::pair<int, bool>, std::vector<BlfPlane>> blf;
-    std::vector<FftPlane> fft;
-    int rows = 0, cols = 0;
-    size_t lds_rows = 0, lds_cols = 0;
-    for (Job* jb : st.jobs) {
+    Group mm{1};
+    std::map<std::pair<int, bool>, Group> blf;
+    Group fft{3};
+    for (Job* jb : jobs) {
       RequestDesc& rd = jb->rd;
       if (it >= rd.iterations) continue;
-      if (rd.normalize) for (auto& a : (first ? rd.mm_first : rd.mm_next)) mm.push_back(a);
-      auto& bucket = blf[{rd.R, first ? rd.joint_first : true}];
+      if (rd.normalize)
+        for (auto& a : (first ? rd.mm_first : rd.mm_next)) push_desc(mm, a);
+      const std::pair<int, bool> key{rd.R, first ? rd.joint_first : true};
+      auto found = blf.find(key);
+      if (found == blf.end()) {
+        Group g{2};
+        g.R = key.first;
+        g.joint = key.second;
+        found = blf.emplace(key, std::move(g)).first;
+      }
+      Group& bg = found->second;
       for (auto b : (first ? rd.blf_first : rd.blf_next)) {
-        int tiles = 0;
-        for (auto& x : bucket) tiles += x.tile_count;
-        b.tile_begin = tiles;
-        bucket.push_back(b);
+        b.tile_begin = bg.items / 2;
+        bg.items += 2 * b.tile_count;
+        push_desc(bg, b);
       }
       for (auto fp : rd.fft) {
-        fp.row_begin = rows;
-        fp.col_begin = cols;
-        rows += fp.row_count;
-        cols += fp.col_count;
-        fft.push_back(fp);
+        fp.row_begin = fft.items;
+        fp.col_begin = fft.items2;
+        fft.items += fp.row_count;
+        fft.items2 += fp.col_count;
+        push_desc(fft, fp);
       }
-      lds_rows = std::max(lds_rows, jb->plan->lds_rows);
-      lds_cols = std::max(lds_cols, jb->plan->lds_cols);
+      fft.lds_rows = std::max(fft.lds_rows, jb->plan->lds_rows);
+      fft.lds_cols = std::max(fft.lds_cols, jb->plan->lds_cols);
     }
-    if (!mm.empty())
-      launches.push_back({1, 0, false, sg.put(mm.data(), mm.size() * sizeof(AuxPlane)),
-                          static_cast<int>(mm.size()), 0, 0, 0, 0, 0, 0});
-    for (auto& kv : blf) {
-      int items = 0;
-      for (auto& b : kv.second) items += 2 * b.tile_count;
-      launches.push_back({2, kv.first.first, kv.first.second,
-                          sg.put(kv.second.data(), kv.second.size() * sizeof(BlfPlane)),
-                          static_cast<int>(kv.second.size()), items, 0, 0, 0, 0, 0});
-    }
-    if (!fft.empty())
-      launches.push_back({3, 0, false, sg.put(fft.data(), fft.size() * sizeof(FftPlane)),
-                          static_cast<int>(fft.size()), 0, rows, cols, lds_rows, lds_cols, 0});
+    mm.items = mm.n * kMinmaxBlocks;
+    if (mm.n) groups.push_back(std::move(mm));
+    for (auto& kv : blf) groups.push_back(std::move(kv.second));
+    if (fft.n) groups.push_back(std::move(fft));
   }
-  if (sg.overflow) return hipErrorOutOfMemory;
-  e = hipMemcpyAsync(sg.dev, sg.host, sg.used, hipMemcpyHostToDevice, stream);
+  return groups;
+}
+
+// LDS of the captured FFT launches: steps whose images all fit 40 KiB keep more
+// FFT workgroups per CU than the worst case would allow.
+constexpr size_t kFftLdsSmall = 40960;
+
+static size_t fft_lds_class(const Group& g, size_t lds_max) {
+  return std::max(g.lds_rows, g.lds_cols) <= kFftLdsSmall ? kFftLdsSmall : lds_max;
+}
+
+static std::vector<int> signature(const std::vector<Group>& groups) {
+  std::vector<int> sig;
+  for (const Group& g : groups) {
+    sig.push_back(g.kind);
+    if (g.kind == 2) sig.push_back(g.R * 2 + (g.joint ? 1 : 0));
+    else if (g.kind == 3) sig.push_back(std::max(g.lds_rows, g.lds_cols) <= kFftLdsSmall ? 1 : 2);
+    else sig.push_back(0);
+  }
+  return sig;
+}
+
+// Direct launches (each kernel sized to its work), for steps that do not fit the
+// fixed descriptor layout of a captured graph.
+hipError_t blfls_server_s::launch_direct(std::vector<Group>& groups, int slot, int ft, size_t tables_used) {
+  uint8_t* host = staging[slot];
+  uint8_t* dev = arena + slot * stage_bytes;
+  size_t used = tables_used;
+  std::vector<size_t> offs;
+  for (Group& g : groups) {
+    used = align_up(used, 256);
+    if (used + g.planes.size() > stage_bytes) return hipErrorOutOfMemory;
+    std::memcpy(host + used, g.planes.data(), g.planes.size());
+    offs.push_back(used);
+    used += g.planes.size();
+  }
+  hipError_t e = hipMemcpyAsync(dev, host, used, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return e;
-  for (const Launch& L : launches) {
-    const uint8_t* d = sg.dev + L.off;
-    switch (L.kind) {
-      case 0: e = launch_gauss(reinterpret_cast<const AuxPlane*>(d), L.n, L.max_pix, stream); break;
-      case 1: e = launch_minmax(reinterpret_cast<const AuxPlane*>(d), L.n, stream); break;
-      case 2: e = launch_blf(L.R, reinterpret_cast<const BlfPlane*>(d), L.n, L.items, L.joint, ft, stream); break;
+  for (size_t i = 0; i < groups.size(); ++i) {
+    const Group& g = groups[i];
+    const uint8_t* d = dev + offs[i];
+    switch (g.kind) {
+      case 0: e = launch_gauss(reinterpret_cast<const AuxPlane*>(d), g.n, g.max_pix, stream); break;
+      case 1: e = launch_minmax(reinterpret_cast<const AuxPlane*>(d), g.n, stream); break;
+      case 2: e = launch_blf(g.R, reinterpret_cast<const BlfPlane*>(d), g.n, g.items, g.joint, ft, stream); break;
       default: {
         const FftPlane* fp = reinterpret_cast<const FftPlane*>(d);
-        e = launch_fft_rows_fwd(fp, L.n, L.rows, L.lds_rows, ft, stream);
-        if (e == hipSuccess) e = launch_fft_cols(fp, L.n, L.cols, L.lds_cols, stream);
-        if (e == hipSuccess) e = launch_fft_rows_inv(fp, L.n, L.rows, L.lds_rows, stream);
+        e = launch_fft_rows_fwd(fp, g.n, g.items, g.lds_rows, ft, stream);
+        if (e == hipSuccess) e = launch_fft_cols(fp, g.n, g.items2, g.lds_cols, stream);
+        if (e == hipSuccess) e = launch_fft_rows_inv(fp, g.n, g.items, g.lds_rows, stream);
       }
     }
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+// Capture the persistent launches of one step signature for one staging slot.
+// Every kernel reads its items and its descriptor array from the slot's work
+// header in device memory, so the graph replays unchanged with new work.
+hipError_t blfls_server_s::build_graph(const std::vector<Group>& groups, int slot, int ft, hipGraphExec_t* out) {
+  WorkHeader* header = reinterpret_cast<WorkHeader*>(arena + slot * stage_bytes);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(capture_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (size_t i = 0; i < groups.size() && le == hipSuccess; ++i) {
+    const Group& g = groups[i];
+    WorkHeader* w = header + i;
+    switch (g.kind) {
+      case 0: le = launch_gauss(nullptr, 0, 0, capture_stream, w, kAuxGrid); break;
+      case 1: le = launch_minmax(nullptr, 0, capture_stream, w, kAuxGrid); break;
+      case 2: le = launch_blf(g.R, nullptr, 0, kBlfGrid, g.joint, ft, capture_stream, w); break;
+      default: {
+        const size_t lds = fft_lds_class(g, kFftLdsMax);
+        le = launch_fft_rows_fwd(nullptr, 0, kFftGrid, lds, ft, capture_stream, w);
+        if (le == hipSuccess) le = launch_fft_cols(nullptr, 0, kFftGrid, lds, capture_stream, w);
+        if (le == hipSuccess) le = launch_fft_rows_inv(nullptr, 0, kFftGrid, lds, capture_stream, w);
+      }
+    }
+  }
+  e = hipStreamEndCapture(capture_stream, &graph);
+  if (le != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return le;
+  }
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  return e;
+}
+
+hipError_t blfls_server_s::launch_step(Step& st, int slot) {
+  const int ft = precision == BLFLS_FP32 ? kF32 : precision == BLFLS_MIXED_BF16 ? kBF16 : kF16;
+  uint8_t* host = staging[slot];
+  uint8_t* dev = arena + slot * stage_bytes;
+  // slot layout: [work header][request tables][packed descriptor arrays]; the
+  // BLF and Gaussian descriptors point at their request's tables
+  const size_t tables_base = kHeaderBytes;
+  for (size_t j = 0; j < st.jobs.size(); ++j) {
+    Job* jb = st.jobs[j];
+    const blfls_request& q = jb->req;
+    const size_t toff = tables_base + j * sizeof(RequestTables);
+    build_request(jb->plan, q.params, jb->radius, q.f, q.guide, q.u, q.pitch, arena + jb->ws_off, dev + toff, &jb->rd);
+    std::memcpy(host + toff, &jb->rd.tables, sizeof(RequestTables));
+  }
+  size_t used = tables_base + st.jobs.size() * sizeof(RequestTables);
+  std::vector<Group> groups = build_groups(st.jobs);
+  if (static_cast<int>(groups.size()) > kMaxGroups) {
+    stats_direct_steps++;
+    const hipError_t e = launch_direct(groups, slot, ft, used);
+    return e == hipSuccess ? hipEventRecord(st.done, stream) : e;
+  }
+  WorkHeader* header = reinterpret_cast<WorkHeader*>(host);
+  std::memset(header, 0, kHeaderBytes);
+  for (size_t i = 0; i < groups.size(); ++i) {
+    used = align_up(used, 256);
+    if (used + groups[i].planes.size() > stage_bytes) return hipErrorOutOfMemory;
+    std::memcpy(host + used, groups[i].planes.data(), groups[i].planes.size());
+    header[i].items = groups[i].items;
+    header[i].nplanes = groups[i].n;
+    header[i].items2 = groups[i].items2;
+    header[i].planes = dev + used;
+    used += groups[i].planes.size();
+  }
+  const auto key = std::make_pair(signature(groups), slot);
+  auto it = graphs.find(key);
+  if (it == graphs.end()) {
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = build_graph(groups, slot, ft, &exec);
+    if (e != hipSuccess) return e;
+    it = graphs.emplace(key, exec).first;
+  }
+  hipError_t e = hipMemcpyAsync(dev, host, used, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return e;
+  e = hipGraphLaunch(it->second, stream);
+  if (e != hipSuccess) return e;
+  stats_graph_steps++;
   return hipEventRecord(st.done, stream);
 }
 
@@ -315,10 +410,14 @@ void blfls_server_s::retire(Step& st) {
 }
 
 void blfls_server_s::admit(std::vector<Job*>* admitted) {
+  // descriptor budget of one step: header, per-group alignment, then requests
+  size_t desc = kHeaderBytes + static_cast<size_t>(kMaxGroups) * 256;
   while (!queue.empty() && running < max_slots) {
     Job* jb = queue.front();
+    if (desc + jb->desc_bytes > stage_bytes) break;  // the rest waits for the next step
     size_t off = 0;
     if (!arena_alloc.alloc(jb->plan->ws_bytes, &off)) break;  // FIFO: the head waits for space
+    desc += jb->desc_bytes;
     jb->ws_off = off;
     queue.pop_front();
     tickets[jb->id].first = BLFLS_RUNNING;
@@ -378,8 +477,9 @@ blfls_status blfls_server_create(blfls_server_t* out, void* arena, size_t arena_
   if (max_slots < 1 || queue_capacity < 1) return set_error(BLFLS_E_INVALID, "max_slots and queue_capacity must be >= 1");
   if (precision != BLFLS_FP32 && precision != BLFLS_MIXED_BF16 && precision != BLFLS_MIXED_FP16)
     return set_error(BLFLS_E_INVALID, "unknown precision");
-  const size_t reserved = kDepth * kStageBytes;
-  if (arena_bytes <= reserved) return set_error(BLFLS_E_NOMEM, "arena smaller than the descriptor region (16 MiB)");
+  const size_t stage_bytes = kStageBytes;  // descriptor staging per in-flight step
+  const size_t reserved = kDepth * stage_bytes;
+  if (arena_bytes <= reserved) return set_error(BLFLS_E_NOMEM, "arena smaller than the descriptor region");
   auto* s = new (std::nothrow) blfls_server_s();
   if (!s) return set_error(BLFLS_E_NOMEM, "host allocation failed");
   s->arena = static_cast<uint8_t*>(arena);
@@ -391,10 +491,14 @@ blfls_status blfls_server_create(blfls_server_t* out, void* arena, size_t arena_
   s->stream = static_cast<hipStream_t>(stream);
   hipError_t e = hipGetDevice(&s->device);
   if (e != hipSuccess) { delete s; return hip_error(e, "hipGetDevice"); }
+  s->stage_bytes = stage_bytes;
+  s->kFftLdsMax = std::max(fft_rows_lds_bytes(kFftLdsComplex - 1, 1), fft_cols_lds_bytes(kFftLdsComplex, 1));
+  e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) { delete s; return hip_error(e, "capture stream"); }
   s->arena_alloc.init(reserved, arena_bytes - reserved);
   s->stats.arena_bytes = arena_bytes - reserved;
   for (int i = 0; i < kDepth; ++i) {
-    e = hipHostMalloc(reinterpret_cast<void**>(&s->staging[i]), kStageBytes, hipHostMallocDefault);
+    e = hipHostMalloc(reinterpret_cast<void**>(&s->staging[i]), stage_bytes, hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->steps[i].done, hipEventDisableTiming);
     if (e != hipSuccess) {
       for (int j = 0; j <= i; ++j) {
@@ -441,8 +545,16 @@ blfls_status blfls_submit(blfls_server_t s, const blfls_request* r, uint64_t* ti
   }
   if (plan->ws_bytes > s->arena_bytes - s->desc_region)
     return set_error(BLFLS_E_NOMEM, "request workspace exceeds the arena");
+  // staging bytes: tables, the Gaussian descriptors, and per iteration one
+  // filter, one FFT and one extrema descriptor per channel
+  const size_t desc_bytes = sizeof(RequestTables) + 16 +
+                            static_cast<size_t>(r->C) * (sizeof(AuxPlane) + static_cast<size_t>(r->params.iterations) *
+                                                         (sizeof(BlfPlane) + sizeof(FftPlane) + sizeof(AuxPlane)));
+  if (desc_bytes + blfls_server_s::kHeaderBytes + blfls_server_s::kMaxGroups * 256 > s->stage_bytes)
+    return set_error(BLFLS_E_NOMEM, "too many iterations for one server step");
   auto* jb = new (std::nothrow) Job();
   if (!jb) return set_error(BLFLS_E_NOMEM, "host allocation failed");
+  jb->desc_bytes = desc_bytes;
   jb->id = s->next_id++;
   jb->t_submit = now_ms();
   jb->req = *r;
@@ -500,6 +612,8 @@ blfls_status blfls_server_destroy(blfls_server_t s) {
   }
   s->cv.notify_all();
   if (s->worker.joinable()) s->worker.join();
+  for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
   for (auto& kv : s->plans) plan_free(kv.second);
   for (int i = 0; i < kDepth; ++i) {
     if (s->staging[i]) (void)hipHostFree(s->staging[i]);

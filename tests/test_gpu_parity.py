@@ -306,3 +306,110 @@ def test_server_results_equal_alone():
         ref = oracle.smooth(f.astype(np.float32).astype(np.float64), prm["lam"], prm["sigma_s"], prm["sigma_r"],
                             guide=None if guide is None else guide.astype(np.float32).astype(np.float64))
         assert np.max(np.abs(u.cpu().numpy() - ref)) <= TOL_FP32
+
+
+# ---------------------------------------------------------------------------
+# Graph capture of the synchronous path
+# ---------------------------------------------------------------------------
+
+def test_smooth_captured_in_graph_replays_match_eager():
+    """blfls_smooth queues only kernels (descriptor upload by kernel argument, no
+    memset or host copy), so it can be captured; every replay must equal the eager
+    result for the inputs present at replay time."""
+    b = blfls()
+    H, W, C = 96, 128, 3
+    plan = b.Plan(H, W, C)
+    prm = dict(lam=20.0, sigma_s=2.0, sigma_r=0.1)
+    static_f = torch.zeros((C, H, W), device="cuda")
+    static_u = torch.zeros_like(static_f)
+    # warm up on a side stream, then capture
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.smooth(static_f, out=static_u, **prm)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.smooth(static_f, out=static_u, **prm)
+    for k in range(4):
+        img = torch.from_numpy(voronoi_rgb(H, W, 20 + k).astype(np.float32)).cuda()
+        static_f.copy_(img)
+        g.replay()
+        torch.cuda.synchronize()
+        eager = plan.smooth(img, **prm)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(static_u, eager), f"replay {k} differs from eager"
+
+
+def test_server_graph_path_all_features_bitwise():
+    """Steps mixing Gaussian guides, normalisation, rolling iterations, joint
+    filtering and three radius classes run as captured graphs; replays with new
+    work must give exactly the synchronous result of each request."""
+    import time
+    b = blfls()
+    reqs = []
+    for k in range(18):
+        H, W = [(40, 48), (64, 80), (72, 90)][k % 3]
+        f = voronoi_image(H, W, 1200 + k)
+        prm = dict(lam=[10.0, 50.0, 200.0][k % 3], sigma_s=[1.0, 2.0, 4.0][(k // 3) % 3],
+                   sigma_r=0.08, iterations=1 + k % 2, normalize=(k % 4 == 1),
+                   sigma_guide=(1.0 if k % 5 == 2 else 0.0))
+        guide = voronoi_image(H, W, 1300 + k) if k % 6 == 3 else None
+        reqs.append((f, guide, prm))
+    server = b.Server(arena_bytes=256 << 20, max_slots=4, precision="fp32")
+    pending = []
+    for f, guide, prm in reqs:  # several steps: the same signatures replay their graphs
+        g = None if guide is None else _to_gpu(guide)
+        t, u = server.submit(_to_gpu(f), guide=g, **prm)
+        pending.append((t, u))
+    deadline = time.time() + 60
+    for t, u in pending:
+        while True:
+            state, status = server.poll(t)
+            if state in (b.DONE, b.FAILED):
+                break
+            assert time.time() < deadline
+            time.sleep(0.001)
+        assert state == b.DONE and status == 0
+    server.stream.synchronize()
+    assert server.stats()["steps"] >= 3
+    server.close()
+    for (f, guide, prm), (_, u) in zip(reqs, pending):
+        g = None if guide is None else _to_gpu(guide)
+        alone = b.smooth(_to_gpu(f), guide=g, **prm)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, u), prm
+
+
+def test_server_rejects_and_backpressure():
+    b = blfls()
+    server = b.Server(arena_bytes=48 << 20, max_slots=2, queue_capacity=2, precision="fp32")
+    f = _to_gpu(voronoi_image(64, 64, 5))
+    with pytest.raises(b.BlflsError) as e:
+        server.submit(_to_gpu(voronoi_image(2048, 2048, 5)), lam=20.0, sigma_s=2.0, sigma_r=0.1)  # never fits
+    assert e.value.status == -3
+    with pytest.raises(b.BlflsError) as e:
+        server.submit(f, lam=-1.0, sigma_s=2.0, sigma_r=0.1)
+    assert e.value.status == -1
+    with pytest.raises(b.BlflsError) as e:
+        server.submit(_to_gpu(voronoi_image(63, 64, 5)), lam=20.0, sigma_s=2.0, sigma_r=0.1)
+    assert e.value.status == -2
+    # a full queue answers E_AGAIN and accepts again once it drains
+    tickets = []
+    again = 0
+    for _ in range(50):
+        try:
+            tickets.append(server.submit(f, lam=20.0, sigma_s=2.0, sigma_r=0.1)[0])
+        except b.BlflsError as err:
+            assert err.status == -4
+            again += 1
+    assert again > 0
+    import time
+    for t in tickets:
+        while server.poll(t)[0] not in (b.DONE, b.FAILED):
+            time.sleep(0.001)
+    with pytest.raises(b.BlflsError) as e:
+        server.poll(tickets[0])  # retired by the poll that reported DONE
+    assert e.value.status == -6
+    server.close()

@@ -39,11 +39,20 @@ def test_no_scratch_or_spills(asm):
 
 def test_filter_one_exp_per_tap(asm):
     text = asm["blf_kernel.hip"]
-    name = "_ZN5blfls16blf_field_kernelILi9ELi8ELi4ELb0EEEvPKNS_8BlfPlaneEii"
-    start = text.index(name + ":")
-    body = text[start:text.index("s_endpgm", start)]
-    # the runtime dx loop is the last loop of the kernel
-    head = [m.start() for m in re.finditer(r"; %bb\.\d+:.*Loop Header|Loop Header", body)][-1]
-    loop = body[head:]
-    exps = len(re.findall(r"\bv_exp_f32", loop))
-    assert exps == 8 * 19, exps  # K outputs x (2R+1) rows per column offset
+    prefix = "_ZN5blfls16blf_field_kernelILi9ELi8ELi4ELb0EEEvPKNS_8BlfPlaneEii"
+    start = text.index(prefix)
+    start = text.index(":", start)
+    body = text[start:text.index("s_endpgm", start)].split("\n")
+    counts = []
+    for i, line in enumerate(body):
+        if "Loop Header" not in line:
+            continue
+        label = line.split(":")[0].strip()
+        exps = 0
+        for later in body[i + 1:]:
+            if re.search(r"s_cbranch_\w+\s+" + re.escape(label) + r"\b", later):
+                break
+            exps += bool(re.match(r"\s*v_exp_f32", later))
+        counts.append(exps)
+    # the runtime dx loop evaluates K outputs x (2R+1) rows: one exp per tap
+    assert 8 * 19 in counts, counts
