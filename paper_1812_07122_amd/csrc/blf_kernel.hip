@@ -222,15 +222,16 @@ __device__ __forceinline__ void blf_item(const BlfPlane* __restrict__ planes, in
   }
 }
 
-// Kernel: with work == nullptr the grid has exactly one workgroup per item;
+// Kernel (two instantiations, each with its own register allocation): direct,
+// the grid has exactly one workgroup per item;
 // otherwise (persistent launch from a captured graph) the work header in
 // device memory gives the items and the plane array, and the workgroups of a
 // fixed grid draw items from its counter.
-template <int R, int K, int WAVES, bool JOINT>
+template <int R, int K, int WAVES, bool JOINT, bool PERSIST>
 __global__ void __launch_bounds__(64 * WAVES)
 blf_field_kernel(const BlfPlane* __restrict__ planes, int nplanes, int field_type,
                  WorkHeader* __restrict__ work) {
-  if (work == nullptr) {
+  if (!PERSIST) {
     blf_item<R, K, WAVES, JOINT>(planes, nplanes, field_type, blockIdx.x);
     return;
   }
@@ -258,10 +259,17 @@ template <int R>
 hipError_t launch_r(const BlfPlane* planes, int nplanes, int total_items, bool joint, int ft, WorkHeader* work,
                     hipStream_t s) {
   dim3 grid(total_items), block(64 * kWaves);
-  if (joint)
-    hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, true>), grid, block, 0, s, planes, nplanes, ft, work);
-  else
-    hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, false>), grid, block, 0, s, planes, nplanes, ft, work);
+  if (work == nullptr) {
+    if (joint)
+      hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, true, false>), grid, block, 0, s, planes, nplanes, ft, work);
+    else
+      hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, false, false>), grid, block, 0, s, planes, nplanes, ft, work);
+  } else {
+    if (joint)
+      hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, true, true>), grid, block, 0, s, planes, nplanes, ft, work);
+    else
+      hipLaunchKernelGGL((blf_field_kernel<R, kK, kWaves, false, true>), grid, block, 0, s, planes, nplanes, ft, work);
+  }
   return hipGetLastError();
 }
 }  // namespace

@@ -519,11 +519,11 @@ __device__ __forceinline__ void rows_inv_item(const FftPlane* __restrict__ plane
 // memory when the kernel runs (launches captured in a graph), from one counter
 // per XCD.  Either way consecutive row blocks run on the same XCD.
 // ---------------------------------------------------------------------------
-template <int FT>
+template <int FT, bool PERSIST>
 __global__ void __launch_bounds__(kFftThreads, 4)
 fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
   extern __shared__ float2 smem[];
-  if (work == nullptr) {
+  if (!PERSIST) {
     rows_fwd_item<FT>(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
     return;
   }
@@ -537,10 +537,11 @@ fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader
   }
 }
 
+template <bool PERSIST>
 __global__ void __launch_bounds__(kFftThreads, 4)
 fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
   extern __shared__ float2 smem[];
-  if (work == nullptr) {
+  if (!PERSIST) {
     cols_item(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
     return;
   }
@@ -554,10 +555,11 @@ fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __
   }
 }
 
+template <bool PERSIST>
 __global__ void __launch_bounds__(kFftThreads, 4)
 fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
   extern __shared__ float2 smem[];
-  if (work == nullptr) {
+  if (!PERSIST) {
     rows_inv_item(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
     return;
   }
@@ -580,11 +582,16 @@ size_t fft_cols_lds_bytes(int H, int cb) { return (kTwMax + padded(cb * H)) * si
 
 hipError_t fft_init_kernels() {
   const int kMax = 128 * 1024;  // largest need is about 73 KiB; static LDS comes on top
-  const void* fns[] = {reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF32>),
-                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kBF16>),
-                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF16>),
-                       reinterpret_cast<const void*>(&fft_cols_kernel),
-                       reinterpret_cast<const void*>(&fft_rows_inv_kernel)};
+  const void* fns[] = {reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF32, false>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kBF16, false>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF16, false>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF32, true>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kBF16, true>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF16, true>),
+                       reinterpret_cast<const void*>(&fft_cols_kernel<false>),
+                       reinterpret_cast<const void*>(&fft_cols_kernel<true>),
+                       reinterpret_cast<const void*>(&fft_rows_inv_kernel<false>),
+                       reinterpret_cast<const void*>(&fft_rows_inv_kernel<true>)};
   for (const void* fn : fns) {
     const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMax);
     if (e != hipSuccess) return e;
@@ -592,30 +599,43 @@ hipError_t fft_init_kernels() {
   return hipSuccess;
 }
 
+template <int FT>
+static void rows_fwd(const FftPlane* planes, int nplanes, int blocks, size_t lds, hipStream_t s, WorkHeader* work) {
+  const dim3 g(blocks), b(kFftThreads);
+  if (work == nullptr)
+    hipLaunchKernelGGL((fft_rows_fwd_kernel<FT, false>), g, b, lds, s, planes, nplanes, work);
+  else
+    hipLaunchKernelGGL((fft_rows_fwd_kernel<FT, true>), g, b, lds, s, planes, nplanes, work);
+}
+
 hipError_t launch_fft_rows_fwd(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
                                int field_type, hipStream_t s, WorkHeader* work) {
   if (blocks <= 0) return hipSuccess;
-  const dim3 g(blocks), b(kFftThreads);
-  if (field_type == kF32)
-    hipLaunchKernelGGL(fft_rows_fwd_kernel<kF32>, g, b, lds_bytes, s, planes, nplanes, work);
-  else if (field_type == kBF16)
-    hipLaunchKernelGGL(fft_rows_fwd_kernel<kBF16>, g, b, lds_bytes, s, planes, nplanes, work);
-  else
-    hipLaunchKernelGGL(fft_rows_fwd_kernel<kF16>, g, b, lds_bytes, s, planes, nplanes, work);
+  if (field_type == kF32) rows_fwd<kF32>(planes, nplanes, blocks, lds_bytes, s, work);
+  else if (field_type == kBF16) rows_fwd<kBF16>(planes, nplanes, blocks, lds_bytes, s, work);
+  else rows_fwd<kF16>(planes, nplanes, blocks, lds_bytes, s, work);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_cols(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes, hipStream_t s,
                            WorkHeader* work) {
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fft_cols_kernel, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes, work);
+  const dim3 g(blocks), b(kFftThreads);
+  if (work == nullptr)
+    hipLaunchKernelGGL((fft_cols_kernel<false>), g, b, lds_bytes, s, planes, nplanes, work);
+  else
+    hipLaunchKernelGGL((fft_cols_kernel<true>), g, b, lds_bytes, s, planes, nplanes, work);
   return hipGetLastError();
 }
 
 hipError_t launch_fft_rows_inv(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
                                hipStream_t s, WorkHeader* work) {
   if (blocks <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fft_rows_inv_kernel, dim3(blocks), dim3(kFftThreads), lds_bytes, s, planes, nplanes, work);
+  const dim3 g(blocks), b(kFftThreads);
+  if (work == nullptr)
+    hipLaunchKernelGGL((fft_rows_inv_kernel<false>), g, b, lds_bytes, s, planes, nplanes, work);
+  else
+    hipLaunchKernelGGL((fft_rows_inv_kernel<true>), g, b, lds_bytes, s, planes, nplanes, work);
   return hipGetLastError();
 }
 

@@ -39,7 +39,7 @@ def test_no_scratch_or_spills(asm):
 
 def test_filter_one_exp_per_tap(asm):
     text = asm["blf_kernel.hip"]
-    prefix = "_ZN5blfls16blf_field_kernelILi9ELi8ELi4ELb0EEEvPKNS_8BlfPlaneEii"
+    prefix = "_ZN5blfls16blf_field_kernelILi9ELi8ELi4ELb0ELb0EE"  # direct launch, self-guided, R = 9
     start = text.index(prefix)
     start = text.index(":", start)
     body = text[start:text.index("s_endpgm", start)].split("\n")
