@@ -28,25 +28,20 @@ thread_local std::string g_last_error;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Factor n into Stockham radices: the powers of two first (16 while at least
-// 16 divides what is left, then one 8, 4 or 2), then the odd part as 15s
-// (3 x 5), 9s, a 3 and 5s; false if another prime divides n.  With the
-// largest power of two first, every later stage's leg strides are multiples
-// of the LDS padding period (see FftSize).
-bool factorize(int n, std::vector<int>* radices) {
+// Factor n into radices up to max_pow2 (16 or 8) for the powers of two, then one
+// 8, 4 or 2, then 3s and 5s; false if another prime divides n.  Row transforms
+// use at most radix 8 (their first stage reads HBM and needs enough butterflies
+// to occupy the workgroup), column transforms radix 16 (fewer barriers).
+bool factorize(int n, std::vector<int>* radices, int max_pow2 = 16) {
   radices->clear();
   int m = n;
-  int v = 0;
-  while (m % 2 == 0) { m /= 2; ++v; }
-  while (v >= 4) { radices->push_back(16); v -= 4; }
-  if (v > 0) radices->push_back(1 << v);
-  int a = 0, b = 0;
-  while (m % 3 == 0) { m /= 3; ++a; }
-  while (m % 5 == 0) { m /= 5; ++b; }
-  while (a >= 1 && b >= 1) { radices->push_back(15); --a; --b; }
-  while (a >= 2) { radices->push_back(9); a -= 2; }
-  if (a == 1) radices->push_back(3);
-  while (b >= 1) { radices->push_back(5); --b; }
+  if (max_pow2 >= 16)
+    while (m % 16 == 0) { radices->push_back(16); m /= 16; }
+  while (m % 8 == 0) { radices->push_back(8); m /= 8; }
+  if (m % 4 == 0) { radices->push_back(4); m /= 4; }
+  if (m % 2 == 0) { radices->push_back(2); m /= 2; }
+  while (m % 3 == 0) { radices->push_back(3); m /= 3; }
+  while (m % 5 == 0) { radices->push_back(5); m /= 5; }
   return m == 1;
 }
 
@@ -76,19 +71,13 @@ std::vector<float2> two_level_table(int n, int emax) {
   return t;
 }
 
-// Stage descriptors of one transform length and its two-level twiddle table.
-// The LDS padding period is 16 when 16 divides n, 8 when 8 does (the first
-// radix is then that period), none otherwise; false if a later stage's
-// strides were not multiples of the period (never, by the factorisation).
-bool build_fft_size(int n, FftSize* sz, std::vector<float2>* tw) {
+// Stage descriptors of one transform length and its twiddle table.
+void build_fft_size(int n, FftSize* sz, std::vector<float2>* tw, int max_pow2) {
   std::vector<int> rad;
-  if (!factorize(n, &rad)) return false;
+  factorize(n, &rad, max_pow2);
   std::memset(sz, 0, sizeof(*sz));
   sz->n = n;
   sz->nstages = static_cast<int>(rad.size());
-  sz->pshift = n % 16 == 0 ? 4 : n % 8 == 0 ? 3 : 31;
-  const int period = sz->pshift >= 31 ? 0 : 1 << sz->pshift;
-  auto padlen = [&](int x) { return x + (period ? x / period : 0); };
   int ns = 1;
   for (size_t s = 0; s < rad.size(); ++s) {
     const int R = rad[s];
@@ -97,16 +86,11 @@ bool build_fft_size(int n, FftSize* sz, std::vector<float2>* tw) {
     S.ns = ns;
     S.per = n / R;
     S.es = n / (ns * R);
-    S.pin = padlen(S.per);
-    S.pout = padlen(ns);
     S.per_div = make_fastdiv(static_cast<uint32_t>(n / R));
     S.ns_div = make_fastdiv(static_cast<uint32_t>(ns));
-    if (s > 0 && period && (S.per % period != 0 || ns % period != 0)) return false;
-    if (s == 0 && period && R != period && rad.size() > 1) return false;
     ns *= R;
   }
   *tw = two_level_table(n, n);
-  return true;
 }
 
 int floor_pow2(int v) {
@@ -174,10 +158,8 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   // tables, built in FP64 and rounded once to FP32
   FftSize szM, szH;
   std::vector<float2> twM, twH;
-  if (!build_fft_size(M, &szM, &twM) || !build_fft_size(H, &szH, &twH)) {
-    delete p;
-    return set_error(BLFLS_E_UNSUPPORTED, "transform length not supported by the FFT stage layout");
-  }
+  build_fft_size(M, &szM, &twM, 8);
+  build_fft_size(H, &szH, &twH, 16);
   const std::vector<float2> twW = two_level_table(W, M + 1);
   std::vector<float> sx(M + 1), sy(H);
   for (int k = 0; k <= M; ++k) {
@@ -226,26 +208,21 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   p->sx = reinterpret_cast<const float*>(base + o_sx);
   p->sy = reinterpret_cast<const float*>(base + o_sy);
 
-  // FFT work items: rb rows (a power of two) or cb spectrum columns, up to
-  // kFftItemTarget complex values each (at most kFftItemMax), split further
-  // while a pass would leave CUs without an item
-  int rb = 1;
-  while (rb < 16 && 2 * rb * M <= kFftItemTarget && 2 * rb <= H) rb *= 2;
-  while (rb > 1 && static_cast<long>(C) * ((H + rb - 1) / rb) < 256) rb /= 2;
-  int cb = std::max(1, std::min(16, kFftItemTarget / H));
+  // FFT geometry: rows per row-pass workgroup (a power of two, rb (W/2+1)
+  // complex values in LDS) and spectrum columns per column-pass workgroup
+  // (cb H), both within 64 KiB so two workgroups share a CU, split further
+  // while the whole pass would not give every CU a workgroup
+  int rb = floor_pow2(std::min(16, std::max(1, kFftLdsComplex / (M + 1))));
+  while (rb > 4 && static_cast<long>(C) * ((H + rb - 1) / rb) < 256) rb /= 2;
+  rb = std::min(rb, floor_pow2(H));
+  int cb = std::min(16, std::max(1, kFftLdsComplex / H));
   while (cb > 1 && static_cast<long>(C) * ((M + 1 + cb - 1) / cb) < 256) cb = (cb + 1) / 2;
   p->rb = rb;
   p->cb = cb;
   p->row_blocks = (H + rb - 1) / rb;
   p->col_blocks = (M + 1 + cb - 1) / cb;
-  p->sM = fft_lds_stride(M + 1);
-  p->sH = fft_lds_stride(H);
-  fft_rows_layout(M, rb, szM.pshift, p->ntwM, p->ntwW, &p->r_split, &p->r_data, &p->lds_rows);
-  fft_cols_layout(H, cb, szH.pshift, p->ntwH, &p->c_sy, &p->c_sx, &p->c_data, &p->lds_cols);
-  const int ft = prec == BLFLS_FP32 ? kF32 : prec == BLFLS_MIXED_BF16 ? kBF16 : kF16;
-  p->grid_rows_fwd = fft_grid(0, ft, p->lds_rows, C * p->row_blocks);
-  p->grid_cols = fft_grid(1, kF32, p->lds_cols, C * p->col_blocks);
-  p->grid_rows_inv = fft_grid(2, kF32, p->lds_rows, C * p->row_blocks);
+  p->lds_rows = fft_rows_lds_bytes(M, rb);
+  p->lds_cols = fft_cols_lds_bytes(H, cb);
   p->tiles_x = (W + blf_tile_w() - 1) / blf_tile_w();
   p->tiles_y = (H + blf_tile_h() - 1) / blf_tile_h();
 
@@ -375,9 +352,6 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
     F.rb = plan->rb; F.cb = plan->cb;
     F.row_begin = ch * plan->row_blocks; F.row_count = plan->row_blocks;
     F.col_begin = ch * plan->col_blocks; F.col_count = plan->col_blocks;
-    F.sM = plan->sM; F.sH = plan->sH;
-    F.r_split = plan->r_split; F.r_data = plan->r_data;
-    F.c_sy = plan->c_sy; F.c_sx = plan->c_sx; F.c_data = plan->c_data;
     F.szM = plan->szM; F.szH = plan->szH;
     F.twM = plan->twM; F.twH = plan->twH; F.twW = plan->twW;
     F.ntwM = plan->ntwM; F.ntwH = plan->ntwH; F.ntwW = plan->ntwW;
@@ -413,17 +387,17 @@ hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, cons
     }
     {
       StageTimer t(BLFLS_STAGE_ROWS_FWD, s);
-      e = launch_fft_rows_fwd(dev.fft, C, plan->row_blocks * C, plan->grid_rows_fwd, plan->lds_rows, ft, s);
+      e = launch_fft_rows_fwd(dev.fft, C, plan->row_blocks * C, plan->lds_rows, ft, s);
       if (e != hipSuccess) return e;
     }
     {
       StageTimer t(BLFLS_STAGE_COLS, s);
-      e = launch_fft_cols(dev.fft, C, plan->col_blocks * C, plan->grid_cols, plan->lds_cols, s);
+      e = launch_fft_cols(dev.fft, C, plan->col_blocks * C, plan->lds_cols, s);
       if (e != hipSuccess) return e;
     }
     {
       StageTimer t(BLFLS_STAGE_ROWS_INV, s);
-      e = launch_fft_rows_inv(dev.fft, C, plan->row_blocks * C, plan->grid_rows_inv, plan->lds_rows, s);
+      e = launch_fft_rows_inv(dev.fft, C, plan->row_blocks * C, plan->lds_rows, s);
       if (e != hipSuccess) return e;
     }
   }

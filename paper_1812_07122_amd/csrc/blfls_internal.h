@@ -16,8 +16,7 @@ constexpr int kSpan = 2 * kMaxR + 1;    // window taps per axis at kMaxR
 constexpr int kMaxStages = 16;          // FFT stages per transform length
 constexpr int kMaxFft = 4096;           // longest transform (W/2 or H)
 constexpr int kFftThreads = 512;        // threads per FFT workgroup
-constexpr int kFftItemMax = 7680;       // complex values transformed per FFT work item at most (15 x 512)
-constexpr int kFftItemTarget = 7680;    // preferred complex values per work item (rows or columns batched)
+constexpr int kFftLdsComplex = 8192;    // complex values per FFT workgroup (64 KiB)
 constexpr int kMinmaxBlocks = 64;       // partial-reduction blocks per plane
 
 enum FieldType : int { kF32 = 0, kBF16 = 1, kF16 = 2 };
@@ -32,28 +31,22 @@ struct FastDiv {
 // One radix stage of a Stockham transform: it combines `radix` sub-transforms
 // of length `ns`; per = N / radix butterflies per transform.  Its twiddles are
 // W_N^(t k es), W_N = exp(-2 pi i / N), es = N / (ns radix), t < radix, k < ns.
-// pin / pout are the padded-LDS strides of the stage's input legs (per) and
-// output legs (ns): pad(x + t per) = pad(x) + t pin whenever x is a leg base.
 struct FftStage {
   int radix, ns, per, es;
-  int pin, pout;
   FastDiv per_div, ns_div;
 };
 
-// One transform length N = prod of the stage radices (powers of two first, the
-// first stage 16 or 8 when N has that factor, then 15, 9, 3, 5).  LDS holds a
-// batch of transforms padded with one spare slot per 2^pshift values
-// (pshift 31: no padding), which spreads the stride-radix writes of the first
-// stage over the banks and keeps every later stage's addresses linear.
+// One transform length N = prod of the stage radices.  Powers of W_N come from
+// a two-level table: W_N^e = hi[e >> 6] * lo[e & 63] (lo: W_N^j, j < 64;
+// hi: W_N^(64 j)); kTwLo + ceil(N / 64) entries in all.
 struct FftSize {
   int n;
   int nstages;
-  int pshift;
-  int pad_;
   FftStage st[kMaxStages];
 };
 
 constexpr int kTwLo = 64;
+constexpr int kTwMax = kTwLo + (kMaxFft * 2) / kTwLo + 1;  // entries of a two-level table (N <= 2 * kMaxFft)
 
 // One channel plane for the bilateral-filter kernel (Eq. (1) on both
 // gradient fields of one channel).
@@ -82,11 +75,6 @@ struct RequestTables {
 };
 
 // One channel plane for the three FFT passes (Eq. (8) in residual form).
-// Work items: row passes take rb rows, the column pass cb spectrum columns.
-// LDS of a row-pass workgroup: [two-level table of W_{W/2}][two-level table of
-// W_W][rb rows, stride sM, padded]; of a column-pass workgroup: [two-level
-// table of W_H][sy as floats][cb columns, stride sH, padded]; offsets in
-// float2 units.
 struct FftPlane {
   const void* rx;        // residual fields, packed [H][W], field type
   const void* ry;
@@ -96,13 +84,10 @@ struct FftPlane {
   int64_t pitch;
   int H, W;
   float lambda;
-  int rb;                // rows per row-pass item
-  int cb;                // spectrum columns per column-pass item
-  int row_begin, row_count;   // items of the row passes
-  int col_begin, col_count;   // items of the column pass
-  int sM, sH;            // LDS strides of one row / one column (multiples of 16)
-  int r_split, r_data;   // row passes: LDS offsets of the W_W table and the rows
-  int c_sy, c_sx, c_data;  // column pass: LDS offsets of sy, the item's sx and the columns
+  int rb;                // rows per row-pass workgroup
+  int cb;                // spectrum columns per column-pass workgroup
+  int row_begin, row_count;   // workgroups of the row passes
+  int col_begin, col_count;   // workgroups of the column pass
   const FftSize* szM;    // W/2 complex transform
   const FftSize* szH;    // H complex transform
   const float2* twM;     // two-level table of W_{W/2}

@@ -23,14 +23,10 @@ struct blfls_plan_s {
   const float* sx = nullptr;
   const float* sy = nullptr;
   int ntwM = 0, ntwH = 0, ntwW = 0;
-  // FFT pass geometry: items (rows / columns per item, items per channel),
-  // LDS layouts and the persistent grids of the three passes
+  // FFT pass geometry
   int rb = 1, cb = 1;
   int row_blocks = 0, col_blocks = 0;   // per channel
-  int sM = 16, sH = 16;
-  int r_split = 0, r_data = 0, c_sy = 0, c_sx = 0, c_data = 0;
   size_t lds_rows = 0, lds_cols = 0;
-  int grid_rows_fwd = 1, grid_cols = 1, grid_rows_inv = 1;
   // BLF geometry
   int tiles_x = 0, tiles_y = 0;
   // workspace layout (bytes from the workspace base)

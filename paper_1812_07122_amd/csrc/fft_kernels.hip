@@ -15,20 +15,13 @@
 //   cols     : per spectrum column: forward FFT over H, multiply by
 //              1/(H W den), inverse FFT over H, all in LDS (one read, one write);
 //   rows_inv : complex-to-real inverse of each row, u = f + delta.
-//
-// Every pass is a persistent loop over small work items (a few rows or
-// columns, about 2048 complex values): while an item's transform runs in LDS,
-// the loads of the workgroup's next item are already in flight into
-// registers, so HBM sees a steady stream instead of load/compute/store
-// phases.  Transforms are Stockham passes with radices 2, 3, 4, 5, 8, 9, 15
-// and 16 (three stages for the usual lengths); twiddles come from two-level
-// tables (built in FP64, rounded once; about 1 KiB) kept in LDS for the
-// workgroup's lifetime, so nearly all LDS holds data; LDS is padded so that
-// every stage after the first addresses its legs linearly.  Work items are
-// handed out in contiguous ranges per XCD, so neighbouring rows meet in one
-// L2 where the transposed spectrum is written and read.
-#include <algorithm>
-
+// Transforms are in-place Stockham passes in LDS with radices 2, 3, 4, 5, 8.
+// Each workgroup first stages two-level twiddle tables of its transform lengths
+// (FP64 host tables rounded to FP32, about 1.5 KiB) in LDS next to the data, so
+// no stage waits on global memory and two workgroups fit on a CU; index
+// arithmetic uses precomputed multiply-shift division; consecutive row blocks
+// are placed on the same XCD so partial lines of the transposed spectrum meet
+// in one L2.
 #include "blfls_internal.h"
 #include "blfls_launch.h"
 #include "blfls_work.h"
@@ -37,16 +30,10 @@ namespace blfls {
 
 namespace {
 
-constexpr int T = kFftThreads;
-
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
-}
-// a * conj(b)
-__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
-  return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 // multiply by i*sg (sg = +-1)
@@ -58,13 +45,21 @@ __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) {
 }
 
 // W_N^e from a two-level table in LDS (lo: W_N^j, j < 64; hi: W_N^(64 j)).
-__device__ __forceinline__ float2 twiddle2(const float2* tab, int e) {
+__device__ __forceinline__ float2 twiddle(const float2* tab, int e) {
   return cmul(tab[kTwLo + (e >> 6)], tab[e & (kTwLo - 1)]);
 }
 
-// ---------------------------------------------------------------------------
-// Butterflies: DFT of R points, A_k = sum_t a_t exp(sg * 2 pi i t k / R)
-// ---------------------------------------------------------------------------
+// Logical workgroup index such that consecutive logical indices run on the same
+// XCD (workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2): neighbouring row blocks then share the L2 lines of the transposed spectrum.
+__device__ __forceinline__ int xcd_remap(int b, int nblk) {
+  constexpr int kXcd = 8;
+  const int q = nblk / kXcd, rem = nblk % kXcd;
+  const int x = b % kXcd;
+  return x * q + min(x, rem) + b / kXcd;
+}
+
+// DFT of R points, A_k = sum_t a_t exp(sg * 2 pi i t k / R)
 template <int R>
 __device__ __forceinline__ void butterfly(float2* a, float sg);
 
@@ -170,280 +165,126 @@ __device__ __forceinline__ void butterfly<16>(float2* a, float sg) {
   }
 }
 
-// Radix 9 as 3 x 3: with t = t1 + 3 t2 and k = 3 k1 + k2,
-// A_{3k1+k2} = sum_{t1} w3^{t1 k1} [ w9^{t1 k2} sum_{t2} a_{t1+3t2} w3^{t2 k2} ].
-template <>
-__device__ __forceinline__ void butterfly<9>(float2* a, float sg) {
-  // cos and sin of 2 pi m / 9 for m = 1, 2, 4
-  constexpr float c1 = 0.76604444311897803520f, s1 = 0.64278760968653932632f;
-  constexpr float c2 = 0.17364817766693034885f, s2 = 0.98480775301220805936f;
-  constexpr float c4 = -0.93969262078590838405f, s4 = 0.34202014332566873304f;
-  float2 b[3][3];
-#pragma unroll
-  for (int t1 = 0; t1 < 3; ++t1) {
-    float2 c[3] = {a[t1], a[t1 + 3], a[t1 + 6]};
-    butterfly<3>(c, sg);
-#pragma unroll
-    for (int k2 = 0; k2 < 3; ++k2) {
-      const int m = t1 * k2;  // 0, 1, 2 or 4
-      float2 w = make_float2(1.0f, 0.0f);
-      if (m == 1) w = make_float2(c1, sg * s1);
-      else if (m == 2) w = make_float2(c2, sg * s2);
-      else if (m == 4) w = make_float2(c4, sg * s4);
-      b[k2][t1] = m == 0 ? c[k2] : cmul(c[k2], w);
-    }
-  }
-#pragma unroll
-  for (int k2 = 0; k2 < 3; ++k2) {
-    butterfly<3>(b[k2], sg);
-#pragma unroll
-    for (int k1 = 0; k1 < 3; ++k1) a[3 * k1 + k2] = b[k2][k1];
-  }
-}
+// Padded LDS index: one spare slot per 16 complex values, so the stride-R
+// writes of the early Stockham stages spread over the LDS banks.
+__device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
 
-// Radix 15 as 3 x 5 without twiddles (Good-Thomas, 3 and 5 coprime): input
-// n = (5 n1 + 3 n2) mod 15, output k = (10 k1 + 6 k2) mod 15 (10 = 5 (5^-1 mod 3),
-// 6 = 3 (3^-1 mod 5)), so W_15^(n k) = W_3^(n1 k1) W_5^(n2 k2).
-template <>
-__device__ __forceinline__ void butterfly<15>(float2* a, float sg) {
-  float2 y[5][3];
-#pragma unroll
-  for (int n2 = 0; n2 < 5; ++n2) {
-    float2 c[3];
-#pragma unroll
-    for (int n1 = 0; n1 < 3; ++n1) c[n1] = a[(5 * n1 + 3 * n2) % 15];
-    butterfly<3>(c, sg);
-#pragma unroll
-    for (int k1 = 0; k1 < 3; ++k1) y[n2][k1] = c[k1];
-  }
-#pragma unroll
-  for (int k1 = 0; k1 < 3; ++k1) {
-    float2 d[5];
-#pragma unroll
-    for (int n2 = 0; n2 < 5; ++n2) d[n2] = y[n2][k1];
-    butterfly<5>(d, sg);
-#pragma unroll
-    for (int k2 = 0; k2 < 5; ++k2) a[(10 * k1 + 6 * k2) % 15] = d[k2];
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Padded LDS batches and stage destinations
-// ---------------------------------------------------------------------------
-struct Lds {
+// Element sources and destinations of a stage; b is the transform, n the element.
+struct LdsIO {  // in-place LDS buffer (padded layout)
+  static constexpr bool kLds = true;
   float2* buf;
-  int stride;  // complex values per transform (multiple of 16)
-  int pshift;  // one spare slot per 2^pshift values (31: none)
-  __device__ __forceinline__ int pad(int i) const { return i + (i >> pshift); }
+  int stride;
+  __device__ __forceinline__ float2 load(int b, int n) const { return buf[pad(b * stride + n)]; }
+  __device__ __forceinline__ void store(int b, int n, float2 v) const { buf[pad(b * stride + n)] = v; }
 };
 
-// Output legs n0 + t ns of transform b.  put() stores all R legs of one
-// butterfly; put1() one value (length-1 transforms).
-struct LdsOut {
-  static constexpr bool kLds = true;
-  Lds l;
-  template <int R>
-  __device__ __forceinline__ void put(int b, int n0, const FftStage& S, const float2* v) const {
-    float2* p = l.buf + l.pad(b * l.stride + n0);
-#pragma unroll
-    for (int t = 0; t < R; ++t) p[t * S.pout] = v[t];
-  }
-  __device__ __forceinline__ void put1(int b, int n, float2 v) const { l.buf[l.pad(b * l.stride + n)] = v; }
-};
-
-// LDS destination that applies the Eq. (8) divide, 1 / (H W (1 + lam (sx + sy))),
-// with sy and the item's sx values staged in LDS (no global access while the
-// next item's loads are in flight).
-struct ScaledLds {
-  static constexpr bool kLds = true;
-  Lds l;
-  const float* sy;   // LDS, [H]
-  const float* sx;   // LDS, [cb]: sx of columns k0 + b
-  float lam, inv_hw;
-  __device__ __forceinline__ float scale(int b, int n) const {
-    const float den = fmaf(lam, sx[b] + sy[n], 1.0f);
-    return inv_hw * __builtin_amdgcn_rcpf(den);
-  }
-  template <int R>
-  __device__ __forceinline__ void put(int b, int n0, const FftStage& S, const float2* v) const {
-    float2* p = l.buf + l.pad(b * l.stride + n0);
-    const float sxb = sx[b];
-#pragma unroll
-    for (int t = 0; t < R; ++t) {
-      const float den = fmaf(lam, sxb + sy[n0 + t * S.ns], 1.0f);
-      p[t * S.pout] = cscale(v[t], inv_hw * __builtin_amdgcn_rcpf(den));
-    }
-  }
-  __device__ __forceinline__ void put1(int b, int n, float2 v) const {
-    l.buf[l.pad(b * l.stride + n)] = cscale(v, scale(b, n));
-  }
-};
-
-// Spectrum columns k0 + b in HBM ([W/2+1][H] layout).
-struct ColOut {
-  static constexpr bool kLds = false;
-  float2* spec;  // column k0
-  int H;
-  template <int R>
-  __device__ __forceinline__ void put(int b, int n0, const FftStage& S, const float2* v) const {
-    float2* q = spec + static_cast<int64_t>(b) * H + n0;
-#pragma unroll
-    for (int t = 0; t < R; ++t) q[t * S.ns] = v[t];
-  }
-  __device__ __forceinline__ void put1(int b, int n, float2 v) const { spec[static_cast<int64_t>(b) * H + n] = v; }
-};
-
-// u = f + delta for row i0 + b; complex value n holds the reals at columns 2n, 2n+1.
-struct RowOut {
-  static constexpr bool kLds = false;
-  const float* __restrict__ f;
-  float* __restrict__ u;
-  int64_t pitch;
-  int i0;
-  __device__ __forceinline__ void put1(int b, int n, float2 v) const {
-    const int64_t o = static_cast<int64_t>(i0 + b) * pitch + 2 * n;
-    u[o] = f[o] + v.x;
-    u[o + 1] = f[o + 1] + v.y;
-  }
-  template <int R>
-  __device__ __forceinline__ void put(int b, int n0, const FftStage& S, const float2* v) const {
-#pragma unroll
-    for (int t = 0; t < R; ++t) put1(b, n0 + t * S.ns, v[t]);
-  }
-};
-
-// ---------------------------------------------------------------------------
-// Stockham stages
-// ---------------------------------------------------------------------------
-
-// One stage over `batch` transforms held in `in`: input legs j + t per of
-// butterfly j, output legs (j - k) R + k + t ns with k = j mod ns (decimation
-// in time), twiddles W_N^(t k es) from the transform's two-level table `tw` in
-// LDS (forward) or their conjugates (inverse).  The first stage (ns = 1, no twiddles) reads
-// with the general padded index; later stages read their legs at a fixed
-// padded stride.  Inputs are read into registers before a barrier, so an
-// LDS destination may be the same buffer; a barrier follows any LDS write.
-template <int R, bool FWD, bool FIRST, class DST>
-__device__ __forceinline__ void fft_stage(const Lds& in, const DST& dst, int batch, const FftStage& S,
-                                          const float2* tw) {
-  constexpr int kMaxB = (kFftItemMax / R + T - 1) / T;
-  constexpr float sg = FWD ? -1.0f : 1.0f;
+// One Stockham stage over `batch` transforms of length N.  Input element
+// j + t*N/R of a transform, output element (j - k) R + k + t Ns with
+// k = j mod Ns (decimation in time).  The stage's twiddles
+// exp(-2 pi i t k/(Ns R)) = W_N^(t k es) come from the transform's two-level
+// table in LDS.  When both ends are the same LDS buffer the inputs are read
+// into registers before a barrier, so the update is in place; a barrier
+// follows any stage that writes LDS.
+template <int R, int T, int MAXE, class SRC, class DST>
+__device__ __forceinline__ void fft_stage(const SRC& src, const DST& dst, int batch, const FftStage& S,
+                                          const float2* tw, float sg) {
+  constexpr int kMaxB = (MAXE / R + T - 1) / T;
   const int per = S.per;
   const int Ns = S.ns;
   const int total = per * batch;
   float2 a[kMaxB][R];
-  int ob[kMaxB], on[kMaxB];
+  int outb[kMaxB], outn[kMaxB];
 #pragma unroll
   for (int m = 0; m < kMaxB; ++m) {
     const int g = threadIdx.x + m * T;
     if (g < total) {
       const int b = static_cast<int>(fdiv(static_cast<uint32_t>(g), S.per_div));
       const int j = g - b * per;
-      if (FIRST) {
 #pragma unroll
-        for (int t = 0; t < R; ++t) a[m][t] = in.buf[in.pad(b * in.stride + j + t * per)];
-        ob[m] = b;
-        on[m] = j * R;
-      } else {
-        const float2* p = in.buf + in.pad(b * in.stride + j);
-#pragma unroll
-        for (int t = 0; t < R; ++t) a[m][t] = p[t * S.pin];
-        const int k = j - static_cast<int>(fdiv(static_cast<uint32_t>(j), S.ns_div)) * Ns;
-        ob[m] = b;
-        on[m] = (j - k) * R + k;
+      for (int t = 0; t < R; ++t) a[m][t] = src.load(b, j + t * per);
+      const int k = j - static_cast<int>(fdiv(static_cast<uint32_t>(j), S.ns_div)) * Ns;
+      outb[m] = b;
+      outn[m] = (j - k) * R + k;
+      if (Ns > 1) {
         const int ek = k * S.es;
 #pragma unroll
         for (int t = 1; t < R; ++t) {
-          const float2 w = twiddle2(tw, t * ek);
-          a[m][t] = FWD ? cmul(a[m][t], w) : cmulc(a[m][t], w);
+          float2 wt = twiddle(tw, t * ek);
+          wt.y = sg > 0.0f ? -wt.y : wt.y;  // the inverse takes the conjugate
+          a[m][t] = cmul(a[m][t], wt);
         }
       }
     }
   }
-  if (DST::kLds) __syncthreads();
+  if (SRC::kLds && DST::kLds) __syncthreads();
 #pragma unroll
   for (int m = 0; m < kMaxB; ++m) {
     const int g = threadIdx.x + m * T;
     if (g < total) {
       butterfly<R>(a[m], sg);
-      dst.template put<R>(ob[m], on[m], S, a[m]);
+#pragma unroll
+      for (int t = 0; t < R; ++t) dst.store(outb[m], outn[m] + t * Ns, a[m][t]);
     }
   }
   if (DST::kLds) __syncthreads();
 }
 
-template <bool FWD, bool FIRST, class DST>
-__device__ __forceinline__ void fft_stage_r(const Lds& in, const DST& dst, int batch, const FftStage& S,
-                                            const float2* tw) {
+template <int T, int MAXE, class SRC, class DST>
+__device__ __forceinline__ void fft_stage_r(const SRC& src, const DST& dst, int batch, const FftStage& S,
+                                            const float2* tw, float sg) {
   switch (S.radix) {
-    case 2: fft_stage<2, FWD, FIRST>(in, dst, batch, S, tw); break;
-    case 3: fft_stage<3, FWD, FIRST>(in, dst, batch, S, tw); break;
-    case 4: fft_stage<4, FWD, FIRST>(in, dst, batch, S, tw); break;
-    case 5: fft_stage<5, FWD, FIRST>(in, dst, batch, S, tw); break;
-    case 8: fft_stage<8, FWD, FIRST>(in, dst, batch, S, tw); break;
-    case 9: fft_stage<9, FWD, FIRST>(in, dst, batch, S, tw); break;
-    case 15: fft_stage<15, FWD, FIRST>(in, dst, batch, S, tw); break;
-    default: fft_stage<16, FWD, FIRST>(in, dst, batch, S, tw); break;
+    case 2: fft_stage<2, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    case 3: fft_stage<3, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    case 4: fft_stage<4, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    case 5: fft_stage<5, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    case 8: fft_stage<8, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    default: fft_stage<16, T, MAXE>(src, dst, batch, S, tw, sg); break;
   }
 }
 
-// Whole transform of the batch in `l`, forward or inverse without scaling; the
-// last stage writes `dst`, the others work in place.  Length 1 copies.
-template <bool FWD, class DST>
-__device__ __forceinline__ void fft_run(const FftSize& sz, const float2* tw, int batch, const Lds& l,
-                                        const DST& dst) {
+// Whole transform, forward (sg = -1) or inverse without scaling (sg = +1): the
+// first stage reads `src`, the last writes `dst`, the others work in place in
+// `lds`.  A length-1 transform copies.
+template <int T, int MAXE, class SRC, class DST>
+__device__ __forceinline__ void fft_run(const FftSize& sz, const float2* tw, float sg, int batch, const SRC& src,
+                                        const LdsIO& lds, const DST& dst) {
   const int n = sz.nstages;
   if (n == 0) {
-    for (int b = threadIdx.x; b < batch; b += T) dst.put1(b, 0, l.buf[l.pad(b * l.stride)]);
+    for (int b = threadIdx.x; b < batch; b += T) dst.store(b, 0, src.load(b, 0));
     if (DST::kLds) __syncthreads();
     return;
   }
   if (n == 1) {
-    fft_stage_r<FWD, true>(l, dst, batch, sz.st[0], tw);
+    fft_stage_r<T, MAXE>(src, dst, batch, sz.st[0], tw, sg);
     return;
   }
-  const LdsOut mid{l};
-  fft_stage_r<FWD, true>(l, mid, batch, sz.st[0], tw);
-  for (int s = 1; s < n - 1; ++s) fft_stage_r<FWD, false>(l, mid, batch, sz.st[s], tw);
-  fft_stage_r<FWD, false>(l, dst, batch, sz.st[n - 1], tw);
+  fft_stage_r<T, MAXE>(src, lds, batch, sz.st[0], tw, sg);
+  for (int s = 1; s < n - 1; ++s) fft_stage_r<T, MAXE>(lds, lds, batch, sz.st[s], tw, sg);
+  fft_stage_r<T, MAXE>(lds, dst, batch, sz.st[n - 1], tw, sg);
 }
 
-// ---------------------------------------------------------------------------
-// Work-item sequences of a persistent workgroup
-// ---------------------------------------------------------------------------
+// Two consecutive field values at an even index, as FP32.
+template <int FT>
+__device__ __forceinline__ float2 load_pair(const void* base, int64_t idx) {
+  if (FT == kF32) return *reinterpret_cast<const float2*>(static_cast<const float*>(base) + idx);
+  const uint32_t w = *reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(base) + idx);
+  if (FT == kBF16) return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xFFFF0000u));
+  _Float16 h0, h1;
+  const uint16_t lo = static_cast<uint16_t>(w & 0xFFFFu), hi = static_cast<uint16_t>(w >> 16);
+  __builtin_memcpy(&h0, &lo, 2);
+  __builtin_memcpy(&h1, &hi, 2);
+  return make_float2(static_cast<float>(h0), static_cast<float>(h1));
+}
 
-// Static: the items are split into 8 contiguous ranges, one per XCD
-// (workgroup b runs on XCD b mod 8); the workgroups of an XCD take its range
-// round-robin.  Every range with items has a workgroup when grid >= min(8, total).
-struct StaticItems {
-  int pos, end, step, total;
-  __device__ __forceinline__ int first(int n) {
-    total = n;
-    const int x = static_cast<int>(blockIdx.x % kXcds);
-    const int s = static_cast<int>(blockIdx.x / kXcds);
-    const int q = n / kXcds, rem = n % kXcds;
-    const int start = x * q + min(x, rem);
-    end = start + q + (x < rem ? 1 : 0);
-    step = (static_cast<int>(gridDim.x) - x + kXcds - 1) / kXcds;
-    pos = start + s;
-    return pos < end ? pos : total;
-  }
-  __device__ __forceinline__ int next() {
-    pos += step;
-    return pos < end ? pos : total;
-  }
-};
-
-// Dynamic: per-XCD counters of the work header (zero when the header is uploaded).
-struct CounterItems {
-  int* counters;
-  int total;
-  __device__ __forceinline__ int first(int n) {
-    total = n;
-    return grab_item(counters, n, true);
-  }
-  __device__ __forceinline__ int next() { return grab_item(counters, total, true); }
-};
+template <int FT>
+__device__ __forceinline__ float load_one(const void* base, int64_t idx) {
+  if (FT == kF32) return static_cast<const float*>(base)[idx];
+  const uint16_t v = static_cast<const uint16_t*>(base)[idx];
+  if (FT == kBF16) return __uint_as_float(static_cast<uint32_t>(v) << 16);
+  _Float16 h;
+  __builtin_memcpy(&h, &v, 2);
+  return static_cast<float>(h);
+}
 
 template <bool COLS>
 __device__ __forceinline__ int find_fft_plane(const FftPlane* planes, int nplanes, int item) {
@@ -456,508 +297,345 @@ __device__ __forceinline__ int find_fft_plane(const FftPlane* planes, int nplane
   return lo;
 }
 
-template <class E>
-__device__ __forceinline__ void copy_to_lds(E* dst, const E* __restrict__ src, int n) {
+template <int T>
+__device__ __forceinline__ void stage_twiddles(float2* dst, const float2* __restrict__ src, int n) {
   for (int i = threadIdx.x; i < n; i += T) dst[i] = src[i];
 }
 
-// Two consecutive field values at an even index, as one word (16-bit fields)
-// or two floats.
-template <int FT>
-struct FieldPair {
-  using type = uint32_t;
-  __device__ __forceinline__ static type load(const void* base, int64_t idx) {
-    return *reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(base) + idx);
-  }
-  __device__ __forceinline__ static float lo(type w) {
-    if (FT == kBF16) return __uint_as_float(w << 16);
-    _Float16 h;
-    const uint16_t v = static_cast<uint16_t>(w & 0xFFFFu);
-    __builtin_memcpy(&h, &v, 2);
-    return static_cast<float>(h);
-  }
-  __device__ __forceinline__ static float hi(type w) {
-    if (FT == kBF16) return __uint_as_float(w & 0xFFFF0000u);
-    _Float16 h;
-    const uint16_t v = static_cast<uint16_t>(w >> 16);
-    __builtin_memcpy(&h, &v, 2);
-    return static_cast<float>(h);
-  }
-  using one = uint32_t;
-  __device__ __forceinline__ static one load1(const void* base, int64_t idx) {
-    return static_cast<const uint16_t*>(base)[idx];
-  }
-  __device__ __forceinline__ static float val1(one w) { return lo(w); }
-};
-
-template <>
-struct FieldPair<kF32> {
-  using type = float2;
-  __device__ __forceinline__ static type load(const void* base, int64_t idx) {
-    return *reinterpret_cast<const float2*>(static_cast<const float*>(base) + idx);
-  }
-  __device__ __forceinline__ static float lo(type w) { return w.x; }
-  __device__ __forceinline__ static float hi(type w) { return w.y; }
-  using one = float;
-  __device__ __forceinline__ static one load1(const void* base, int64_t idx) {
-    return static_cast<const float*>(base)[idx];
-  }
-  __device__ __forceinline__ static float val1(one w) { return w; }
-};
-
-// Prefetch slots per thread: items up to T * kPre complex values stream
-// through registers (the row pass's residual inputs: T * kPre / 2); larger
-// items load their remainder when committed.
-constexpr int kPre = 8;
+// Global -> LDS copies issue kLoadBatch loads per thread before storing any of
+// them, so one memory round trip covers kLoadBatch elements instead of one.
+constexpr int kLoadBatch = 8;
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Pass 1: c = lam (D_x^T r_x + D_y^T r_y), real FFT of each row, transposed store
+// Stage sources and destinations of the three passes
 // ---------------------------------------------------------------------------
-template <int FT>
-struct RowsFwd {
-  static constexpr int kRaw = kPre / 2;  // raw residual values take 7 registers per element
-  using FP = FieldPair<FT>;
-  typename FP::type x[kRaw], y[kRaw], yp[kRaw];
-  typename FP::one xm[kRaw];
 
-  __device__ __forceinline__ static const FftPlane& plane(const FftPlane* pl, int np, int item) {
-    return pl[find_fft_plane<false>(pl, np, item)];
-  }
-  __device__ __forceinline__ static const void* table_key(const FftPlane& P) { return P.twM; }
-  __device__ __forceinline__ static void load_tables(const FftPlane& P, float2* smem) {
-    copy_to_lds(smem, P.twM, P.ntwM);
-    copy_to_lds(smem + P.r_split, P.twW, P.ntwW);
-  }
-  // residual values of element e (row e / M, complex column e mod M) of item rows i0..
-  __device__ __forceinline__ static void load_raw(const FftPlane& P, int i0, int e, typename FP::type& vx,
-                                                  typename FP::type& vy, typename FP::type& vyp,
-                                                  typename FP::one& vxm) {
-    const int M = P.W >> 1;
-    const int row = static_cast<int>(fdiv(static_cast<uint32_t>(e), P.m_div));
-    const int n = e - row * M;
-    const int i = i0 + row;
-    const int im1 = i == 0 ? P.H - 1 : i - 1;
+// Right-hand side of the residual-form solve for row i0 + b, two reals per
+// complex: c(i, j) = lam ((r_x(i, j-1) - r_x(i, j)) + (r_y(i-1, j) - r_y(i, j))).
+template <int FT>
+struct RhsSrc {
+  static constexpr bool kLds = false;
+  const void* rx;
+  const void* ry;
+  int i0, H, W;
+  float lam;
+  __device__ __forceinline__ float2 load(int b, int n) const {
+    const int i = i0 + b;
+    const int im1 = i == 0 ? H - 1 : i - 1;
     const int j0 = 2 * n;
-    const int jm = j0 == 0 ? P.W - 1 : j0 - 1;
-    const int64_t ri = static_cast<int64_t>(i) * P.W;
-    vx = FP::load(P.rx, ri + j0);
-    vy = FP::load(P.ry, ri + j0);
-    vyp = FP::load(P.ry, static_cast<int64_t>(im1) * P.W + j0);
-    vxm = FP::load1(P.rx, ri + jm);
-  }
-  // c(i, j) = lam ((r_x(i, j-1) - r_x(i, j)) + (r_y(i-1, j) - r_y(i, j))) at j = 2n, 2n+1
-  __device__ __forceinline__ static float2 rhs(float lam, typename FP::type vx, typename FP::type vy,
-                                               typename FP::type vyp, typename FP::one vxm) {
-    const float x0 = FP::lo(vx), x1 = FP::hi(vx);
-    return make_float2(lam * ((FP::val1(vxm) - x0) + (FP::lo(vyp) - FP::lo(vy))),
-                       lam * ((x0 - x1) + (FP::hi(vyp) - FP::hi(vy))));
-  }
-  __device__ __forceinline__ void prefetch(const FftPlane* pl, int np, int item) {
-    const FftPlane& P = plane(pl, np, item);
-    const int i0 = (item - P.row_begin) * P.rb;
-    const int nel = min(P.rb, P.H - i0) * (P.W >> 1);
-#pragma unroll
-    for (int u = 0; u < kRaw; ++u) {
-      const int e = threadIdx.x + u * T;
-      if (e < nel) load_raw(P, i0, e, x[u], y[u], yp[u], xm[u]);
-    }
-  }
-  __device__ __forceinline__ void commit(const FftPlane& P, int item, float2* smem) const {
-    const int M = P.W >> 1;
-    const int i0 = (item - P.row_begin) * P.rb;
-    const int nel = min(P.rb, P.H - i0) * M;
-    const Lds l{smem + P.r_data, P.sM, P.szM->pshift};
-#pragma unroll
-    for (int u = 0; u < kRaw; ++u) {
-      const int e = threadIdx.x + u * T;
-      if (e < nel) {
-        const int row = static_cast<int>(fdiv(static_cast<uint32_t>(e), P.m_div));
-        l.buf[l.pad(row * l.stride + e - row * M)] = rhs(P.lambda, x[u], y[u], yp[u], xm[u]);
-      }
-    }
-    for (int e0 = threadIdx.x + kRaw * T; e0 < nel; e0 += kRaw * T) {
-      typename FP::type vx[kRaw], vy[kRaw], vyp[kRaw];
-      typename FP::one vxm[kRaw];
-#pragma unroll
-      for (int u = 0; u < kRaw; ++u)
-        if (e0 + u * T < nel) load_raw(P, i0, e0 + u * T, vx[u], vy[u], vyp[u], vxm[u]);
-#pragma unroll
-      for (int u = 0; u < kRaw; ++u) {
-        const int e = e0 + u * T;
-        if (e < nel) {
-          const int row = static_cast<int>(fdiv(static_cast<uint32_t>(e), P.m_div));
-          l.buf[l.pad(row * l.stride + e - row * M)] = rhs(P.lambda, vx[u], vy[u], vyp[u], vxm[u]);
-        }
-      }
-    }
-  }
-  __device__ __forceinline__ static void compute(const FftPlane& P, int item, float2* smem) {
-    const int H = P.H, M = P.W >> 1;
-    const int i0 = (item - P.row_begin) * P.rb;
-    const int nrows = min(P.rb, H - i0);
-    const Lds l{smem + P.r_data, P.sM, P.szM->pshift};
-    fft_run<true>(*P.szM, smem, nrows, l, LdsOut{l});
-    // split step: X[k] = E[k] + exp(-2 pi i k/W) O[k], k = 0..M, Z[M] = Z[0]
-    const float2* twR = smem + P.r_split;
-    float2* spec = P.spec;
-    for (int idx = threadIdx.x; idx < (M + 1) * nrows; idx += T) {
-      int k, row;
-      if (nrows == P.rb) {
-        k = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.rb_div));
-        row = idx - k * nrows;
-      } else {
-        k = idx / nrows;
-        row = idx - k * nrows;
-      }
-      const float2 zk = l.buf[l.pad(row * l.stride + (k == M ? 0 : k))];
-      const float2 zm = l.buf[l.pad(row * l.stride + (k == 0 ? 0 : M - k))];
-      const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-      // o = (zk - conj(zm)) / (2i)
-      const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-      spec[static_cast<int64_t>(k) * H + i0 + row] = cadd(e, cmul(twiddle2(twR, k), o));
-    }
+    const int jm = j0 == 0 ? W - 1 : j0 - 1;
+    const int64_t ri = static_cast<int64_t>(i) * W;
+    const float2 x = load_pair<FT>(rx, ri + j0);
+    const float2 y = load_pair<FT>(ry, ri + j0);
+    const float2 yp = load_pair<FT>(ry, static_cast<int64_t>(im1) * W + j0);
+    const float xm = load_one<FT>(rx, ri + jm);
+    return make_float2(lam * ((xm - x.x) + (yp.x - y.x)), lam * ((x.x - x.y) + (yp.y - y.y)));
   }
 };
+
+// Spectrum columns in HBM ([W/2+1][H] layout, column b of the block).
+struct ColIO {
+  static constexpr bool kLds = false;
+  float2* spec;
+  int H;
+  __device__ __forceinline__ float2 load(int b, int n) const { return spec[static_cast<int64_t>(b) * H + n]; }
+  __device__ __forceinline__ void store(int b, int n, float2 v) const { spec[static_cast<int64_t>(b) * H + n] = v; }
+};
+
+// LDS destination that applies the Eq. (8) divide, 1 / (H W (1 + lam (sx + sy))).
+struct ScaledLds {
+  static constexpr bool kLds = true;
+  float2* buf;
+  int H, k0;
+  const float* sx;
+  const float* sy;
+  float lam, inv_hw;
+  __device__ __forceinline__ void store(int b, int n, float2 v) const {
+    const float den = fmaf(lam, sx[k0 + b] + sy[n], 1.0f);
+    buf[pad(b * H + n)] = cscale(v, inv_hw / den);
+  }
+};
+
+// u = f + delta for row i0 + b; element n holds the reals at columns 2n, 2n+1.
+struct OutDst {
+  static constexpr bool kLds = false;
+  const float* __restrict__ f;
+  float* __restrict__ u;
+  int64_t pitch;
+  int i0;
+  __device__ __forceinline__ void store(int b, int n, float2 v) const {
+    const int64_t o = static_cast<int64_t>(i0 + b) * pitch + 2 * n;
+    u[o] = f[o] + v.x;
+    u[o + 1] = f[o + 1] + v.y;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Pass 1: c = lam (D_x^T r_x + D_y^T r_y), real FFT of each row, transposed store
+// LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1), padded]
+// ---------------------------------------------------------------------------
+template <int FT>
+__device__ __forceinline__ void rows_fwd_item(const FftPlane* __restrict__ planes, int nplanes, int item,
+                                              float2* smem) {
+  constexpr int T = kFftThreads;
+  const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
+  const int blk = item - P.row_begin;
+  if (blk >= P.row_count) return;
+  const int H = P.H, W = P.W, M = W >> 1;
+  const int i0 = blk * P.rb;
+  const int nrows = min(P.rb, H - i0);
+  const int tid = threadIdx.x;
+  float2* twS = smem;
+  float2* twR = smem + kTwMax;
+  float2* buf = smem + 2 * kTwMax;
+  stage_twiddles<T>(twS, P.twM, P.ntwM);
+  stage_twiddles<T>(twR, P.twW, P.ntwW);
+  __syncthreads();
+  // the first stage forms the right-hand side straight from the residual fields
+  const LdsIO lds{buf, M};
+  fft_run<T, kFftLdsComplex>(*P.szM, twS, -1.0f, nrows, RhsSrc<FT>{P.rx, P.ry, i0, H, W, P.lambda}, lds, lds);
+
+  // split step: X[k] = E[k] + exp(-2 pi i k/W) O[k], k = 0..M, Z[M] = Z[0]
+  float2* spec = P.spec;
+  for (int idx = tid; idx < (M + 1) * nrows; idx += T) {
+    int k, row;
+    if (nrows == P.rb) {
+      k = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.rb_div));
+      row = idx - k * nrows;
+    } else {
+      k = idx / nrows;
+      row = idx - k * nrows;
+    }
+    const float2 zk = buf[pad(row * M + (k == M ? 0 : k))];
+    const float2 zm = buf[pad(row * M + (k == 0 ? 0 : M - k))];
+    const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    // o = (zk - conj(zm)) / (2i)
+    const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+    spec[static_cast<int64_t>(k) * H + i0 + row] = cadd(e, cmul(twiddle(twR, k), o));
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Pass 2: per spectrum column, forward FFT over H, divide, inverse FFT over H.
+// The forward transform reads the columns from HBM in its first stage and
+// applies the divide in its last; the inverse writes HBM in its last stage.
+// LDS: [table of W_H: kTwMax][columns: cb x H, padded]
 // ---------------------------------------------------------------------------
-struct Cols {
-  float2 v[kPre];
-
-  __device__ __forceinline__ static const FftPlane& plane(const FftPlane* pl, int np, int item) {
-    return pl[find_fft_plane<true>(pl, np, item)];
-  }
-  __device__ __forceinline__ static const void* table_key(const FftPlane& P) { return P.twH; }
-  __device__ __forceinline__ static void load_tables(const FftPlane& P, float2* smem) {
-    copy_to_lds(smem, P.twH, P.ntwH);
-    copy_to_lds(reinterpret_cast<float*>(smem + P.c_sy), P.sy, P.H);
-  }
-  __device__ __forceinline__ void prefetch(const FftPlane* pl, int np, int item) {
-    const FftPlane& P = plane(pl, np, item);
-    const int k0 = (item - P.col_begin) * P.cb;
-    const int nel = min(P.cb, (P.W >> 1) + 1 - k0) * P.H;
-    const float2* src = P.spec + static_cast<int64_t>(k0) * P.H;
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int e = threadIdx.x + u * T;
-      if (e < nel) v[u] = src[e];
-    }
-  }
-  __device__ __forceinline__ void commit(const FftPlane& P, int item, float2* smem) const {
-    const int H = P.H;
-    const int k0 = (item - P.col_begin) * P.cb;
-    const int ncols = min(P.cb, (P.W >> 1) + 1 - k0);
-    const int nel = ncols * H;
-    const Lds l{smem + P.c_data, P.sH, P.szH->pshift};
-    if (static_cast<int>(threadIdx.x) < ncols) reinterpret_cast<float*>(smem + P.c_sx)[threadIdx.x] = P.sx[k0 + threadIdx.x];
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int e = threadIdx.x + u * T;
-      if (e < nel) {
-        const int b = static_cast<int>(fdiv(static_cast<uint32_t>(e), P.h_div));
-        l.buf[l.pad(b * l.stride + e - b * H)] = v[u];
-      }
-    }
-    const float2* src = P.spec + static_cast<int64_t>(k0) * H;
-    for (int e0 = threadIdx.x + kPre * T; e0 < nel; e0 += kPre * T) {
-      float2 w[kPre];
-#pragma unroll
-      for (int u = 0; u < kPre; ++u)
-        if (e0 + u * T < nel) w[u] = src[e0 + u * T];
-#pragma unroll
-      for (int u = 0; u < kPre; ++u) {
-        const int e = e0 + u * T;
-        if (e < nel) {
-          const int b = static_cast<int>(fdiv(static_cast<uint32_t>(e), P.h_div));
-          l.buf[l.pad(b * l.stride + e - b * H)] = w[u];
-        }
-      }
-    }
-  }
-  __device__ __forceinline__ static void compute(const FftPlane& P, int item, float2* smem) {
-    const int H = P.H, W = P.W, M = W >> 1;
-    const int k0 = (item - P.col_begin) * P.cb;
-    const int ncols = min(P.cb, M + 1 - k0);
-    const Lds l{smem + P.c_data, P.sH, P.szH->pshift};
-    const ScaledLds scaled{l, reinterpret_cast<const float*>(smem + P.c_sy), reinterpret_cast<const float*>(smem + P.c_sx),
-                           P.lambda, 1.0f / (static_cast<float>(H) * static_cast<float>(W))};
-    fft_run<true>(*P.szH, smem, ncols, l, scaled);
-    fft_run<false>(*P.szH, smem, ncols, l, ColOut{P.spec + static_cast<int64_t>(k0) * H, H});
-  }
-};
+__device__ __forceinline__ void cols_item(const FftPlane* __restrict__ planes, int nplanes, int item,
+                                          float2* smem) {
+  constexpr int T = kFftThreads;
+  const FftPlane& P = planes[find_fft_plane<true>(planes, nplanes, item)];
+  const int blk = item - P.col_begin;
+  if (blk >= P.col_count) return;
+  const int H = P.H, W = P.W, M = W >> 1;
+  const int k0 = blk * P.cb;
+  const int ncols = min(P.cb, M + 1 - k0);
+  float2* twS = smem;
+  float2* buf = smem + kTwMax;
+  stage_twiddles<T>(twS, P.twH, P.ntwH);
+  __syncthreads();
+  const ColIO col{P.spec + static_cast<int64_t>(k0) * H, H};
+  const LdsIO lds{buf, H};
+  const ScaledLds scaled{buf, H, k0, P.sx, P.sy, P.lambda,
+                         1.0f / (static_cast<float>(H) * static_cast<float>(W))};
+  fft_run<T, kFftLdsComplex>(*P.szH, twS, -1.0f, ncols, col, lds, scaled);
+  fft_run<T, kFftLdsComplex>(*P.szH, twS, 1.0f, ncols, lds, lds, col);
+}
 
 // ---------------------------------------------------------------------------
 // Pass 3: complex-to-real inverse of each row, u = f + delta (written by the
 // last stage of the inverse transform)
+// LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1), padded]
 // ---------------------------------------------------------------------------
-struct RowsInv {
-  float2 v[kPre];
-
-  __device__ __forceinline__ static const FftPlane& plane(const FftPlane* pl, int np, int item) {
-    return pl[find_fft_plane<false>(pl, np, item)];
-  }
-  __device__ __forceinline__ static const void* table_key(const FftPlane& P) { return P.twM; }
-  __device__ __forceinline__ static void load_tables(const FftPlane& P, float2* smem) {
-    copy_to_lds(smem, P.twM, P.ntwM);
-    copy_to_lds(smem + P.r_split, P.twW, P.ntwW);
-  }
-  // element e of the item: spectrum column k = e / nrows, row e mod nrows
-  __device__ __forceinline__ static void coords(const FftPlane& P, int nrows, int e, int& k, int& row) {
-    if (nrows == P.rb) {
-      k = static_cast<int>(fdiv(static_cast<uint32_t>(e), P.rb_div));
-    } else {
-      k = e / nrows;
-    }
-    row = e - k * nrows;
-  }
-  __device__ __forceinline__ void prefetch(const FftPlane* pl, int np, int item) {
-    const FftPlane& P = plane(pl, np, item);
-    const int i0 = (item - P.row_begin) * P.rb;
-    const int nrows = min(P.rb, P.H - i0);
-    const int nel = ((P.W >> 1) + 1) * nrows;
+__device__ __forceinline__ void rows_inv_item(const FftPlane* __restrict__ planes, int nplanes, int item,
+                                              float2* smem) {
+  constexpr int T = kFftThreads;
+  const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
+  const int blk = item - P.row_begin;
+  if (blk >= P.row_count) return;
+  const int H = P.H, W = P.W, M = W >> 1;
+  const int S = M + 1;  // LDS row stride
+  const int i0 = blk * P.rb;
+  const int nrows = min(P.rb, H - i0);
+  const int tid = threadIdx.x;
+  float2* twS = smem;
+  float2* twR = smem + kTwMax;
+  float2* buf = smem + 2 * kTwMax;
+  stage_twiddles<T>(twS, P.twM, P.ntwM);
+  stage_twiddles<T>(twR, P.twW, P.ntwW);
+  const float2* spec = P.spec;
+  const int ntot = S * nrows;
+  for (int base = tid; base < ntot; base += T * kLoadBatch) {
+    float2 v[kLoadBatch];
+    int dst[kLoadBatch];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int e = threadIdx.x + u * T;
-      if (e < nel) {
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int idx = base + u * T;
+      if (idx < ntot) {
         int k, row;
-        coords(P, nrows, e, k, row);
-        v[u] = P.spec[static_cast<int64_t>(k) * P.H + i0 + row];
-      }
-    }
-  }
-  __device__ __forceinline__ void commit(const FftPlane& P, int item, float2* smem) const {
-    const int i0 = (item - P.row_begin) * P.rb;
-    const int nrows = min(P.rb, P.H - i0);
-    const int nel = ((P.W >> 1) + 1) * nrows;
-    const Lds l{smem + P.r_data, P.sM, P.szM->pshift};
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int e = threadIdx.x + u * T;
-      if (e < nel) {
-        int k, row;
-        coords(P, nrows, e, k, row);
-        l.buf[l.pad(row * l.stride + k)] = v[u];
-      }
-    }
-    for (int e0 = threadIdx.x + kPre * T; e0 < nel; e0 += kPre * T) {
-      float2 w[kPre];
-      int dst[kPre];
-#pragma unroll
-      for (int u = 0; u < kPre; ++u) {
-        const int e = e0 + u * T;
-        if (e < nel) {
-          int k, row;
-          coords(P, nrows, e, k, row);
-          w[u] = P.spec[static_cast<int64_t>(k) * P.H + i0 + row];
-          dst[u] = l.pad(row * l.stride + k);
+        if (nrows == P.rb) {
+          k = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.rb_div));
+          row = idx - k * nrows;
+        } else {
+          k = idx / nrows;
+          row = idx - k * nrows;
         }
+        v[u] = spec[static_cast<int64_t>(k) * H + i0 + row];
+        dst[u] = pad(row * S + k);
       }
+    }
 #pragma unroll
-      for (int u = 0; u < kPre; ++u)
-        if (e0 + u * T < nel) l.buf[dst[u]] = w[u];
-    }
+    for (int u = 0; u < kLoadBatch; ++u)
+      if (base + u * T < ntot) buf[dst[u]] = v[u];
   }
-  __device__ __forceinline__ static void compute(const FftPlane& P, int item, float2* smem) {
-    const int M = P.W >> 1;
-    const int i0 = (item - P.row_begin) * P.rb;
-    const int nrows = min(P.rb, P.H - i0);
-    const Lds l{smem + P.r_data, P.sM, P.szM->pshift};
-    const float2* twR = smem + P.r_split;
-    // Z[k] = (X[k] + conj X[M-k]) + i exp(2 pi i k/W) (X[k] - conj X[M-k]), k = 0..M-1;
-    // one thread forms the pair (k, M-k) so the update is in place
-    const int half = M / 2;
-    for (int idx = threadIdx.x; idx < (half + 1) * nrows; idx += T) {
-      const int row = idx / (half + 1);
-      const int k = idx - row * (half + 1);
-      const int ia = l.pad(row * l.stride + k), ib = l.pad(row * l.stride + M - k);
-      const float2 a = l.buf[ia], b = l.buf[ib];
-      const float2 wa = cconj(twiddle2(twR, k));  // exp(+2 pi i k/W)
-      const float2 wb = cconj(twiddle2(twR, M - k));
-      const float2 sa = cadd(a, cconj(b)), da = csub(a, cconj(b));
-      const float2 za = cadd(sa, cmul_isg(cmul(wa, da), 1.0f));
-      const float2 sb = cadd(b, cconj(a)), db = csub(b, cconj(a));
-      const float2 zb = cadd(sb, cmul_isg(cmul(wb, db), 1.0f));
-      l.buf[ia] = za;
-      if (k != 0 && M - k != k) l.buf[ib] = zb;
-    }
-    __syncthreads();
-    fft_run<false>(*P.szM, smem, nrows, l, RowOut{P.f, P.u, P.pitch, i0});
+  __syncthreads();
+  // Z[k] = (X[k] + conj X[M-k]) + i exp(2 pi i k/W) (X[k] - conj X[M-k]), k = 0..M-1;
+  // one thread forms the pair (k, M-k) so the update is in place
+  const int half = M / 2;
+  for (int idx = tid; idx < (half + 1) * nrows; idx += T) {
+    const int row = idx / (half + 1);
+    const int k = idx - row * (half + 1);
+    const int ia = pad(row * S + k), ib = pad(row * S + M - k);
+    const float2 a = buf[ia], b = buf[ib];
+    const float2 wa = cconj(twiddle(twR, k));  // exp(+2 pi i k/W)
+    const float2 wb = cconj(twiddle(twR, M - k));
+    const float2 sa = cadd(a, cconj(b)), da = csub(a, cconj(b));
+    const float2 za = cadd(sa, cmul_isg(cmul(wa, da), 1.0f));
+    const float2 sb = cadd(b, cconj(a)), db = csub(b, cconj(a));
+    const float2 zb = cadd(sb, cmul_isg(cmul(wb, db), 1.0f));
+    buf[ia] = za;
+    if (k != 0 && M - k != k) buf[ib] = zb;
   }
-};
-
-// ---------------------------------------------------------------------------
-// Persistent driver: commit the prefetched item into LDS, start the next
-// item's loads, transform the committed item.  Tables are (re)loaded when an
-// item's plane uses other tables than the ones in LDS.
-// ---------------------------------------------------------------------------
-template <class PASS, class SEQ>
-__device__ __forceinline__ void run_items(const FftPlane* __restrict__ planes, int nplanes, int total, SEQ& seq,
-                                          float2* smem) {
-  PASS pass;
-  int item = seq.first(total);
-  if (item < total) pass.prefetch(planes, nplanes, item);
-  const void* loaded = nullptr;
-  while (item < total) {
-    const FftPlane& P = PASS::plane(planes, nplanes, item);
-    const void* key = PASS::table_key(P);
-    if (key != loaded) {
-      PASS::load_tables(P, smem);
-      loaded = key;
-    }
-    pass.commit(P, item, smem);
-    __syncthreads();
-    const int next = seq.next();
-    if (next < total) pass.prefetch(planes, nplanes, next);
-    PASS::compute(P, item, smem);
-    __syncthreads();
-    item = next;
-  }
+  __syncthreads();
+  const LdsIO lds{buf, S};
+  fft_run<T, kFftLdsComplex>(*P.szM, twS, 1.0f, nrows, lds, lds, OutDst{P.f, P.u, P.pitch, i0});
 }
 
-// With work == nullptr the launch covers `items` items of `planes` with a
-// fixed grid and static ranges; otherwise (launches captured in a graph) the
-// item counts and planes come from the work header in device memory and the
-// items from its per-XCD counters.
-template <int FT, bool DYN>
+// ---------------------------------------------------------------------------
+// Kernels: with work == nullptr one workgroup per item; otherwise a fixed
+// (persistent) grid draws the items of the work header, read from device
+// memory when the kernel runs (launches captured in a graph), from one counter
+// per XCD.  Either way consecutive row blocks run on the same XCD.
+// ---------------------------------------------------------------------------
+template <int FT, bool PERSIST>
 __global__ void __launch_bounds__(kFftThreads, 4)
-fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes, int items, WorkHeader* __restrict__ work) {
+fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
   extern __shared__ float2 smem[];
-  if (!DYN) {
-    StaticItems seq;
-    run_items<RowsFwd<FT>>(planes, nplanes, items, seq, smem);
-  } else {
-    CounterItems seq{work->next[0], 0};
-    run_items<RowsFwd<FT>>(static_cast<const FftPlane*>(work->planes), work->nplanes, work->items, seq, smem);
+  if (!PERSIST) {
+    rows_fwd_item<FT>(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
+    return;
+  }
+  const int total = work->items, np = work->nplanes;
+  const FftPlane* pl = static_cast<const FftPlane*>(work->planes);
+  for (;;) {
+    const int item = grab_item(work->next[0], total, true);
+    if (item >= total) break;
+    rows_fwd_item<FT>(pl, np, item, smem);
+    __syncthreads();
   }
 }
 
-template <bool DYN>
+template <bool PERSIST>
 __global__ void __launch_bounds__(kFftThreads, 4)
-fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes, int items, WorkHeader* __restrict__ work) {
+fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
   extern __shared__ float2 smem[];
-  if (!DYN) {
-    StaticItems seq;
-    run_items<Cols>(planes, nplanes, items, seq, smem);
-  } else {
-    CounterItems seq{work->next[1], 0};
-    run_items<Cols>(static_cast<const FftPlane*>(work->planes), work->nplanes, work->items2, seq, smem);
+  if (!PERSIST) {
+    cols_item(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
+    return;
+  }
+  const int total = work->items2, np = work->nplanes;
+  const FftPlane* pl = static_cast<const FftPlane*>(work->planes);
+  for (;;) {
+    const int item = grab_item(work->next[1], total, true);
+    if (item >= total) break;
+    cols_item(pl, np, item, smem);
+    __syncthreads();
   }
 }
 
-template <bool DYN>
+template <bool PERSIST>
 __global__ void __launch_bounds__(kFftThreads, 4)
-fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes, int items, WorkHeader* __restrict__ work) {
+fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
   extern __shared__ float2 smem[];
-  if (!DYN) {
-    StaticItems seq;
-    run_items<RowsInv>(planes, nplanes, items, seq, smem);
-  } else {
-    CounterItems seq{work->next[2], 0};
-    run_items<RowsInv>(static_cast<const FftPlane*>(work->planes), work->nplanes, work->items, seq, smem);
+  if (!PERSIST) {
+    rows_inv_item(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
+    return;
+  }
+  const int total = work->items, np = work->nplanes;
+  const FftPlane* pl = static_cast<const FftPlane*>(work->planes);
+  for (;;) {
+    const int item = grab_item(work->next[2], total, true);
+    if (item >= total) break;
+    rows_inv_item(pl, np, item, smem);
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Host side: LDS sizes, kernel attributes, occupancy, launchers
+// Launchers
 // ---------------------------------------------------------------------------
-static int align16(int n) { return (n + 15) / 16 * 16; }
-static int padded(int n, int pshift) { return n + (pshift >= 31 ? 0 : (n >> pshift)) + 1; }
-
-int fft_lds_stride(int n) { return align16(n); }
-
-void fft_rows_layout(int M, int rb, int pshift, int ntwM, int ntwW, int* r_split, int* r_data, size_t* bytes) {
-  *r_split = align16(ntwM);
-  *r_data = *r_split + align16(ntwW);
-  *bytes = static_cast<size_t>(*r_data + padded(rb * align16(M + 1), pshift)) * sizeof(float2);
-}
-
-void fft_cols_layout(int H, int cb, int pshift, int ntwH, int* c_sy, int* c_sx, int* c_data, size_t* bytes) {
-  *c_sy = align16(ntwH);
-  *c_sx = *c_sy + align16((H + 1) / 2);
-  *c_data = *c_sx + 16;
-  *bytes = static_cast<size_t>(*c_data + padded(cb * align16(H), pshift)) * sizeof(float2);
-}
-
-static const void* fft_kernel_fn(int pass, int ft, bool dyn) {
-  if (pass == 0) {
-    if (ft == kF32) return dyn ? reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF32, true>)
-                               : reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF32, false>);
-    if (ft == kBF16) return dyn ? reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kBF16, true>)
-                                : reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kBF16, false>);
-    return dyn ? reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF16, true>)
-               : reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF16, false>);
-  }
-  if (pass == 1) return dyn ? reinterpret_cast<const void*>(&fft_cols_kernel<true>)
-                            : reinterpret_cast<const void*>(&fft_cols_kernel<false>);
-  return dyn ? reinterpret_cast<const void*>(&fft_rows_inv_kernel<true>)
-             : reinterpret_cast<const void*>(&fft_rows_inv_kernel<false>);
-}
+static size_t padded(int n) { return static_cast<size_t>(n) + static_cast<size_t>(n) / 16 + 1; }
+size_t fft_rows_lds_bytes(int M, int rb) { return (2 * kTwMax + padded(rb * (M + 1))) * sizeof(float2); }
+size_t fft_cols_lds_bytes(int H, int cb) { return (kTwMax + padded(cb * H)) * sizeof(float2); }
 
 hipError_t fft_init_kernels() {
-  const int kMax = 128 * 1024;  // largest need is about 84 KiB; static LDS comes on top
-  for (int pass = 0; pass < 3; ++pass)
-    for (int ft = 0; ft < 3; ++ft)
-      for (int dyn = 0; dyn < 2; ++dyn) {
-        if (pass > 0 && ft > 0) continue;
-        const hipError_t e = hipFuncSetAttribute(fft_kernel_fn(pass, ft, dyn != 0),
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, kMax);
-        if (e != hipSuccess) return e;
-      }
+  const int kMax = 128 * 1024;  // largest need is about 73 KiB; static LDS comes on top
+  const void* fns[] = {reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF32, false>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kBF16, false>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF16, false>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF32, true>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kBF16, true>),
+                       reinterpret_cast<const void*>(&fft_rows_fwd_kernel<kF16, true>),
+                       reinterpret_cast<const void*>(&fft_cols_kernel<false>),
+                       reinterpret_cast<const void*>(&fft_cols_kernel<true>),
+                       reinterpret_cast<const void*>(&fft_rows_inv_kernel<false>),
+                       reinterpret_cast<const void*>(&fft_rows_inv_kernel<true>)};
+  for (const void* fn : fns) {
+    const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMax);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
-int fft_grid(int pass, int ft, size_t lds_bytes, int items) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fft_kernel_fn(pass, ft, false), kFftThreads,
-                                                   lds_bytes) != hipSuccess || per_cu < 1)
-    per_cu = 1;
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    cus = 256;
-  return std::max(1, std::min(items, cus * per_cu));
-}
-
 template <int FT>
-static void rows_fwd(const FftPlane* planes, int nplanes, int items, int grid, size_t lds, hipStream_t s,
-                     WorkHeader* work) {
-  const dim3 g(grid), b(kFftThreads);
+static void rows_fwd(const FftPlane* planes, int nplanes, int blocks, size_t lds, hipStream_t s, WorkHeader* work) {
+  const dim3 g(blocks), b(kFftThreads);
   if (work == nullptr)
-    hipLaunchKernelGGL((fft_rows_fwd_kernel<FT, false>), g, b, lds, s, planes, nplanes, items, work);
+    hipLaunchKernelGGL((fft_rows_fwd_kernel<FT, false>), g, b, lds, s, planes, nplanes, work);
   else
-    hipLaunchKernelGGL((fft_rows_fwd_kernel<FT, true>), g, b, lds, s, planes, nplanes, items, work);
+    hipLaunchKernelGGL((fft_rows_fwd_kernel<FT, true>), g, b, lds, s, planes, nplanes, work);
 }
 
-hipError_t launch_fft_rows_fwd(const FftPlane* planes, int nplanes, int items, int grid, size_t lds_bytes,
+hipError_t launch_fft_rows_fwd(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
                                int field_type, hipStream_t s, WorkHeader* work) {
-  if (grid <= 0) return hipSuccess;
-  if (field_type == kF32) rows_fwd<kF32>(planes, nplanes, items, grid, lds_bytes, s, work);
-  else if (field_type == kBF16) rows_fwd<kBF16>(planes, nplanes, items, grid, lds_bytes, s, work);
-  else rows_fwd<kF16>(planes, nplanes, items, grid, lds_bytes, s, work);
+  if (blocks <= 0) return hipSuccess;
+  if (field_type == kF32) rows_fwd<kF32>(planes, nplanes, blocks, lds_bytes, s, work);
+  else if (field_type == kBF16) rows_fwd<kBF16>(planes, nplanes, blocks, lds_bytes, s, work);
+  else rows_fwd<kF16>(planes, nplanes, blocks, lds_bytes, s, work);
   return hipGetLastError();
 }
 
-hipError_t launch_fft_cols(const FftPlane* planes, int nplanes, int items, int grid, size_t lds_bytes,
-                           hipStream_t s, WorkHeader* work) {
-  if (grid <= 0) return hipSuccess;
-  const dim3 g(grid), b(kFftThreads);
+hipError_t launch_fft_cols(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes, hipStream_t s,
+                           WorkHeader* work) {
+  if (blocks <= 0) return hipSuccess;
+  const dim3 g(blocks), b(kFftThreads);
   if (work == nullptr)
-    hipLaunchKernelGGL((fft_cols_kernel<false>), g, b, lds_bytes, s, planes, nplanes, items, work);
+    hipLaunchKernelGGL((fft_cols_kernel<false>), g, b, lds_bytes, s, planes, nplanes, work);
   else
-    hipLaunchKernelGGL((fft_cols_kernel<true>), g, b, lds_bytes, s, planes, nplanes, items, work);
+    hipLaunchKernelGGL((fft_cols_kernel<true>), g, b, lds_bytes, s, planes, nplanes, work);
   return hipGetLastError();
 }
 
-hipError_t launch_fft_rows_inv(const FftPlane* planes, int nplanes, int items, int grid, size_t lds_bytes,
+hipError_t launch_fft_rows_inv(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
                                hipStream_t s, WorkHeader* work) {
-  if (grid <= 0) return hipSuccess;
-  const dim3 g(grid), b(kFftThreads);
+  if (blocks <= 0) return hipSuccess;
+  const dim3 g(blocks), b(kFftThreads);
   if (work == nullptr)
-    hipLaunchKernelGGL((fft_rows_inv_kernel<false>), g, b, lds_bytes, s, planes, nplanes, items, work);
+    hipLaunchKernelGGL((fft_rows_inv_kernel<false>), g, b, lds_bytes, s, planes, nplanes, work);
   else
-    hipLaunchKernelGGL((fft_rows_inv_kernel<true>), g, b, lds_bytes, s, planes, nplanes, items, work);
+    hipLaunchKernelGGL((fft_rows_inv_kernel<true>), g, b, lds_bytes, s, planes, nplanes, work);
   return hipGetLastError();
 }
 

@@ -161,6 +161,7 @@ struct blfls_server_s {
   static constexpr size_t kHeaderBytes = 16384;
   static constexpr int kMaxGroups = static_cast<int>(kHeaderBytes / sizeof(WorkHeader));
   static constexpr int kBlfGrid = 2048;  // persistent grids of the captured kernels
+  static constexpr int kFftGrid = 1024;
   static constexpr int kAuxGrid = 1024;
   size_t stage_bytes = 0;
   size_t kFftLdsMax = 0;
@@ -242,17 +243,14 @@ static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
   return groups;
 }
 
-// LDS classes of the captured FFT launches (4, 3 and 2 workgroups per CU, then
-// the worst case): a step whose images all fit a smaller class keeps more FFT
-// workgroups per CU.  Each class stays 256 bytes under its share of the CU's
-// 160 KiB, which leaves room for the kernels' static LDS (the item counter).
-constexpr size_t kFftLdsClasses[3] = {40960 - 256, 49152 - 256, 81920 - 256};
+// LDS of the captured FFT launches: steps whose images all fit the small class
+// keep four FFT workgroups per CU instead of the worst case's two.  The class
+// stays 256 bytes under a quarter of the CU's 160 KiB, which leaves room for
+// the kernels' static LDS (the item counter).
+constexpr size_t kFftLdsSmall = 40960 - 256;
 
-static int fft_lds_class(const Group& g) {
-  const size_t need = std::max(g.lds_rows, g.lds_cols);
-  int c = 0;
-  while (c < 3 && need > kFftLdsClasses[c]) ++c;
-  return c;
+static size_t fft_lds_class(const Group& g, size_t lds_max) {
+  return std::max(g.lds_rows, g.lds_cols) <= kFftLdsSmall ? kFftLdsSmall : lds_max;
 }
 
 static std::vector<int> signature(const std::vector<Group>& groups) {
@@ -260,7 +258,7 @@ static std::vector<int> signature(const std::vector<Group>& groups) {
   for (const Group& g : groups) {
     sig.push_back(g.kind);
     if (g.kind == 2) sig.push_back(g.R * 2 + (g.joint ? 1 : 0));
-    else if (g.kind == 3) sig.push_back(1 + fft_lds_class(g));
+    else if (g.kind == 3) sig.push_back(std::max(g.lds_rows, g.lds_cols) <= kFftLdsSmall ? 1 : 2);
     else sig.push_back(0);
   }
   return sig;
@@ -291,11 +289,9 @@ hipError_t blfls_server_s::launch_direct(std::vector<Group>& groups, int slot, i
       case 2: e = launch_blf(g.R, reinterpret_cast<const BlfPlane*>(d), g.n, g.items, g.joint, ft, stream); break;
       default: {
         const FftPlane* fp = reinterpret_cast<const FftPlane*>(d);
-        e = launch_fft_rows_fwd(fp, g.n, g.items, fft_grid(0, ft, g.lds_rows, g.items), g.lds_rows, ft, stream);
-        if (e == hipSuccess)
-          e = launch_fft_cols(fp, g.n, g.items2, fft_grid(1, kF32, g.lds_cols, g.items2), g.lds_cols, stream);
-        if (e == hipSuccess)
-          e = launch_fft_rows_inv(fp, g.n, g.items, fft_grid(2, kF32, g.lds_rows, g.items), g.lds_rows, stream);
+        e = launch_fft_rows_fwd(fp, g.n, g.items, g.lds_rows, ft, stream);
+        if (e == hipSuccess) e = launch_fft_cols(fp, g.n, g.items2, g.lds_cols, stream);
+        if (e == hipSuccess) e = launch_fft_rows_inv(fp, g.n, g.items, g.lds_rows, stream);
       }
     }
     if (e != hipSuccess) return e;
@@ -320,14 +316,10 @@ hipError_t blfls_server_s::build_graph(const std::vector<Group>& groups, int slo
       case 1: le = launch_minmax(nullptr, 0, capture_stream, w, kAuxGrid); break;
       case 2: le = launch_blf(g.R, nullptr, 0, kBlfGrid, g.joint, ft, capture_stream, w); break;
       default: {
-        const int c = fft_lds_class(g);
-        const size_t lds = c < 3 ? kFftLdsClasses[c] : kFftLdsMax;
-        const int all = 1 << 30;  // grid: every workgroup the device holds at once
-        le = launch_fft_rows_fwd(nullptr, 0, 0, fft_grid(0, ft, lds, all), lds, ft, capture_stream, w);
-        if (le == hipSuccess)
-          le = launch_fft_cols(nullptr, 0, 0, fft_grid(1, kF32, lds, all), lds, capture_stream, w);
-        if (le == hipSuccess)
-          le = launch_fft_rows_inv(nullptr, 0, 0, fft_grid(2, kF32, lds, all), lds, capture_stream, w);
+        const size_t lds = fft_lds_class(g, kFftLdsMax);
+        le = launch_fft_rows_fwd(nullptr, 0, kFftGrid, lds, ft, capture_stream, w);
+        if (le == hipSuccess) le = launch_fft_cols(nullptr, 0, kFftGrid, lds, capture_stream, w);
+        if (le == hipSuccess) le = launch_fft_rows_inv(nullptr, 0, kFftGrid, lds, capture_stream, w);
       }
     }
   }
@@ -358,10 +350,7 @@ hipError_t blfls_server_s::launch_step(Step& st, int slot) {
   }
   size_t used = tables_base + st.jobs.size() * sizeof(RequestTables);
   std::vector<Group> groups = build_groups(st.jobs);
-  bool fits = static_cast<int>(groups.size()) <= kMaxGroups;
-  for (const Group& g : groups)
-    if (g.kind == 3 && std::max(g.lds_rows, g.lds_cols) > kFftLdsMax) fits = false;
-  if (!fits) {
+  if (static_cast<int>(groups.size()) > kMaxGroups) {
     stats_direct_steps++;
     const hipError_t e = launch_direct(groups, slot, ft, used);
     return e == hipSuccess ? hipEventRecord(st.done, stream) : e;
@@ -505,17 +494,7 @@ blfls_status blfls_server_create(blfls_server_t* out, void* arena, size_t arena_
   hipError_t e = hipGetDevice(&s->device);
   if (e != hipSuccess) { delete s; return hip_error(e, "hipGetDevice"); }
   s->stage_bytes = stage_bytes;
-  {
-    // LDS of the largest captured FFT class: 4096-point columns with the
-    // densest padding bound every plan's needs (a step that needed more would
-    // take the direct launches, which size LDS exactly)
-    int a = 0, b = 0;
-    size_t rows = 0, cols = 0;
-    fft_rows_layout(kMaxFft, 2, 3, kMaxFft, kTwLo + kMaxFft / kTwLo + 1, &a, &b, &rows);
-    int c = 0;
-    fft_cols_layout(kMaxFft, 2, 3, kMaxFft, &a, &c, &b, &cols);
-    s->kFftLdsMax = std::max(rows, cols);
-  }
+  s->kFftLdsMax = std::max(fft_rows_lds_bytes(kFftLdsComplex - 1, 1), fft_cols_lds_bytes(kFftLdsComplex, 1));
   e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
   if (e != hipSuccess) { delete s; return hip_error(e, "capture stream"); }
   s->arena_alloc.init(reserved, arena_bytes - reserved);
