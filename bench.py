@@ -163,16 +163,16 @@ def run_rgb1024(args, torch, blfls):
     }
     if not args.no_cpu_baseline:
         import oracle
-        fin = f64[0].astype(np.float32).astype(np.float64)
+        fin = f64.astype(np.float32).astype(np.float64)
         t0 = time.perf_counter()
-        ref = oracle.smooth(fin, prm["lam"], prm["sigma_s"], prm["sigma_r"])
+        ref = np.stack([oracle.smooth(fin[c], prm["lam"], prm["sigma_s"], prm["sigma_r"]) for c in range(C)])
         t = time.perf_counter() - t0
-        err = float(np.max(np.abs(u_fp32[0].cpu().numpy().astype(np.float64) - ref)))
-        out["cpu_baseline"] = {"value": round(H * W / (C * t) / 1e6, 4), "unit": "MPix/s", "cores": 1,
+        err = float(np.max(np.abs(u_fp32.cpu().numpy().astype(np.float64) - ref)))
+        out["cpu_baseline"] = {"value": round(H * W / t / 1e6, 4), "unit": "MPix/s", "cores": 1,
                                "kind": "oracle",
-                               "sample": f"channel 0 of the 1024x1024 RGB image (1 of 3 channels, {t:.1f} s, "
-                                         f"numpy FP64 single thread on {cpu_model()}); rate scaled to RGB images"}
-        out["max_abs_vs_oracle_ch0"] = err
+                               "sample": f"one whole 1024x1024 RGB image (the three channels, {t:.1f} s, "
+                                         f"numpy FP64 single thread on {cpu_model()})"}
+        out["max_abs_vs_oracle"] = err
     plan.close()
     return out
 
