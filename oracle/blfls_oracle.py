@@ -31,6 +31,10 @@ Readings taken where the paper is silent (each one is listed in the design notes
   * the optional normalisation of the experiments section (images and gradients
     mapped to [0, 1] before smoothing and back after) is applied per channel and
     per field, literally, when ``normalize=True``;
+  * NC-LS (Section III-D) replaces the BLF by the normalized-convolution filter
+    of the domain transform on the same fields and guides; its borders do not
+    wrap, it runs three iterations, and its window-membership decisions are
+    taken in FP32 (see the NC section below);
   * iterations > 1 follow the rolling-guidance extension: iteration k filters
     the input's gradients with range weights from the gradients of u_{k-1}, and
     u_0 is the guidance image if one is given (optionally Gaussian-smoothed
@@ -49,6 +53,7 @@ __all__ = [
     "difference_otf", "ls_solve", "blfls_solve",
     "dense_difference_matrices", "dense_blfls_solve",
     "gaussian_blur", "smooth", "smooth_channel",
+    "nc_schedule", "nc_increments", "nc_box_pass", "nc_filter", "nc_filter_bruteforce",
 ]
 
 
@@ -159,6 +164,156 @@ def bilateral_filter_at(p, q, sigma_s, sigma_r, radius, rows, cols):
 
 
 # ---------------------------------------------------------------------------
+# Normalized-convolution filter of the domain transform (Section III-D: NC-LS
+# embeds it in place of the BLF; its definition is Gastal and Oliveira,
+# "Domain Transform for Edge-Aware Image and Video Processing", 2011)
+# ---------------------------------------------------------------------------
+#
+# Along a row, the domain transform maps pixel j to ct(j) = sum_{t <= j} d(t)
+# with increments d(t) = 1 + (sigma_s / sigma_r) |q(t) - q(t-1)|, q the guide
+# field; the NC filter replaces each value by the mean of the values whose
+# transformed coordinate lies within r of its own (a box in the transformed
+# domain), and iterates horizontal then vertical passes with shrinking boxes.
+# Readings (listed in the design notes): the filtered signal is the gradient
+# field and the guide is the field itself or the guide image's field of the
+# same axis (as for the BLF); windows stop at the image borders (the filter
+# is defined on a finite signal; only the solve is circular); three
+# iterations.  Window membership is an integer decision taken from floating
+# point, so it is computed in FP32 with the increments accumulated outward
+# from the centre pixel, as the GPU kernel does; the averages are FP64.
+
+def nc_schedule(sigma_s: float, n_iter: int = 3):
+    """Box radii of the n_iter passes: sigma_k = sigma_s sqrt(3) 2^(n-k) / sqrt(4^n - 1)
+    (the iterated boxes' variances sum to sigma_s^2) and r_k = sqrt(3) sigma_k (a box of
+    half-width r has variance r^2 / 3)."""
+    n = int(n_iter)
+    out = []
+    for k in range(1, n + 1):
+        sk = float(sigma_s) * math.sqrt(3.0) * 2.0 ** (n - k) / math.sqrt(4.0 ** n - 1.0)
+        out.append(math.sqrt(3.0) * sk)
+    return out
+
+
+def nc_increments(q: np.ndarray, a: np.float32, inv_span=None):
+    """FP32 domain-transform increments of the guide field q: dh[i, j] = 1 + a |q[i, j] - q[i, j-1]|
+    (column 0 unused) and dv[i, j] = 1 + a |q[i, j] - q[i-1, j]| (row 0 unused); with inv_span the
+    term is (a |dq|) * inv_span (normalised fields).  Products and sums are rounded to FP32 one
+    operation at a time."""
+    q32 = np.asarray(q, dtype=np.float64).astype(np.float32)
+    a = np.float32(a)
+    def inc(diff):
+        t = np.abs(diff).astype(np.float32)
+        t = (a * t).astype(np.float32)
+        if inv_span is not None:
+            t = (t * np.float32(inv_span)).astype(np.float32)
+        return (np.float32(1.0) + t).astype(np.float32)
+    dh = np.ones_like(q32)
+    dv = np.ones_like(q32)
+    dh[:, 1:] = inc(q32[:, 1:] - q32[:, :-1])
+    dv[1:, :] = inc(q32[1:, :] - q32[:-1, :])
+    return dh, dv
+
+
+def nc_box_pass(F: np.ndarray, d: np.ndarray, r: float, axis: int) -> np.ndarray:
+    """One transformed-domain box pass along `axis` (1: rows, 0: columns).  The output at j
+    is the mean of F over the m on the same line with transformed distance
+    dist(j, m) <= r, dist being the FP32 sum of the increments d between j and m taken
+    outward from j; no wrap at the borders."""
+    F = np.asarray(F, dtype=np.float64)
+    if axis == 0:
+        return nc_box_pass(F.T, d.T, r, 1).T
+    r32 = np.float32(r)
+    Hn, Wn = F.shape
+    num = F.copy()
+    cnt = np.ones_like(F)
+    R = int(math.floor(float(r32))) + 1
+    # to the right: m = j + k, distance accumulates d[j+1], ..., d[j+k]
+    dist = np.zeros((Hn, Wn), dtype=np.float32)
+    live = np.ones((Hn, Wn), dtype=bool)
+    for k in range(1, min(R, Wn - 1) + 1):
+        inc = np.full((Hn, Wn), np.float32(np.inf), dtype=np.float32)
+        inc[:, :Wn - k] = d[:, k:]
+        dist = (dist + inc).astype(np.float32)
+        live &= dist <= r32
+        vals = np.zeros_like(F)
+        vals[:, :Wn - k] = F[:, k:]
+        num += np.where(live, vals, 0.0)
+        cnt += live
+    # to the left: m = j - k, distance accumulates d[j], d[j-1], ..., d[j-k+1]
+    dist = np.zeros((Hn, Wn), dtype=np.float32)
+    live = np.ones((Hn, Wn), dtype=bool)
+    for k in range(1, min(R, Wn - 1) + 1):
+        inc = np.full((Hn, Wn), np.float32(np.inf), dtype=np.float32)
+        inc[:, k:] = d[:, 1:Wn - k + 1]
+        dist = (dist + inc).astype(np.float32)
+        live &= dist <= r32
+        vals = np.zeros_like(F)
+        vals[:, k:] = F[:, :Wn - k]
+        num += np.where(live, vals, 0.0)
+        cnt += live
+    return num / cnt
+
+
+def nc_filter(p: np.ndarray, q, sigma_s: float, sigma_r: float, n_iter: int = 3, inv_span=None) -> np.ndarray:
+    """NC filter of field p guided by q (None: p itself): n_iter rounds of a horizontal then a
+    vertical box pass with radii nc_schedule(sigma_s, n_iter); the increments come from the
+    guide once (the domain transform is not recomputed between passes).  sigma_r = inf
+    switches the range term off (increments 1: plain iterated box filters)."""
+    p = np.asarray(p, dtype=np.float64)
+    qq = p if q is None else np.asarray(q, dtype=np.float64)
+    a = np.float32(0.0) if math.isinf(sigma_r) else np.float32(float(sigma_s) / float(sigma_r))
+    dh, dv = nc_increments(qq, a, inv_span)
+    F = p
+    for r in nc_schedule(sigma_s, n_iter):
+        F = nc_box_pass(F, dh, r, 1)
+        F = nc_box_pass(F, dv, r, 0)
+    return F
+
+
+def nc_filter_bruteforce(p, q, sigma_s, sigma_r, n_iter=3):
+    """Pixel-by-pixel loops over the same definition (tiny inputs only): for each pixel walk
+    outward along the line, adding FP32 increments, and average the values reached within r."""
+    p = np.asarray(p, dtype=np.float64)
+    qq = p if q is None else np.asarray(q, dtype=np.float64)
+    Hn, Wn = p.shape
+    q32 = qq.astype(np.float32)
+    a = np.float32(0.0) if math.isinf(sigma_r) else np.float32(float(sigma_s) / float(sigma_r))
+
+    def incr(x1, x0):
+        return np.float32(np.float32(1.0) + np.float32(a * np.float32(abs(np.float32(x1 - x0)))))
+
+    def line_pass(vals, guide, r32):
+        n = len(vals)
+        out = [0.0] * n
+        for j in range(n):
+            tot, cnt = vals[j], 1
+            dist = np.float32(0.0)
+            for m in range(j + 1, n):
+                dist = np.float32(dist + incr(guide[m], guide[m - 1]))
+                if not dist <= r32:
+                    break
+                tot += vals[m]
+                cnt += 1
+            dist = np.float32(0.0)
+            for m in range(j - 1, -1, -1):
+                dist = np.float32(dist + incr(guide[m + 1], guide[m]))
+                if not dist <= r32:
+                    break
+                tot += vals[m]
+                cnt += 1
+            out[j] = tot / cnt
+        return out
+
+    F = [list(row) for row in p]
+    for r in nc_schedule(sigma_s, n_iter):
+        r32 = np.float32(r)
+        F = [line_pass(F[i], list(q32[i]), r32) for i in range(Hn)]
+        cols = [line_pass([F[i][j] for i in range(Hn)], [q32[i][j] for i in range(Hn)], r32) for j in range(Wn)]
+        F = [[cols[j][i] for j in range(Wn)] for i in range(Hn)]
+    return np.array(F, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
 # Fourier-domain least-squares solves, Eq. (6) and Eq. (8)
 # ---------------------------------------------------------------------------
 
@@ -257,7 +412,21 @@ def _normalise_unit(v: np.ndarray):
     return v - lo, lo, 1.0
 
 
-def _filter_field(p, q, sigma_s, sigma_r, radius, normalize):
+def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iterations=3):
+    if filt == "nc":
+        # NC-LS (Section III-D): the NC filter in place of the BLF.  With the
+        # normalisation of the experiments section the guide field g is mapped
+        # to [0, 1], which scales its differences by 1/span(g): the increments
+        # take that factor, computed in FP32 from the raw field (min, max and
+        # the reciprocal of max - min each rounded once); the filtered field's
+        # own affine map commutes with the averaging.
+        inv = None
+        if normalize and math.isfinite(sigma_r):
+            g32 = np.asarray(p if q is None else q, dtype=np.float64).astype(np.float32)
+            span32 = np.float32(np.float32(g32.max()) - np.float32(g32.min()))
+            if span32 > 0:
+                inv = np.float32(np.float32(1.0) / span32)
+        return nc_filter(p, q, sigma_s, sigma_r, nc_iterations, inv)
     if not normalize:
         return bilateral_filter(p, q, sigma_s, sigma_r, radius)
     # experiments section: fields taken to [0, 1], filtered, then mapped back
@@ -267,21 +436,23 @@ def _filter_field(p, q, sigma_s, sigma_r, radius, normalize):
 
 
 def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None,
-                   normalize=False, sigma_guide=0.0, return_fields=False):
+                   normalize=False, sigma_guide=0.0, return_fields=False, filter="blf", nc_iterations=3):
     """BLF-LS on one channel (Section III-A two-step procedure, Section III-D extensions).
 
-    Step 1 filters p_x, p_y with Eq. (1); step 2 solves Eq. (8).  ``guide`` switches
-    to joint filtering; ``iterations`` > 1 is rolling guidance.
+    Step 1 filters p_x, p_y with Eq. (1) (``filter="nc"``: the NC filter of the domain
+    transform, NC-LS); step 2 solves Eq. (8).  ``guide`` switches to joint filtering;
+    ``iterations`` > 1 is rolling guidance.
     """
     f = np.asarray(f, dtype=np.float64)
     r = default_radius(sigma_s) if radius is None or radius < 0 else int(radius)
+    nc = filter == "nc"
     lo, span = 0.0, 1.0
-    if normalize:
+    if normalize and not nc:
         f, lo, span = _normalise_unit(f)
     px, py = grad_x(f), grad_y(f)
     if guide is not None:
         h = np.asarray(guide, dtype=np.float64)
-        if normalize:
+        if normalize and not nc:
             h = _normalise_unit(h)[0]
         if sigma_guide > 0:
             h = gaussian_blur(h, sigma_guide)
@@ -297,8 +468,8 @@ def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None
             qx = qy = None
         else:
             qx, qy = grad_x(prev), grad_y(prev)
-        gx = _filter_field(px, qx, sigma_s, sigma_r, r, normalize)
-        gy = _filter_field(py, qy, sigma_s, sigma_r, r, normalize)
+        gx = _filter_field(px, qx, sigma_s, sigma_r, r, normalize, filter, nc_iterations)
+        gy = _filter_field(py, qy, sigma_s, sigma_r, r, normalize, filter, nc_iterations)
         u = blfls_solve(f, gx, gy, lam)
         prev = u
     out = u * span + lo
@@ -308,16 +479,17 @@ def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None
 
 
 def smooth(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None, normalize=False,
-           sigma_guide=0.0):
-    """BLF-LS on a (H, W) or (C, H, W) image; channels are independent."""
+           sigma_guide=0.0, filter="blf", nc_iterations=3):
+    """BLF-LS (or NC-LS with ``filter="nc"``) on a (H, W) or (C, H, W) image; channels are
+    independent."""
     f = np.asarray(f, dtype=np.float64)
     if f.ndim == 2:
         return smooth_channel(f, lam, sigma_s, sigma_r, radius, iterations, guide, normalize,
-                              sigma_guide)
+                              sigma_guide, filter=filter, nc_iterations=nc_iterations)
     g = None if guide is None else np.asarray(guide, dtype=np.float64)
     outs = []
     for c in range(f.shape[0]):
         gc = None if g is None else (g[c] if g.ndim == 3 else g)
         outs.append(smooth_channel(f[c], lam, sigma_s, sigma_r, radius, iterations, gc,
-                                   normalize, sigma_guide))
+                                   normalize, sigma_guide, filter=filter, nc_iterations=nc_iterations))
     return np.stack(outs)

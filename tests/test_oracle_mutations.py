@@ -1,7 +1,8 @@
 """Plant plausible mistakes in the oracle (CPU only) and check that a pin fails.
 
 Each mutation swaps one oracle function for a subtly wrong version: a backward
-difference, a missing conjugate, a wrong range-kernel sign, a dropped term.
+difference, a missing conjugate, a wrong range-kernel sign, a dropped term, an
+NC filter with a wrong box schedule, wrapping windows or wrong increments.
 The pins of ``test_oracle.py`` must reject every one of them.
 """
 import math
@@ -12,6 +13,7 @@ import pytest
 import oracle
 from oracle import blfls_oracle as ob
 import tests.test_oracle as pins
+import tests.test_oracle_nc as nc_pins
 
 
 def _patch(monkeypatch, name, fn):
@@ -67,6 +69,43 @@ def _bad_otf_transposed(H, W):
     return F1, Fy, Fx
 
 
+def _bad_nc_schedule_flat(sigma_s, n_iter=3):
+    # every pass with the widest box
+    return [math.sqrt(3.0) * sigma_s] * int(n_iter)
+
+
+def _bad_nc_schedule_sigma(sigma_s, n_iter=3):
+    # box half-width sigma_k instead of sqrt(3) sigma_k
+    n = int(n_iter)
+    return [sigma_s * math.sqrt(3.0) * 2.0 ** (n - k) / math.sqrt(4.0 ** n - 1.0) for k in range(1, n + 1)]
+
+
+def _bad_nc_box_wrap(F, d, r, axis):
+    # windows wrap around the borders
+    F = np.asarray(F, dtype=np.float64)
+    if axis == 0:
+        return _bad_nc_box_wrap(F.T, d.T, r, 1).T
+    r32 = np.float32(r)
+    num, cnt = F.copy(), np.ones_like(F)
+    for sgn in (1, -1):
+        dist = np.zeros(F.shape, dtype=np.float32)
+        live = np.ones(F.shape, dtype=bool)
+        for k in range(1, int(r32) + 2):
+            inc = np.roll(d, -k if sgn > 0 else k - 1, axis=1)
+            dist = (dist + inc).astype(np.float32)
+            live &= dist <= r32
+            num += np.where(live, np.roll(F, -sgn * k, axis=1), 0.0)
+            cnt += live
+    return num / cnt
+
+
+def _bad_nc_increments(q, a, inv_span=None):
+    # increments from the guide values instead of their differences
+    q32 = np.asarray(q, dtype=np.float64).astype(np.float32)
+    d = (np.float32(1.0) + (np.float32(a) * np.abs(q32)).astype(np.float32)).astype(np.float32)
+    return d, d.copy()
+
+
 MUTATIONS = {
     "backward_grad_x": ("grad_x", lambda f: f - np.roll(f, 1, axis=-1)),
     "grad_y_along_x": ("grad_y", lambda f: np.roll(f, -1, axis=-1) - f),
@@ -74,6 +113,10 @@ MUTATIONS = {
     "spatial_sigma": ("bilateral_filter", _bad_blf_sigma),
     "solve_no_conj": ("blfls_solve", _bad_solve_noconj),
     "solve_drops_y_term": ("blfls_solve", _bad_solve_dropped_y),
+    "nc_flat_schedule": ("nc_schedule", _bad_nc_schedule_flat),
+    "nc_box_sigma_not_sqrt3": ("nc_schedule", _bad_nc_schedule_sigma),
+    "nc_windows_wrap": ("nc_box_pass", _bad_nc_box_wrap),
+    "nc_increments_from_values": ("nc_increments", _bad_nc_increments),
 }
 
 PIN_SUITE = [
@@ -86,6 +129,10 @@ PIN_SUITE = [
     lambda: pins.test_P7_sigma_r_infinite_closed_form(32, 40, 1.5, 5),
     pins.test_P11_symmetries,
     pins.test_normalisation_is_a_range_rescale,
+    lambda: nc_pins.test_nc_matches_pixel_loops(5, 7, 2.0, 0.3, 3),
+    lambda: nc_pins.test_nc_schedule_variances_sum_to_sigma_s_squared(3),
+    nc_pins.test_nc_without_range_term_is_iterated_box_filtering,
+    nc_pins.test_nc_keeps_constants_and_clean_steps,
 ]
 
 
