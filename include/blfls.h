@@ -66,6 +66,20 @@ typedef enum {
  * field's (max - min), which is how it is computed. */
 #define BLFLS_F_NORMALIZE 0x1u
 
+/* The edge-preserving filter of step 1 (applied to each gradient field). */
+typedef enum {
+  BLFLS_FILTER_BLF = 0,  /* the bilateral filter of Eq. (1): BLF-LS */
+  BLFLS_FILTER_NC = 1    /* the normalized-convolution filter of the domain transform
+                            (Gastal and Oliveira 2011) in its place: NC-LS (Section III-D).
+                            Along a row (then a column) the transform advances by
+                            1 + (sigma_s / sigma_r) |q(t) - q(t-1)| per pixel, q the range
+                            source's gradient field of the same axis; each pass replaces a
+                            value by the mean of the values within r_k of it in transformed
+                            distance, r_k = 3 sigma_s 2^(N-k) / sqrt(4^N - 1) for round
+                            k = 1..N, windows stopping at the image borders.  Window
+                            membership is decided in FP32. */
+} blfls_filter;
+
 /* Parameters of Eq. (1) and Eq. (7). */
 typedef struct {
   float lambda;      /* weight of the gradient term of Eq. (7); >= 0, finite.
@@ -82,6 +96,11 @@ typedef struct {
   float sigma_guide; /* >= 0.  > 0 smooths the initial range source (the guidance image,
                         or f itself) with a circular Gaussian of this standard deviation,
                         as the rolling-guidance extension does (Section III-D). 0 = off. */
+  int32_t filter;    /* blfls_filter.  BLFLS_FILTER_NC ignores radius; its first box
+                        radius r_1 must be at most BLFLS_MAX_RADIUS pixels
+                        (sigma_s <= 21 for N = 3), else BLFLS_E_INVALID. */
+  int32_t filter_iterations; /* NC rounds N of a horizontal and a vertical box pass,
+                        1..8; 0 selects 3.  Must be 0 for the BLF. */
 } blfls_params;
 
 #define BLFLS_MAX_RADIUS 32

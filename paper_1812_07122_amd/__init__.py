@@ -51,6 +51,8 @@ class Params(ctypes.Structure):
         ("iterations", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
         ("sigma_guide", ctypes.c_float),
+        ("filter", ctypes.c_int32),
+        ("filter_iterations", ctypes.c_int32),
     ]
 
 
@@ -141,10 +143,18 @@ def _check(status: int):
         raise BlflsError(status, msg.decode() if msg else "")
 
 
+FILTERS = {"blf": 0, "nc": 1}
+
+
 def make_params(lam: float, sigma_s: float, sigma_r: float, radius: int = -1, iterations: int = 1,
-                normalize: bool = False, sigma_guide: float = 0.0) -> Params:
+                normalize: bool = False, sigma_guide: float = 0.0, filter: str = "blf",
+                filter_iterations: int = 0) -> Params:
+    """``filter``: "blf" (BLF-LS) or "nc" (NC-LS: the domain transform's normalized
+    convolution in place of the BLF; ``filter_iterations`` rounds, 0 = 3)."""
+    if filter not in FILTERS:
+        raise ValueError(f"filter must be one of {sorted(FILTERS)}")
     return Params(float(lam), float(sigma_s), float(sigma_r), int(radius), int(iterations),
-                  F_NORMALIZE if normalize else 0, float(sigma_guide))
+                  F_NORMALIZE if normalize else 0, float(sigma_guide), FILTERS[filter], int(filter_iterations))
 
 
 def _stream_handle(stream) -> int:
@@ -186,7 +196,8 @@ class Plan:
         self.workspace_ptr = (base + 255) // 256 * 256
 
     def smooth(self, f, lam: float, sigma_s: float, sigma_r: float, radius: int = -1, iterations: int = 1,
-               guide=None, normalize: bool = False, sigma_guide: float = 0.0, out=None, stream=None):
+               guide=None, normalize: bool = False, sigma_guide: float = 0.0, out=None, stream=None,
+               filter: str = "blf", filter_iterations: int = 0):
         import torch
         shape = (self.C, self.H, self.W)
         f3 = f.reshape(shape) if f.dim() == 2 else f
@@ -200,7 +211,8 @@ class Plan:
             if tuple(g3.shape) != shape or g3.dtype != torch.float32 or not g3.is_contiguous():
                 raise ValueError(f"guide must be a contiguous float32 CUDA tensor of shape {shape}")
         u = torch.empty_like(f3) if out is None else out
-        prm = make_params(lam, sigma_s, sigma_r, radius, iterations, normalize, sigma_guide)
+        prm = make_params(lam, sigma_s, sigma_r, radius, iterations, normalize, sigma_guide, filter,
+                          filter_iterations)
         _check(lib().blfls_smooth(self._handle, ctypes.byref(prm), ctypes.c_void_p(f3.data_ptr()),
                                   ctypes.c_void_p(g3.data_ptr() if g3 is not None else 0),
                                   ctypes.c_void_p(u.data_ptr()), self.W, ctypes.c_void_p(self.workspace_ptr),
@@ -224,11 +236,12 @@ _plan_cache: dict = {}
 
 def smooth(f, lam: float = 1024.0, sigma_s: float = 3.0, sigma_r: float = 0.1, radius: int = -1,
            iterations: int = 1, guide=None, normalize: bool = False, sigma_guide: float = 0.0,
-           precision="fp32", out=None, stream=None):
+           precision="fp32", out=None, stream=None, filter: str = "blf", filter_iterations: int = 0):
     """BLF-LS of a float32 CUDA image of shape (H, W) or (C, H, W); returns u (same shape).
 
     lam is lambda of Eq. (7) (the paper's default is 1024), sigma_s / sigma_r the
     spatial and range sigmas of Eq. (1), radius -1 means ceil(3 sigma_s).
+    filter="nc" runs NC-LS (Section III-D) with filter_iterations rounds (0 = 3).
     """
     C, H, W = (1, *f.shape) if f.dim() == 2 else tuple(f.shape)
     key = (C, H, W, _PRECISIONS[precision], f.device.index)
@@ -236,7 +249,8 @@ def smooth(f, lam: float = 1024.0, sigma_s: float = 3.0, sigma_r: float = 0.1, r
     if plan is None:
         plan = Plan(H, W, C, precision, device=f.device)
         _plan_cache[key] = plan
-    return plan.smooth(f, lam, sigma_s, sigma_r, radius, iterations, guide, normalize, sigma_guide, out, stream)
+    return plan.smooth(f, lam, sigma_s, sigma_r, radius, iterations, guide, normalize, sigma_guide, out, stream,
+                       filter, filter_iterations)
 
 
 class Server:
@@ -262,7 +276,8 @@ class Server:
         return self._stream
 
     def submit(self, f, lam: float, sigma_s: float, sigma_r: float, radius: int = -1, iterations: int = 1,
-               guide=None, normalize: bool = False, sigma_guide: float = 0.0, out=None):
+               guide=None, normalize: bool = False, sigma_guide: float = 0.0, out=None, filter: str = "blf",
+               filter_iterations: int = 0):
         """Queue one image; returns (ticket, u).  u is valid once poll(ticket) reports DONE.
 
         Raises BlflsError with status E_AGAIN when the queue is full.
@@ -271,7 +286,8 @@ class Server:
         C, H, W = (1, *f.shape) if f.dim() == 2 else tuple(f.shape)
         u = torch.empty_like(f) if out is None else out
         req = Request(H, W, C, f.data_ptr(), guide.data_ptr() if guide is not None else 0, u.data_ptr(), W,
-                      make_params(lam, sigma_s, sigma_r, radius, iterations, normalize, sigma_guide))
+                      make_params(lam, sigma_s, sigma_r, radius, iterations, normalize, sigma_guide, filter,
+                                  filter_iterations))
         ticket = ctypes.c_uint64()
         _check(lib().blfls_submit(self._handle, ctypes.byref(req), ctypes.byref(ticket)))
         self._keep[ticket.value] = (f, guide, u)

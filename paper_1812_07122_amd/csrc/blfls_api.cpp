@@ -100,6 +100,17 @@ int floor_pow2(int v) {
 }
 }  // namespace
 
+// Box radius of NC round k of n (domain transform, iterated boxes):
+// 3 sigma_s 2^(n-k) / sqrt(4^n - 1), formed in FP64 from the FP32 sigma_s.
+double nc_box_radius(float sigma_s, int n, int k) {
+  const double sk = static_cast<double>(sigma_s) * std::sqrt(3.0) * std::ldexp(1.0, n - k) /
+                    std::sqrt(std::ldexp(1.0, 2 * n) - 1.0);
+  return std::sqrt(3.0) * sk;
+}
+
+// Farthest pixel offset an NC box of FP32 radius r can reach (increments are >= 1).
+int nc_pixel_radius(float r) { return static_cast<int>(std::floor(static_cast<double>(r))); }
+
 blfls_status set_error(blfls_status st, const std::string& msg) {
   g_last_error = msg;
   return st;
@@ -129,10 +140,23 @@ blfls_status check_params(const blfls_params* p, int* radius_out) {
   if (p->iterations < 1) return set_error(BLFLS_E_INVALID, "iterations must be >= 1");
   if (!std::isfinite(p->sigma_guide) || p->sigma_guide < 0.0f) return set_error(BLFLS_E_INVALID, "sigma_guide must be finite and >= 0");
   if (p->flags & ~BLFLS_F_NORMALIZE) return set_error(BLFLS_E_INVALID, "unknown flag bits");
+  if (p->filter != BLFLS_FILTER_BLF && p->filter != BLFLS_FILTER_NC)
+    return set_error(BLFLS_E_INVALID, "unknown filter");
+  if (p->filter_iterations < 0 || p->filter_iterations > 8)
+    return set_error(BLFLS_E_INVALID, "filter_iterations must be in [0, 8]");
+  if (p->filter == BLFLS_FILTER_BLF && p->filter_iterations != 0)
+    return set_error(BLFLS_E_INVALID, "filter_iterations applies to the NC filter only");
   int r = p->radius;
   if (r < -1) return set_error(BLFLS_E_INVALID, "radius must be >= 0 or -1");
-  if (r == -1) r = static_cast<int>(std::ceil(3.0 * static_cast<double>(p->sigma_s)));
-  if (r > BLFLS_MAX_RADIUS) return set_error(BLFLS_E_INVALID, "radius exceeds BLFLS_MAX_RADIUS (32)");
+  if (p->filter == BLFLS_FILTER_NC) {
+    const int n = p->filter_iterations ? p->filter_iterations : 3;
+    if (nc_pixel_radius(static_cast<float>(nc_box_radius(p->sigma_s, n, 1))) > kNcMaxR)
+      return set_error(BLFLS_E_INVALID, "sigma_s too large for the NC filter (first box radius above 32 pixels)");
+    r = 0;
+  } else {
+    if (r == -1) r = static_cast<int>(std::ceil(3.0 * static_cast<double>(p->sigma_s)));
+    if (r > BLFLS_MAX_RADIUS) return set_error(BLFLS_E_INVALID, "radius exceeds BLFLS_MAX_RADIUS (32)");
+  }
   if (p->sigma_guide > 0.0f && static_cast<int>(std::ceil(3.0 * static_cast<double>(p->sigma_guide))) > kMaxR)
     return set_error(BLFLS_E_INVALID, "sigma_guide too large (radius ceil(3 sigma_guide) must be <= 32)");
   *radius_out = r;
@@ -146,7 +170,10 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
     return set_error(BLFLS_E_INVALID, "unknown precision");
   static std::once_flag init_once;
   static hipError_t init_err = hipSuccess;
-  std::call_once(init_once, [] { init_err = fft_init_kernels(); });
+  std::call_once(init_once, [] {
+    init_err = fft_init_kernels();
+    if (init_err == hipSuccess) init_err = nc_init_kernels();
+  });
   if (init_err != hipSuccess) return hip_error(init_err, "FFT kernel attributes");
   auto* p = new (std::nothrow) blfls_plan_s();
   if (!p) return set_error(BLFLS_E_NOMEM, "host allocation failed");
@@ -237,6 +264,9 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   p->off_spec = w; w = align_up(w + static_cast<size_t>(C) * (M + 1) * H * sizeof(float2), 256);
   p->off_gauss = w; w = align_up(w + C * plane * sizeof(float), 256);
   p->off_tmp = w; w = align_up(w + C * plane * sizeof(float), 256);
+  // NC filter passes: ping buffers of both fields here; the pong buffers
+  // overlay the spectrum (x) and the Gaussian scratch (y), idle while filtering
+  p->off_nc = w; w = align_up(w + 2 * C * plane * sizeof(float), 256);
   p->ws_bytes = w;
   *out = p;
   return BLFLS_OK;
@@ -291,6 +321,14 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
   out->mm_next.assign(C, AuxPlane{});
   out->gauss.assign(C, AuxPlane{});
   out->fft.assign(C, FftPlane{});
+  out->nc_first.assign(C, NcPlane{});
+  out->nc_next.assign(C, NcPlane{});
+  out->filter = prm.filter;
+  out->nc_rounds = prm.filter == BLFLS_FILTER_NC ? (prm.filter_iterations ? prm.filter_iterations : 3) : 0;
+  for (int k = 1; k <= out->nc_rounds; ++k) {
+    out->nc_r[k - 1] = static_cast<float>(nc_box_radius(prm.sigma_s, out->nc_rounds, k));
+    out->nc_R[k - 1] = nc_pixel_radius(out->nc_r[k - 1]);
+  }
   float* gauss_base = reinterpret_cast<float*>(wsb + plan->off_gauss);
   float* tmp_base = reinterpret_cast<float*>(wsb + plan->off_tmp);
   float* partial_base = reinterpret_cast<float*>(wsb + plan->off_partial);
@@ -344,6 +382,28 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
         B.g = uc;
       }
     }
+    for (int it = 0; it < 2; ++it) {
+      const BlfPlane& B = it == 0 ? out->blf_first[ch] : out->blf_next[ch];
+      NcPlane& N = it == 0 ? out->nc_first[ch] : out->nc_next[ch];
+      N.f = fc;
+      N.g = B.g;
+      N.pitch = pitch;
+      N.gpitch = B.gpitch;
+      float* ping = reinterpret_cast<float*>(wsb + plan->off_nc);
+      N.buf[0][0] = ping + (0 * C + ch) * plane;
+      N.buf[0][1] = ping + (1 * C + ch) * plane;
+      N.buf[1][0] = reinterpret_cast<float*>(wsb + plan->off_spec) + ch * plane;
+      N.buf[1][1] = tmp_base + ch * plane;
+      N.rx = rx;
+      N.ry = ry;
+      N.minmax = B.minmax;
+      N.H = H; N.W = W;
+      N.a = range_on ? static_cast<float>(static_cast<double>(prm.sigma_s) / static_cast<double>(prm.sigma_r)) : 0.0f;
+      N.rcount = nc_row_items(H, W);
+      N.rbegin = ch * N.rcount;
+      N.ccount = nc_col_items(H, W);
+      N.cbegin = ch * N.ccount;
+    }
     FftPlane& F = out->fft[ch];
     F.rx = rx; F.ry = ry;
     F.spec = reinterpret_cast<float2*>(wsb + plan->off_spec) + static_cast<size_t>(ch) * (M + 1) * H;
@@ -380,7 +440,17 @@ hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, cons
       e = launch_minmax(first ? dev.mm_first : dev.mm_next, C, s);
       if (e != hipSuccess) return e;
     }
-    {
+    if (rd.filter == BLFLS_FILTER_NC) {
+      StageTimer t(BLFLS_STAGE_BLF, s);
+      const NcPlane* np = first ? dev.nc_first : dev.nc_next;
+      const int passes = 2 * rd.nc_rounds;
+      for (int pass = 0; pass < passes; ++pass) {
+        const int k = pass / 2;
+        const int n_items = (pass & 1) ? C * nc_col_items(plan->H, plan->W) : C * nc_row_items(plan->H, plan->W);
+        e = launch_nc_pass(np, C, n_items, pass, passes, rd.nc_r[k], rd.nc_R[k], ft, s);
+        if (e != hipSuccess) return e;
+      }
+    } else {
       StageTimer t(BLFLS_STAGE_BLF, s);
       e = launch_blf(rd.R, first ? dev.blf_first : dev.blf_next, C, items, first ? rd.joint_first : true, ft, s);
       if (e != hipSuccess) return e;
@@ -487,6 +557,11 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   const size_t o_m2 = place(rd.mm_next.data(), C * sizeof(AuxPlane));
   const size_t o_g = place(rd.gauss.data(), C * sizeof(AuxPlane));
   const size_t o_f = place(rd.fft.data(), C * sizeof(FftPlane));
+  size_t o_n1 = 0, o_n2 = 0;
+  if (rd.filter == BLFLS_FILTER_NC) {
+    o_n1 = place(rd.nc_first.data(), C * sizeof(NcPlane));
+    o_n2 = place(rd.nc_next.data(), C * sizeof(NcPlane));
+  }
   if (blob.size() > kDescBytes) return set_error(BLFLS_E_INVALID, "descriptor area overflow");
   hipStream_t s = static_cast<hipStream_t>(stream);
   {
@@ -501,6 +576,10 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   dd.mm_next = reinterpret_cast<const AuxPlane*>(dbase + o_m2);
   dd.gauss = reinterpret_cast<const AuxPlane*>(dbase + o_g);
   dd.fft = reinterpret_cast<const FftPlane*>(dbase + o_f);
+  if (rd.filter == BLFLS_FILTER_NC) {
+    dd.nc_first = reinterpret_cast<const NcPlane*>(dbase + o_n1);
+    dd.nc_next = reinterpret_cast<const NcPlane*>(dbase + o_n2);
+  }
   e = enqueue_request(plan, rd, dd, s);
   if (e != hipSuccess) return hip_error(e, "kernel launch");
   return BLFLS_OK;

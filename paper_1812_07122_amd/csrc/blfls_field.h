@@ -1,0 +1,43 @@
+// Device helpers shared by the kernels that write the residual fields.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "blfls_internal.h"
+
+namespace blfls {
+
+// Store v as element idx of a packed field of type ft (FP32, BF16 or FP16,
+// rounded to nearest even).
+__device__ __forceinline__ void store_field(void* base, int64_t idx, float v, int ft) {
+  if (ft == kF32) {
+    static_cast<float*>(base)[idx] = v;
+  } else if (ft == kBF16) {
+    uint32_t b = __float_as_uint(v);
+    b += 0x7FFFu + ((b >> 16) & 1u);  // round to nearest even (values are finite)
+    static_cast<uint16_t*>(base)[idx] = static_cast<uint16_t>(b >> 16);
+  } else {
+    static_cast<_Float16*>(base)[idx] = static_cast<_Float16>(v);  // round to nearest even
+  }
+}
+
+// Reduce the minmax partials of one field: returns max - min of the range source.
+__device__ inline float field_span(const float* partial, int field) {
+  __shared__ float red[2];
+  if (threadIdx.x < 64) {
+    const int i = threadIdx.x;
+    float lo = partial[i * 4 + field * 2 + 0];
+    float hi = partial[i * 4 + field * 2 + 1];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, off));
+      hi = fmaxf(hi, __shfl_xor(hi, off));
+    }
+    if (i == 0) { red[0] = lo; red[1] = hi; }
+  }
+  __syncthreads();
+  return red[1] - red[0];
+}
+
+}  // namespace blfls

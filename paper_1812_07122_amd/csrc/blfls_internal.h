@@ -101,6 +101,27 @@ struct FftPlane {
   FastDiv rb_div;        // division by rb
 };
 
+// One channel plane for the NC filter passes (NC-LS, Section III-D): both
+// gradient fields of one channel.  Pass s of the 2N passes reads buf[s % 2]
+// (the first pass forms the gradients from f instead) and writes
+// buf[(s + 1) % 2]; the last pass writes the residual fields rx, ry.
+constexpr int kNcMaxR = 32;             // largest NC box radius in pixels
+struct NcPlane {
+  const float* f;        // image whose gradients are filtered, [H][pitch]
+  const float* g;        // range-source image (guide / previous output) or nullptr = f
+  int64_t pitch;         // elements per row of f
+  int64_t gpitch;        // elements per row of g
+  float* buf[2][2];      // [ping/pong][field] FP32 fields, packed [H][W]
+  void* rx;              // residual r_x = NC(p_x) - p_x, packed [H][W], field type
+  void* ry;
+  const float* minmax;   // range-source gradient extrema partials (normalise flag) or nullptr
+  int H, W;
+  float a;               // sigma_s / sigma_r rounded to FP32 (0: range term off)
+  int rbegin, rcount;    // items of the row passes: 2 fields x ceil(H/4) x ceil(W/64)
+  int cbegin, ccount;    // items of the column passes: 2 fields x ceil(H/64) x ceil(W/64)
+  int pad_;
+};
+
 // Minmax (normalise flag) and Gaussian-guide descriptors.
 struct AuxPlane {
   const float* src;      // range-source image [H][pitch]

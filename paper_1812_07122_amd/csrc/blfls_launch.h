@@ -36,6 +36,14 @@ hipError_t launch_fft_cols(const FftPlane* planes, int nplanes, int blocks, size
                            WorkHeader* work = nullptr);
 hipError_t launch_fft_rows_inv(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
                                hipStream_t s, WorkHeader* work = nullptr);
+// NC filter passes (NC-LS).  Items per plane of a row pass / a column pass;
+// pass s in [0, npasses) is a row pass when even, the last writes the
+// residual fields in field type.
+int nc_row_items(int H, int W);
+int nc_col_items(int H, int W);
+hipError_t nc_init_kernels();
+hipError_t launch_nc_pass(const NcPlane* planes, int nplanes, int items, int pass, int npasses, float r, int R,
+                          int field_type, hipStream_t s);
 hipError_t launch_minmax(const AuxPlane* planes, int nplanes, hipStream_t s, WorkHeader* work = nullptr,
                          int grid = 0);
 hipError_t launch_gauss(const AuxPlane* planes, int nplanes, int64_t max_pixels, hipStream_t s,

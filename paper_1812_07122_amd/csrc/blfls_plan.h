@@ -31,7 +31,7 @@ struct blfls_plan_s {
   int tiles_x = 0, tiles_y = 0;
   // workspace layout (bytes from the workspace base)
   size_t field_elem = 4;
-  size_t off_desc = 0, off_partial = 0, off_rx = 0, off_ry = 0, off_spec = 0, off_gauss = 0, off_tmp = 0;
+  size_t off_desc = 0, off_partial = 0, off_rx = 0, off_ry = 0, off_spec = 0, off_gauss = 0, off_tmp = 0, off_nc = 0;
   size_t ws_bytes = 0;
 };
 
@@ -44,6 +44,11 @@ blfls_status set_error(blfls_status st, const std::string& msg);
 blfls_status hip_error(hipError_t e, const char* where);
 
 FastDiv make_fastdiv(uint32_t d);
+
+// NC filter geometry: box radius of round k of n, and the farthest pixel a
+// box of FP32 radius r reaches.
+double nc_box_radius(float sigma_s, int n, int k);
+int nc_pixel_radius(float r);
 
 // Size and parameter validation shared by the ABI entry points.
 blfls_status check_shape(int H, int W, int C);
@@ -62,6 +67,12 @@ struct RequestDesc {
   std::vector<AuxPlane> mm_next;
   std::vector<AuxPlane> gauss;       // guide smoothing
   std::vector<FftPlane> fft;
+  std::vector<NcPlane> nc_first;     // NC-LS: the NC passes of iteration 1
+  std::vector<NcPlane> nc_next;      // and of iterations 2..n
+  int filter = BLFLS_FILTER_BLF;
+  int nc_rounds = 0;                 // NC rounds (a row and a column pass each)
+  float nc_r[8] = {};                // box radius of each round (FP32)
+  int nc_R[8] = {};                  // farthest pixel offset of each round
   bool joint_first = false;
   int R = 0;                         // kernel radius class
   int iterations = 1;
@@ -86,6 +97,8 @@ struct DeviceDesc {
   const AuxPlane* mm_next = nullptr;
   const AuxPlane* gauss = nullptr;
   const FftPlane* fft = nullptr;
+  const NcPlane* nc_first = nullptr;
+  const NcPlane* nc_next = nullptr;
 };
 hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, const DeviceDesc& dev,
                            hipStream_t s);

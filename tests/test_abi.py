@@ -76,3 +76,37 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(blfls, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         blfls.lib()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes mirrors have the header's sizes and field offsets (compiled with gcc)."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    import paper_1812_07122_amd as b
+    checks = {
+        "blfls_params": (b.Params, ["lambda", "sigma_s", "sigma_r", "radius", "iterations", "flags", "sigma_guide",
+                                    "filter", "filter_iterations"]),
+        "blfls_request": (b.Request, ["H", "W", "C", "f", "guide", "u", "pitch", "params"]),
+        "blfls_stats": (b.Stats, [n for n, _ in b.Stats._fields_]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "blfls.h"', "int main(void) {"]
+    for struct, (_, fields) in checks.items():
+        lines.append(f'  printf("{struct} %zu\\n", sizeof({struct}));')
+        for fld in fields:
+            lines.append(f'  printf("{struct}.{fld} %zu\\n", offsetof({struct}, {fld}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                                check=True).stdout.split("\n") if line)
+    for struct, (cls, fields) in checks.items():
+        assert int(out[struct]) == ctypes.sizeof(cls), struct
+        names = [n for n, _ in cls._fields_]
+        for fld, py in zip(fields, names):
+            assert int(out[f"{struct}.{fld}"]) == getattr(cls, py).offset, f"{struct}.{fld}"
