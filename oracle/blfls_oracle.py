@@ -261,10 +261,13 @@ def nc_filter(p: np.ndarray, q, sigma_s: float, sigma_r: float, n_iter: int = 3,
     switches the range term off (increments 1: plain iterated box filters)."""
     p = np.asarray(p, dtype=np.float64)
     qq = p if q is None else np.asarray(q, dtype=np.float64)
-    a = np.float32(0.0) if math.isinf(sigma_r) else np.float32(float(sigma_s) / float(sigma_r))
+    # the sigmas arrive as FP32 (the library's parameters); a and the radii are
+    # formed from them in FP64 and rounded once to FP32
+    s32 = float(np.float32(sigma_s))
+    a = np.float32(0.0) if math.isinf(sigma_r) else np.float32(s32 / float(np.float32(sigma_r)))
     dh, dv = nc_increments(qq, a, inv_span)
     F = p
-    for r in nc_schedule(sigma_s, n_iter):
+    for r in nc_schedule(s32, n_iter):
         F = nc_box_pass(F, dh, r, 1)
         F = nc_box_pass(F, dv, r, 0)
     return F
@@ -277,7 +280,8 @@ def nc_filter_bruteforce(p, q, sigma_s, sigma_r, n_iter=3):
     qq = p if q is None else np.asarray(q, dtype=np.float64)
     Hn, Wn = p.shape
     q32 = qq.astype(np.float32)
-    a = np.float32(0.0) if math.isinf(sigma_r) else np.float32(float(sigma_s) / float(sigma_r))
+    s32 = float(np.float32(sigma_s))
+    a = np.float32(0.0) if math.isinf(sigma_r) else np.float32(s32 / float(np.float32(sigma_r)))
 
     def incr(x1, x0):
         return np.float32(np.float32(1.0) + np.float32(a * np.float32(abs(np.float32(x1 - x0)))))
@@ -305,7 +309,7 @@ def nc_filter_bruteforce(p, q, sigma_s, sigma_r, n_iter=3):
         return out
 
     F = [list(row) for row in p]
-    for r in nc_schedule(sigma_s, n_iter):
+    for r in nc_schedule(s32, n_iter):
         r32 = np.float32(r)
         F = [line_pass(F[i], list(q32[i]), r32) for i in range(Hn)]
         cols = [line_pass([F[i][j] for i in range(Hn)], [q32[i][j] for i in range(Hn)], r32) for j in range(Wn)]
