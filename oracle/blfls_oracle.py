@@ -54,6 +54,7 @@ __all__ = [
     "dense_difference_matrices", "dense_blfls_solve",
     "gaussian_blur", "smooth", "smooth_channel",
     "nc_schedule", "nc_increments", "nc_box_pass", "nc_filter", "nc_filter_bruteforce",
+    "grid_cell", "grid_range", "grid_filter", "grid_filter_bruteforce",
 ]
 
 
@@ -318,6 +319,157 @@ def nc_filter_bruteforce(p, q, sigma_s, sigma_r, n_iter=3):
 
 
 # ---------------------------------------------------------------------------
+# Bilateral-grid approximation of Eq. (1) (Paris and Durand, "A Fast
+# Approximation of the Bilateral Filter using a Signal Processing Approach",
+# 2006: the fast BLF the paper's experiments use, Section III-B)
+# ---------------------------------------------------------------------------
+#
+# The filter is a 3-D linear convolution in (x, y, range) followed by a
+# division: values p and ones are splatted into a grid of cells s pixels wide
+# and one range cell deep, both grids are blurred with a Gaussian, and each
+# pixel reads num / den back by trilinear interpolation at its own
+# (x, y, q).  Readings (listed in the design notes):
+#   * spatial cell s = max(1, round(sigma_s)) pixels: pixel x lies in cell
+#     floor((x + floor(s/2)) / s) and is read back at x / s;
+#   * range cell 1 / inv from min(q): inv = 1 / sigma_r, lowered if needed so
+#     that at most GRID_ZMAX bins span [min q, max q]; a pixel's bin is the
+#     integer decision floor((q - min q) inv + 1/2), taken in FP32 one
+#     rounding per operation as the GPU kernel takes it; with the normalise
+#     flag inv is divided by the field's span first;
+#   * blur: Gaussian taps exp(-k^2 / (2 sigma^2)) for k in [-2, 2], sigma =
+#     sigma_s / s cells along x and y and sigma_r inv cells along the range;
+#     the range axis has two empty bins of padding at each end;
+#   * the image is periodic (as in the exact filter): the grid is built over
+#     the periodic extension, so every output sees the same neighbourhood of
+#     cells whatever its position.
+
+GRID_PAD = 2
+GRID_ZMAX = 32
+
+
+def grid_cell(sigma_s: float) -> int:
+    """Spatial cell size s = max(1, round(sigma_s)) from the FP32 sigma_s."""
+    return max(1, int(round(float(np.float32(sigma_s)))))
+
+
+def grid_range(q: np.ndarray, sigma_r: float, inv_span=None):
+    """FP32 range origin and scale of the guide field q: (qmin, inv, bins per pixel, bins in use)."""
+    q32 = np.asarray(q, dtype=np.float64).astype(np.float32)
+    qmin = np.float32(q32.min())
+    span = np.float32(np.float32(q32.max()) - qmin)
+    inv = np.float32(0.0) if math.isinf(sigma_r) else np.float32(1.0 / float(np.float32(sigma_r)))
+    if inv_span is not None:
+        inv = np.float32(inv * np.float32(inv_span))
+    if np.float32(span * inv) > np.float32(GRID_ZMAX - 1):
+        inv = np.float32(np.float32(GRID_ZMAX - 1) / span)
+    t = ((q32 - qmin).astype(np.float32) * inv).astype(np.float32)
+    z = np.floor((t + np.float32(0.5)).astype(np.float32)).astype(np.int64)
+    return float(qmin), inv, z, int(z.max()) + 1
+
+
+def _grid_taps(sigma_cells: float):
+    k = np.arange(-GRID_PAD, GRID_PAD + 1, dtype=np.float64)
+    if sigma_cells <= 0.0:
+        return (k == 0).astype(np.float64)
+    return np.exp(-(k * k) / (2.0 * sigma_cells * sigma_cells))
+
+
+def grid_filter(p: np.ndarray, q, sigma_s: float, sigma_r: float, inv_span=None) -> np.ndarray:
+    """Bilateral-grid approximation of Eq. (1) on field p with range values q (None: p)."""
+    p = np.asarray(p, dtype=np.float64)
+    qq = p if q is None else np.asarray(q, dtype=np.float64)
+    H, W = p.shape
+    s = grid_cell(sigma_s)
+    qmin, inv, zb, nz = grid_range(qq, sigma_r, inv_span)
+    sig_xy = float(np.float32(sigma_s)) / s
+    # the range Gaussian, sigma_r in the (normalised) guide's units, measured in cells
+    sig_z = 0.0 if math.isinf(sigma_r) else float(np.float32(sigma_r)) * float(inv)
+    if inv_span is not None and sig_z > 0.0:
+        sig_z /= float(inv_span)
+    # periodic extension by m pixels: enough for every cell within 3 of an output's cell
+    m = 4 * s + s // 2 + 1
+    ys = np.arange(-m, H + m)
+    xs = np.arange(-m, W + m)
+    cy = (ys + s // 2) // s
+    cx = (xs + s // 2) // s
+    oy, ox = cy.min(), cx.min()
+    gy, gx, gz = cy.max() - oy + 1, cx.max() - ox + 1, nz + 2 * GRID_PAD
+    num = np.zeros((gz, gy, gx))
+    den = np.zeros((gz, gy, gx))
+    Y, X = np.meshgrid(ys % H, xs % W, indexing="ij")
+    CY, CX = np.meshgrid(cy - oy, cx - ox, indexing="ij")
+    np.add.at(num, (zb[Y, X] + GRID_PAD, CY, CX), p[Y, X])
+    np.add.at(den, (zb[Y, X] + GRID_PAD, CY, CX), 1.0)
+    for axis, taps in ((2, _grid_taps(sig_xy)), (1, _grid_taps(sig_xy)), (0, _grid_taps(sig_z))):
+        for arr in (num, den):
+            out = np.zeros_like(arr)
+            n = arr.shape[axis]
+            for k, w in zip(range(-GRID_PAD, GRID_PAD + 1), taps):
+                src = [slice(None)] * 3
+                dst = [slice(None)] * 3
+                src[axis] = slice(max(0, k), n + min(0, k))
+                dst[axis] = slice(max(0, -k), n - max(0, k))
+                out[tuple(dst)] += w * arr[tuple(src)]
+            arr[...] = out
+    yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+    q32 = qq.astype(np.float32).astype(np.float64)
+    fz = (q32 - qmin) * float(inv) + GRID_PAD
+    fy = yy / s - oy
+    fx = xx / s - ox
+    z0, y0, x0 = np.floor(fz).astype(np.int64), np.floor(fy).astype(np.int64), np.floor(fx).astype(np.int64)
+    az, ay, ax = fz - z0, fy - y0, fx - x0
+    vn = np.zeros_like(p)
+    vd = np.zeros_like(p)
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                w = (az if dz else 1 - az) * (ay if dy else 1 - ay) * (ax if dx else 1 - ax)
+                vn += w * num[z0 + dz, y0 + dy, x0 + dx]
+                vd += w * den[z0 + dz, y0 + dy, x0 + dx]
+    return vn / vd
+
+
+def grid_filter_bruteforce(p, q, sigma_s, sigma_r):
+    """The same approximation as one sum per output over the pixels of the periodic
+    extension (tiny inputs): the output is sum_j T(i, j) p_j / sum_j T(i, j), T(i, j) the
+    trilinear read at pixel i's grid position of the blurred unit splat of pixel j."""
+    p = np.asarray(p, dtype=np.float64)
+    qq = p if q is None else np.asarray(q, dtype=np.float64)
+    H, W = p.shape
+    s = grid_cell(sigma_s)
+    qmin, inv, zb, nz = grid_range(qq, sigma_r)
+    ts = _grid_taps(float(np.float32(sigma_s)) / s)
+    tz = _grid_taps(0.0 if math.isinf(sigma_r) else float(np.float32(sigma_r)) * float(inv))
+    q32 = qq.astype(np.float32).astype(np.float64)
+    m = 4 * s + s // 2 + 1
+
+    def tap(taps, d):
+        return taps[d + GRID_PAD] if abs(d) <= GRID_PAD else 0.0
+
+    out = np.zeros_like(p)
+    for i in range(H):
+        for j in range(W):
+            fz, fy, fx = (q32[i, j] - qmin) * float(inv), i / s, j / s
+            z0, y0, x0 = math.floor(fz), math.floor(fy), math.floor(fx)
+            num = den = 0.0
+            for a in range(-m, H + m):
+                for b in range(-m, W + m):
+                    cz, cy, cx = int(zb[a % H, b % W]), (a + s // 2) // s, (b + s // 2) // s
+                    t = 0.0
+                    for dz in (0, 1):
+                        for dy in (0, 1):
+                            for dx in (0, 1):
+                                w = ((fz - z0) if dz else 1 - (fz - z0)) * ((fy - y0) if dy else 1 - (fy - y0)) * \
+                                    ((fx - x0) if dx else 1 - (fx - x0))
+                                if w != 0.0:
+                                    t += w * tap(tz, z0 + dz - cz) * tap(ts, y0 + dy - cy) * tap(ts, x0 + dx - cx)
+                    num += t * p[a % H, b % W]
+                    den += t
+            out[i, j] = num / den
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Fourier-domain least-squares solves, Eq. (6) and Eq. (8)
 # ---------------------------------------------------------------------------
 
@@ -416,7 +568,21 @@ def _normalise_unit(v: np.ndarray):
     return v - lo, lo, 1.0
 
 
+def _field_inv_span(p, q, sigma_r, normalize):
+    # the normalisation of the experiments section maps the guide field g to
+    # [0, 1], scaling its differences by 1/span(g): taken in FP32 from the raw
+    # field (min, max and the reciprocal of max - min each rounded once)
+    if not (normalize and math.isfinite(sigma_r)):
+        return None
+    g32 = np.asarray(p if q is None else q, dtype=np.float64).astype(np.float32)
+    span32 = np.float32(np.float32(g32.max()) - np.float32(g32.min()))
+    return np.float32(np.float32(1.0) / span32) if span32 > 0 else None
+
+
 def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iterations=3):
+    if filt == "grid":
+        # the bilateral-grid approximation in place of the exact filter
+        return grid_filter(p, q, sigma_s, sigma_r, _field_inv_span(p, q, sigma_r, normalize))
     if filt == "nc":
         # NC-LS (Section III-D): the NC filter in place of the BLF.  With the
         # normalisation of the experiments section the guide field g is mapped
@@ -444,12 +610,13 @@ def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None
     """BLF-LS on one channel (Section III-A two-step procedure, Section III-D extensions).
 
     Step 1 filters p_x, p_y with Eq. (1) (``filter="nc"``: the NC filter of the domain
-    transform, NC-LS); step 2 solves Eq. (8).  ``guide`` switches to joint filtering;
+    transform, NC-LS; ``filter="grid"``: the bilateral-grid approximation of Eq. (1));
+    step 2 solves Eq. (8).  ``guide`` switches to joint filtering;
     ``iterations`` > 1 is rolling guidance.
     """
     f = np.asarray(f, dtype=np.float64)
     r = default_radius(sigma_s) if radius is None or radius < 0 else int(radius)
-    nc = filter == "nc"
+    nc = filter in ("nc", "grid")   # these normalise through the guide field's span
     lo, span = 0.0, 1.0
     if normalize and not nc:
         f, lo, span = _normalise_unit(f)

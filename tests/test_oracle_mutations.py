@@ -2,7 +2,8 @@
 
 Each mutation swaps one oracle function for a subtly wrong version: a backward
 difference, a missing conjugate, a wrong range-kernel sign, a dropped term, an
-NC filter with a wrong box schedule, wrapping windows or wrong increments.
+NC filter with a wrong box schedule, wrapping windows or wrong increments, a
+bilateral grid with a wrong Gaussian or without the periodic extension.
 The pins of ``test_oracle.py`` must reject every one of them.
 """
 import math
@@ -14,11 +15,13 @@ import oracle
 from oracle import blfls_oracle as ob
 import tests.test_oracle as pins
 import tests.test_oracle_nc as nc_pins
+import tests.test_oracle_grid as grid_pins
 
 
 def _patch(monkeypatch, name, fn):
     monkeypatch.setattr(ob, name, fn)
-    monkeypatch.setattr(oracle, name, fn)
+    if hasattr(oracle, name):  # private helpers live in the module only
+        monkeypatch.setattr(oracle, name, fn)
 
 
 def _bad_blf_sign(p, q, sigma_s, sigma_r, radius):
@@ -106,6 +109,29 @@ def _bad_nc_increments(q, a, inv_span=None):
     return d, d.copy()
 
 
+def _bad_grid_taps(sigma_cells):
+    # Gaussian with sigma instead of sigma^2
+    k = np.arange(-ob.GRID_PAD, ob.GRID_PAD + 1, dtype=np.float64)
+    if sigma_cells <= 0.0:
+        return (k == 0).astype(np.float64)
+    return np.exp(-(k * k) / (2.0 * sigma_cells))
+
+
+_orig_grid_filter = ob.grid_filter
+
+
+def _bad_grid_zero_border(p, q, sigma_s, sigma_r, inv_span=None):
+    # the grid built over the image alone (zero beyond the border) instead of its periodic extension
+    p = np.asarray(p, dtype=np.float64)
+    H, W = p.shape
+    big = np.zeros((3 * H, 3 * W))
+    big[H:2 * H, W:2 * W] = p
+    qq = p if q is None else np.asarray(q, dtype=np.float64)
+    qbig = np.full((3 * H, 3 * W), qq.min())
+    qbig[H:2 * H, W:2 * W] = qq
+    return _orig_grid_filter(big, qbig, sigma_s, sigma_r, inv_span)[H:2 * H, W:2 * W]
+
+
 MUTATIONS = {
     "backward_grad_x": ("grad_x", lambda f: f - np.roll(f, 1, axis=-1)),
     "grad_y_along_x": ("grad_y", lambda f: np.roll(f, -1, axis=-1) - f),
@@ -117,6 +143,8 @@ MUTATIONS = {
     "nc_box_sigma_not_sqrt3": ("nc_schedule", _bad_nc_schedule_sigma),
     "nc_windows_wrap": ("nc_box_pass", _bad_nc_box_wrap),
     "nc_increments_from_values": ("nc_increments", _bad_nc_increments),
+    "grid_sigma_not_squared": ("_grid_taps", _bad_grid_taps),
+    "grid_zero_border": ("grid_filter", _bad_grid_zero_border),
 }
 
 PIN_SUITE = [
@@ -133,6 +161,8 @@ PIN_SUITE = [
     lambda: nc_pins.test_nc_schedule_variances_sum_to_sigma_s_squared(3),
     nc_pins.test_nc_without_range_term_is_iterated_box_filtering,
     nc_pins.test_nc_keeps_constants_and_clean_steps,
+    lambda: grid_pins.test_grid_with_unit_cells_and_no_range_is_the_exact_gaussian(0.75),
+    grid_pins.test_grid_commutes_with_whole_cell_shifts,
 ]
 
 
