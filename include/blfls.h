@@ -69,7 +69,7 @@ typedef enum {
 /* The edge-preserving filter of step 1 (applied to each gradient field). */
 typedef enum {
   BLFLS_FILTER_BLF = 0,  /* the bilateral filter of Eq. (1): BLF-LS */
-  BLFLS_FILTER_NC = 1    /* the normalized-convolution filter of the domain transform
+  BLFLS_FILTER_NC = 1,   /* the normalized-convolution filter of the domain transform
                             (Gastal and Oliveira 2011) in its place: NC-LS (Section III-D).
                             Along a row (then a column) the transform advances by
                             1 + (sigma_s / sigma_r) |q(t) - q(t-1)| per pixel, q the range
@@ -78,6 +78,14 @@ typedef enum {
                             distance, r_k = 3 sigma_s 2^(N-k) / sqrt(4^N - 1) for round
                             k = 1..N, windows stopping at the image borders.  Window
                             membership is decided in FP32. */
+  BLFLS_FILTER_GRID = 2  /* the bilateral-grid approximation of Eq. (1) (Paris and Durand
+                            2006), the fast filter of the paper's experiments: p and 1 are
+                            splatted into cells of s = floor(sigma_s + 1/2) pixels by one
+                            range cell (1/sigma_r, widened so that at most 32 bins span the
+                            range source's values), blurred with a Gaussian of sigma_s / s
+                            cells across and one range cell deep (taps to +-2 cells), and
+                            read back by trilinear interpolation; periodic like the exact
+                            filter.  Ignores radius; s at most 32 pixels. */
 } blfls_filter;
 
 /* Parameters of Eq. (1) and Eq. (7). */
@@ -100,7 +108,7 @@ typedef struct {
                         radius r_1 must be at most BLFLS_MAX_RADIUS pixels
                         (sigma_s <= 21 for N = 3), else BLFLS_E_INVALID. */
   int32_t filter_iterations; /* NC rounds N of a horizontal and a vertical box pass,
-                        1..8; 0 selects 3.  Must be 0 for the BLF. */
+                        1..8; 0 selects 3.  Must be 0 for the other filters. */
 } blfls_params;
 
 #define BLFLS_MAX_RADIUS 32

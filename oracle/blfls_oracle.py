@@ -329,7 +329,7 @@ def nc_filter_bruteforce(p, q, sigma_s, sigma_r, n_iter=3):
 # and one range cell deep, both grids are blurred with a Gaussian, and each
 # pixel reads num / den back by trilinear interpolation at its own
 # (x, y, q).  Readings (listed in the design notes):
-#   * spatial cell s = max(1, round(sigma_s)) pixels: pixel x lies in cell
+#   * spatial cell s = max(1, floor(sigma_s + 1/2)) pixels: pixel x lies in cell
 #     floor((x + floor(s/2)) / s) and is read back at x / s;
 #   * range cell 1 / inv from min(q): inv = 1 / sigma_r, lowered if needed so
 #     that at most GRID_ZMAX bins span [min q, max q]; a pixel's bin is the
@@ -348,8 +348,8 @@ GRID_ZMAX = 32
 
 
 def grid_cell(sigma_s: float) -> int:
-    """Spatial cell size s = max(1, round(sigma_s)) from the FP32 sigma_s."""
-    return max(1, int(round(float(np.float32(sigma_s)))))
+    """Spatial cell size s = max(1, floor(sigma_s + 1/2)) from the FP32 sigma_s."""
+    return max(1, int(math.floor(float(np.float32(sigma_s)) + 0.5)))
 
 
 def grid_range(q: np.ndarray, sigma_r: float, inv_span=None):

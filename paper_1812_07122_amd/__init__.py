@@ -143,14 +143,15 @@ def _check(status: int):
         raise BlflsError(status, msg.decode() if msg else "")
 
 
-FILTERS = {"blf": 0, "nc": 1}
+FILTERS = {"blf": 0, "nc": 1, "grid": 2}
 
 
 def make_params(lam: float, sigma_s: float, sigma_r: float, radius: int = -1, iterations: int = 1,
                 normalize: bool = False, sigma_guide: float = 0.0, filter: str = "blf",
                 filter_iterations: int = 0) -> Params:
-    """``filter``: "blf" (BLF-LS) or "nc" (NC-LS: the domain transform's normalized
-    convolution in place of the BLF; ``filter_iterations`` rounds, 0 = 3)."""
+    """``filter``: "blf" (BLF-LS), "nc" (NC-LS: the domain transform's normalized
+    convolution in place of the BLF; ``filter_iterations`` rounds, 0 = 3) or "grid" (the
+    bilateral-grid approximation of the BLF)."""
     if filter not in FILTERS:
         raise ValueError(f"filter must be one of {sorted(FILTERS)}")
     return Params(float(lam), float(sigma_s), float(sigma_r), int(radius), int(iterations),

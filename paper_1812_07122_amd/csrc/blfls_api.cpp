@@ -140,15 +140,19 @@ blfls_status check_params(const blfls_params* p, int* radius_out) {
   if (p->iterations < 1) return set_error(BLFLS_E_INVALID, "iterations must be >= 1");
   if (!std::isfinite(p->sigma_guide) || p->sigma_guide < 0.0f) return set_error(BLFLS_E_INVALID, "sigma_guide must be finite and >= 0");
   if (p->flags & ~BLFLS_F_NORMALIZE) return set_error(BLFLS_E_INVALID, "unknown flag bits");
-  if (p->filter != BLFLS_FILTER_BLF && p->filter != BLFLS_FILTER_NC)
+  if (p->filter != BLFLS_FILTER_BLF && p->filter != BLFLS_FILTER_NC && p->filter != BLFLS_FILTER_GRID)
     return set_error(BLFLS_E_INVALID, "unknown filter");
   if (p->filter_iterations < 0 || p->filter_iterations > 8)
     return set_error(BLFLS_E_INVALID, "filter_iterations must be in [0, 8]");
-  if (p->filter == BLFLS_FILTER_BLF && p->filter_iterations != 0)
+  if (p->filter != BLFLS_FILTER_NC && p->filter_iterations != 0)
     return set_error(BLFLS_E_INVALID, "filter_iterations applies to the NC filter only");
+  if (p->filter == BLFLS_FILTER_GRID && grid_cell_size(p->sigma_s) > kGridMaxCell)
+    return set_error(BLFLS_E_INVALID, "sigma_s too large for the bilateral grid (cell above 32 pixels)");
   int r = p->radius;
   if (r < -1) return set_error(BLFLS_E_INVALID, "radius must be >= 0 or -1");
-  if (p->filter == BLFLS_FILTER_NC) {
+  if (p->filter == BLFLS_FILTER_GRID) {
+    r = 0;
+  } else if (p->filter == BLFLS_FILTER_NC) {
     const int n = p->filter_iterations ? p->filter_iterations : 3;
     if (nc_pixel_radius(static_cast<float>(nc_box_radius(p->sigma_s, n, 1))) > kNcMaxR)
       return set_error(BLFLS_E_INVALID, "sigma_s too large for the NC filter (first box radius above 32 pixels)");
@@ -321,6 +325,8 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
   out->mm_next.assign(C, AuxPlane{});
   out->gauss.assign(C, AuxPlane{});
   out->fft.assign(C, FftPlane{});
+  out->grid_first.assign(C, GridPlane{});
+  out->grid_next.assign(C, GridPlane{});
   out->nc_first.assign(C, NcPlane{});
   out->nc_next.assign(C, NcPlane{});
   out->filter = prm.filter;
@@ -404,6 +410,27 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
       N.ccount = nc_col_items(H, W);
       N.cbegin = ch * N.ccount;
     }
+    for (int it = 0; it < 2; ++it) {
+      const BlfPlane& B = it == 0 ? out->blf_first[ch] : out->blf_next[ch];
+      GridPlane& G2 = it == 0 ? out->grid_first[ch] : out->grid_next[ch];
+      const int sc = grid_cell_size(prm.sigma_s);
+      G2.f = fc;
+      G2.g = B.g;
+      G2.pitch = pitch;
+      G2.gpitch = B.gpitch;
+      G2.rx = rx;
+      G2.ry = ry;
+      G2.minmax = partial;
+      G2.H = H; G2.W = W;
+      G2.s = sc;
+      G2.tiles_x = grid_tiles_x(W, sc);
+      G2.tile_count = G2.tiles_x * grid_tiles_y(H, sc);
+      G2.tile_begin = ch * G2.tile_count;
+      G2.inv_r = range_on ? static_cast<float>(1.0 / static_cast<double>(prm.sigma_r)) : 0.0f;
+      G2.sigma_r = range_on ? prm.sigma_r : 0.0f;
+      G2.sig_xy = static_cast<float>(static_cast<double>(prm.sigma_s) / sc);
+      G2.normalize = (prm.flags & BLFLS_F_NORMALIZE) != 0 ? 1 : 0;
+    }
     FftPlane& F = out->fft[ch];
     F.rx = rx; F.ry = ry;
     F.spec = reinterpret_cast<float2*>(wsb + plan->off_spec) + static_cast<size_t>(ch) * (M + 1) * H;
@@ -435,12 +462,18 @@ hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, cons
   }
   for (int it = 0; it < rd.iterations; ++it) {
     const bool first = it == 0;
-    if (rd.normalize) {
+    if (rd.normalize || rd.filter == BLFLS_FILTER_GRID) {
       StageTimer t(BLFLS_STAGE_MINMAX, s);
       e = launch_minmax(first ? dev.mm_first : dev.mm_next, C, s);
       if (e != hipSuccess) return e;
     }
-    if (rd.filter == BLFLS_FILTER_NC) {
+    if (rd.filter == BLFLS_FILTER_GRID) {
+      StageTimer t(BLFLS_STAGE_BLF, s);
+      const GridPlane* gp = first ? dev.grid_first : dev.grid_next;
+      const GridPlane& g0 = first ? rd.grid_first[0] : rd.grid_next[0];
+      e = launch_grid(gp, C, 2 * C * g0.tile_count, ft, s);
+      if (e != hipSuccess) return e;
+    } else if (rd.filter == BLFLS_FILTER_NC) {
       StageTimer t(BLFLS_STAGE_BLF, s);
       const NcPlane* np = first ? dev.nc_first : dev.nc_next;
       const int passes = 2 * rd.nc_rounds;
@@ -561,6 +594,9 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   if (rd.filter == BLFLS_FILTER_NC) {
     o_n1 = place(rd.nc_first.data(), C * sizeof(NcPlane));
     o_n2 = place(rd.nc_next.data(), C * sizeof(NcPlane));
+  } else if (rd.filter == BLFLS_FILTER_GRID) {
+    o_n1 = place(rd.grid_first.data(), C * sizeof(GridPlane));
+    o_n2 = place(rd.grid_next.data(), C * sizeof(GridPlane));
   }
   if (blob.size() > kDescBytes) return set_error(BLFLS_E_INVALID, "descriptor area overflow");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -579,6 +615,9 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   if (rd.filter == BLFLS_FILTER_NC) {
     dd.nc_first = reinterpret_cast<const NcPlane*>(dbase + o_n1);
     dd.nc_next = reinterpret_cast<const NcPlane*>(dbase + o_n2);
+  } else if (rd.filter == BLFLS_FILTER_GRID) {
+    dd.grid_first = reinterpret_cast<const GridPlane*>(dbase + o_n1);
+    dd.grid_next = reinterpret_cast<const GridPlane*>(dbase + o_n2);
   }
   e = enqueue_request(plan, rd, dd, s);
   if (e != hipSuccess) return hip_error(e, "kernel launch");

@@ -122,6 +122,29 @@ struct NcPlane {
   int pad_;
 };
 
+// One channel plane for the bilateral-grid approximation of Eq. (1): both
+// gradient fields of one channel, tiles of 8 x 8 grid cells per field.
+constexpr int kGridZMax = 32;           // range bins at most
+constexpr int kGridMaxCell = 32;        // spatial cell size at most (pixels)
+struct GridPlane {
+  const float* f;        // image whose gradients are filtered, [H][pitch]
+  const float* g;        // range-source image or nullptr = f
+  int64_t pitch;
+  int64_t gpitch;
+  void* rx;              // residual r_x = grid(p_x) - p_x, packed [H][W], field type
+  void* ry;
+  const float* minmax;   // range-source gradient extrema partials (always)
+  int H, W;
+  int s;                 // spatial cell size in pixels
+  int tiles_x;           // tiles across W (8 cells each)
+  int tile_begin;        // first tile index of this plane in the launch
+  int tile_count;        // tiles per field
+  float inv_r;           // 1 / sigma_r rounded to FP32 (0: range term off)
+  float sigma_r;         // sigma_r (FP32): the range blur is sigma_r * inv cells wide
+  float sig_xy;          // sigma_s / s: the spatial blur width in cells
+  int normalize;         // divide the range scale by the field's span
+};
+
 // Minmax (normalise flag) and Gaussian-guide descriptors.
 struct AuxPlane {
   const float* src;      // range-source image [H][pitch]

@@ -44,6 +44,12 @@ int nc_col_items(int H, int W);
 hipError_t nc_init_kernels();
 hipError_t launch_nc_pass(const NcPlane* planes, int nplanes, int items, int pass, int npasses, float r, int R,
                           int field_type, hipStream_t s);
+// Bilateral-grid approximation: cell size for sigma_s, tiles (8 x 8 cells)
+// across W and down H, and the launch over 2 fields x tiles of every plane.
+int grid_cell_size(float sigma_s);
+int grid_tiles_x(int W, int s);
+int grid_tiles_y(int H, int s);
+hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int field_type, hipStream_t s);
 hipError_t launch_minmax(const AuxPlane* planes, int nplanes, hipStream_t s, WorkHeader* work = nullptr,
                          int grid = 0);
 hipError_t launch_gauss(const AuxPlane* planes, int nplanes, int64_t max_pixels, hipStream_t s,

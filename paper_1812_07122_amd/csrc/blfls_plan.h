@@ -67,6 +67,8 @@ struct RequestDesc {
   std::vector<AuxPlane> mm_next;
   std::vector<AuxPlane> gauss;       // guide smoothing
   std::vector<FftPlane> fft;
+  std::vector<GridPlane> grid_first; // bilateral grid: iteration 1
+  std::vector<GridPlane> grid_next;  // and iterations 2..n
   std::vector<NcPlane> nc_first;     // NC-LS: the NC passes of iteration 1
   std::vector<NcPlane> nc_next;      // and of iterations 2..n
   int filter = BLFLS_FILTER_BLF;
@@ -97,6 +99,8 @@ struct DeviceDesc {
   const AuxPlane* mm_next = nullptr;
   const AuxPlane* gauss = nullptr;
   const FftPlane* fft = nullptr;
+  const GridPlane* grid_first = nullptr;
+  const GridPlane* grid_next = nullptr;
   const NcPlane* nc_first = nullptr;
   const NcPlane* nc_next = nullptr;
 };

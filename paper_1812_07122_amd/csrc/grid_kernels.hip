@@ -1,0 +1,236 @@
+// Bilateral-grid approximation of Eq. (1) on the gradient fields (the fast
+// filter of Paris and Durand 2006 that the paper's experiments use in place of
+// the exact one, Section III-B), for gfx950.
+//
+// The approximation is a 3-D linear filter in (x, y, range) followed by a
+// division: p and 1 are splatted into cells of s x s pixels by one range cell,
+// blurred with a Gaussian (taps to +-2 cells), and read back at each pixel's
+// own (x / s, y / s, range position) by trilinear interpolation.  The image is
+// periodic like the exact filter's window.
+//
+// No global grid is stored: a workgroup owns 8 x 8 output cells of one field
+// and builds, in LDS, the 14 x 14 cells (+-3) that can reach them through the
+// blur and the interpolation, with the whole range axis (at most 32 bins plus
+// 2 empty bins of padding at each end):
+//   * splat: thread c owns local cell c and adds its s x s pixels (wrapped into
+//     the image) to its own bins, so no atomics are needed and the sums are
+//     deterministic;
+//   * blur: along the range axis per cell, then along x and y per grid line,
+//     each line held in registers (in place);
+//   * slice: each output pixel interpolates num and den from the 8 cells
+//     around it, and the residual g - p is written in the field type.
+// The range bin floor((q - qmin) inv + 1/2) is an integer decision: it is
+// computed in FP32 one rounding per operation, as the checker computes it.
+// qmin and the span come from the gradient-extrema partials of the range
+// source.
+#include "blfls_field.h"
+#include "blfls_internal.h"
+#include "blfls_launch.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace blfls {
+
+namespace {
+
+constexpr int kTileCells = 8;                   // output cells per tile side
+constexpr int kLocal = kTileCells + 6;          // local grid cells per side (+-3)
+constexpr int kCells = kLocal * kLocal;         // 196
+constexpr int kZPad = 2;
+constexpr int kZS = kGridZMax + 2 * kZPad + 1;  // 37: odd stride per cell (LDS banks)
+constexpr int kGridThreads = 256;
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+  const int m = v % n;
+  return m < 0 ? m + n : m;
+}
+
+// Circular forward difference of image x along the field's axis at (i, j).
+__device__ __forceinline__ float grad_px(const float* __restrict__ x, int64_t pitch, int H, int W, int i, int j,
+                                         int field) {
+  const float v = x[static_cast<int64_t>(i) * pitch + j];
+  if (field == 0) return x[static_cast<int64_t>(i) * pitch + (j + 1 == W ? 0 : j + 1)] - v;
+  return x[static_cast<int64_t>(i + 1 == H ? 0 : i + 1) * pitch + j] - v;
+}
+
+// Range source extrema of one field from the minmax partials (block-wide call).
+__device__ __forceinline__ void field_extrema(const float* partial, int field, float* lo_out, float* hi_out) {
+  __shared__ float red[2];
+  if (threadIdx.x < 64) {
+    const int i = threadIdx.x;
+    float lo = partial[i * 4 + field * 2 + 0];
+    float hi = partial[i * 4 + field * 2 + 1];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      lo = fminf(lo, __shfl_xor(lo, off));
+      hi = fmaxf(hi, __shfl_xor(hi, off));
+    }
+    if (i == 0) { red[0] = lo; red[1] = hi; }
+  }
+  __syncthreads();
+  *lo_out = red[0];
+  *hi_out = red[1];
+}
+
+__device__ __forceinline__ int find_grid_plane(const GridPlane* planes, int nplanes, int item) {
+  int lo = 0, hi = nplanes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (2 * planes[mid].tile_begin <= item) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// In-place 5-tap blur of n values spaced `stride` apart, zero beyond the ends.
+template <int N>
+__device__ __forceinline__ void blur_line(float* base, int stride, int n, const float* w) {
+  float v[N];
+#pragma unroll
+  for (int t = 0; t < N; ++t) v[t] = t < n ? base[t * stride] : 0.0f;
+#pragma unroll
+  for (int t = 0; t < N; ++t) {
+    if (t < n) {
+      float acc = 0.0f;
+#pragma unroll
+      for (int k = -2; k <= 2; ++k) {
+        const int u = t + k;
+        if (u >= 0 && u < N) acc += w[k + 2] * v[u];
+      }
+      base[t * stride] = acc;
+    }
+  }
+}
+
+}  // namespace
+
+// One workgroup: (plane, field, tile of 8 x 8 output cells).
+__global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPlane* __restrict__ planes,
+                                                                   int nplanes, int field_type) {
+  __shared__ float snum[kCells * kZS];
+  __shared__ float sden[kCells * kZS];
+  __shared__ float taps[2][5];
+  const int item = blockIdx.x;
+  const GridPlane& P = planes[find_grid_plane(planes, nplanes, item)];
+  const int local = item - 2 * P.tile_begin;
+  const int field = local >= P.tile_count ? 1 : 0;
+  const int tile = local - field * P.tile_count;
+  const int H = P.H, W = P.W, s = P.s, half = s / 2;
+  const int X0 = (tile % P.tiles_x) * kTileCells;   // first output cell of the tile
+  const int Y0 = (tile / P.tiles_x) * kTileCells;
+  const int tid = threadIdx.x;
+
+  // range axis: origin, scale (capped to kGridZMax bins), bins in use, blur width
+  float qmin, qmax;
+  field_extrema(P.minmax, field, &qmin, &qmax);
+  const float span = qmax - qmin;
+  float inv = P.inv_r;
+  float inv_span = 1.0f;
+  const bool norm = P.normalize != 0 && inv != 0.0f && span > 0.0f;
+  if (norm) {
+    inv_span = __fdiv_rn(1.0f, span);
+    inv = __fmul_rn(inv, inv_span);
+  }
+  if (__fmul_rn(span, inv) > static_cast<float>(kGridZMax - 1)) inv = __fdiv_rn(static_cast<float>(kGridZMax - 1), span);
+  const int nz = static_cast<int>(floorf(__fadd_rn(__fmul_rn(span, inv), 0.5f))) + 1;
+  const int zt = nz + 2 * kZPad;
+  if (tid < 5) {
+    const float k = static_cast<float>(tid - 2);
+    const float sz = inv == 0.0f ? 0.0f : (norm ? P.sigma_r * inv / inv_span : P.sigma_r * inv);
+    taps[0][tid] = expf(-(k * k) / (2.0f * P.sig_xy * P.sig_xy));
+    taps[1][tid] = sz > 0.0f ? expf(-(k * k) / (2.0f * sz * sz)) : (tid == 2 ? 1.0f : 0.0f);
+  }
+  for (int i = tid; i < kCells * kZS; i += kGridThreads) {
+    snum[i] = 0.0f;
+    sden[i] = 0.0f;
+  }
+  __syncthreads();
+
+  const float* __restrict__ f = P.f;
+  const float* __restrict__ g = P.g ? P.g : P.f;
+  const int64_t gp = P.g ? P.gpitch : P.pitch;
+
+  // splat: local cell c = (cy, cx) is grid cell (Y0 - 3 + cy, X0 - 3 + cx), whose
+  // pixels (extended coordinates) start at cell * s - s/2
+  if (tid < kCells) {
+    const int cy = tid / kLocal, cx = tid - (tid / kLocal) * kLocal;
+    const int py0 = (Y0 - 3 + cy) * s - half;
+    const int px0 = (X0 - 3 + cx) * s - half;
+    float* cn = snum + tid * kZS + kZPad;
+    float* cd = sden + tid * kZS + kZPad;
+    for (int a = 0; a < s; ++a) {
+      const int i = wrapi(py0 + a, H);
+      for (int b = 0; b < s; ++b) {
+        const int j = wrapi(px0 + b, W);
+        const float pv = grad_px(f, P.pitch, H, W, i, j, field);
+        const float qv = grad_px(g, gp, H, W, i, j, field);
+        const float t = __fmul_rn(__fsub_rn(qv, qmin), inv);
+        const int z = static_cast<int>(floorf(__fadd_rn(t, 0.5f)));
+        cn[z] += pv;
+        cd[z] += 1.0f;
+      }
+    }
+  }
+  __syncthreads();
+
+  // blur along the range axis (per cell), then x, then y (per grid line)
+  if (tid < kCells) {
+    blur_line<kGridZMax + 2 * kZPad>(snum + tid * kZS, 1, zt, taps[1]);
+    blur_line<kGridZMax + 2 * kZPad>(sden + tid * kZS, 1, zt, taps[1]);
+  }
+  __syncthreads();
+  for (int l = tid; l < kLocal * zt; l += kGridThreads) {   // line (cy, z) along x
+    const int cy = l / zt, z = l - (l / zt) * zt;
+    blur_line<kLocal>(snum + cy * kLocal * kZS + z, kZS, kLocal, taps[0]);
+    blur_line<kLocal>(sden + cy * kLocal * kZS + z, kZS, kLocal, taps[0]);
+  }
+  __syncthreads();
+  for (int l = tid; l < kLocal * zt; l += kGridThreads) {   // line (cx, z) along y
+    const int cx = l / zt, z = l - (l / zt) * zt;
+    blur_line<kLocal>(snum + cx * kZS + z, kLocal * kZS, kLocal, taps[0]);
+    blur_line<kLocal>(sden + cx * kZS + z, kLocal * kZS, kLocal, taps[0]);
+  }
+  __syncthreads();
+
+  // slice the output pixels of the tile: pixels whose cell lies in [Y0, Y0+8) x [X0, X0+8)
+  const int y_lo = max(Y0 * s - half, 0), y_hi = min((Y0 + kTileCells) * s - half, H);
+  const int x_lo = max(X0 * s - half, 0), x_hi = min((X0 + kTileCells) * s - half, W);
+  const int tw = x_hi - x_lo, npx = (y_hi - y_lo) * max(tw, 0);
+  const float inv_s = 1.0f / static_cast<float>(s);
+  void* out = field ? P.ry : P.rx;
+  for (int e = tid; e < npx; e += kGridThreads) {
+    const int i = y_lo + e / tw, j = x_lo + (e - (e / tw) * tw);
+    const float pv = grad_px(f, P.pitch, H, W, i, j, field);
+    const float qv = grad_px(g, gp, H, W, i, j, field);
+    const float fz = __fmul_rn(__fsub_rn(qv, qmin), inv) + static_cast<float>(kZPad);
+    const float fy = static_cast<float>(i) * inv_s - static_cast<float>(Y0 - 3);
+    const float fx = static_cast<float>(j) * inv_s - static_cast<float>(X0 - 3);
+    const int z0 = min(max(static_cast<int>(floorf(fz)), 0), zt - 2);
+    const int y0 = static_cast<int>(floorf(fy)), x0 = static_cast<int>(floorf(fx));
+    const float az = fz - static_cast<float>(z0), ay = fy - static_cast<float>(y0), ax = fx - static_cast<float>(x0);
+    float vn = 0.0f, vd = 0.0f;
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const float wxy = (dy ? ay : 1.0f - ay) * (dx ? ax : 1.0f - ax);
+        const int c = ((y0 + dy) * kLocal + (x0 + dx)) * kZS + z0;
+        vn += wxy * ((1.0f - az) * snum[c] + az * snum[c + 1]);
+        vd += wxy * ((1.0f - az) * sden[c] + az * sden[c + 1]);
+      }
+    store_field(out, static_cast<int64_t>(i) * W + j, vn / vd - pv, field_type);
+  }
+}
+
+int grid_cell_size(float sigma_s) { return std::max(1, static_cast<int>(std::floor(static_cast<double>(sigma_s) + 0.5))); }
+
+int grid_tiles_x(int W, int s) { return ((W - 1 + s / 2) / s + 1 + kTileCells - 1) / kTileCells; }
+int grid_tiles_y(int H, int s) { return ((H - 1 + s / 2) / s + 1 + kTileCells - 1) / kTileCells; }
+
+hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int field_type, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(grid_filter_kernel, dim3(items), dim3(kGridThreads), 0, s, planes, nplanes, field_type);
+  return hipGetLastError();
+}
+
+}  // namespace blfls

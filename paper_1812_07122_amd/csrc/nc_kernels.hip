@@ -73,7 +73,7 @@ __device__ __forceinline__ bool field_scale(const NcPlane& P, int field, float* 
   if (P.minmax == nullptr || P.a == 0.0f) return false;
   const float span = field_span(P.minmax, field);
   if (!(span > 0.0f)) return false;
-  *inv = 1.0f / span;
+  *inv = __fdiv_rn(1.0f, span);
   return true;
 }
 

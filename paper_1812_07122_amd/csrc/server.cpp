@@ -524,7 +524,7 @@ blfls_status blfls_submit(blfls_server_t s, const blfls_request* r, uint64_t* ti
   st = check_params(&r->params, &radius);
   if (st != BLFLS_OK) return st;
   if (r->params.filter != BLFLS_FILTER_BLF)
-    return set_error(BLFLS_E_UNSUPPORTED, "the server runs BLF-LS; NC-LS runs through blfls_smooth");
+    return set_error(BLFLS_E_UNSUPPORTED, "the server runs the exact BLF; other filters run through blfls_smooth");
   if (r->f == nullptr || r->u == nullptr) return set_error(BLFLS_E_INVALID, "f and u must not be NULL");
   if (r->pitch < r->W) return set_error(BLFLS_E_INVALID, "pitch must be >= W");
   const size_t img = static_cast<size_t>(r->C) * r->H * r->pitch * sizeof(float);

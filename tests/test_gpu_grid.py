@@ -1,0 +1,137 @@
+"""GPU parity of the bilateral-grid approximation (filter="grid") against the
+FP64 oracle, through the C ABI.
+
+The range bin of each pixel is decided in FP32 on both sides from the same
+guide values, so with identical range sources the GPU and the oracle fill the
+same cells and differ only by FP32 sums, blurs and interpolation: max-abs 1e-5
+for FP32 fields, 2e-3 and PSNR >= 50 dB for 16-bit fields.  Iteration 2 of
+rolling guidance is checked against the oracle's joint step guided by the
+GPU's own first iteration.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import voronoi_image, voronoi_rgb, joint_pair
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-5
+TOL_MIXED = 2e-3
+
+
+def blfls():
+    import paper_1812_07122_amd as b
+    return b
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _grid(f64, guide64=None, **kw):
+    f32 = np.asarray(f64, dtype=np.float32)
+    g = None if guide64 is None else _gpu(guide64)
+    u = blfls().smooth(_gpu(f32), guide=g, filter="grid", **kw)
+    torch.cuda.synchronize()
+    return u.cpu().numpy().astype(np.float64), f32.astype(np.float64)
+
+
+def _psnr(a, b):
+    mse = float(np.mean((a - b) ** 2))
+    return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+@pytest.mark.parametrize("H,W,ss,sr,lam", [
+    (96, 128, 4.0, 0.05, 20.0),
+    (72, 90, 8.0, 0.05, 20.0),      # ragged tiles (8-cell tiles of 8-pixel cells)
+    (60, 50, 2.5, 0.1, 50.0),       # s = 3: cells straddle the wrap
+    (8, 12, 3.0, 0.05, 10.0),       # image smaller than one tile: the grid wraps several times
+    (2, 4, 1.0, 0.1, 5.0),
+    (80, 100, 20.0, 0.2, 20.0),     # s = 20
+    (64, 64, 4.0, 0.003, 20.0),     # more bins than the cap: wider range cells
+])
+def test_grid_ls_parity(H, W, ss, sr, lam):
+    f = voronoi_image(H, W, 700 + H + W)
+    u, fin = _grid(f, lam=lam, sigma_s=ss, sigma_r=sr)
+    ref = oracle.smooth(fin, lam, ss, sr, filter="grid")
+    err = float(np.max(np.abs(u - ref)))
+    print(f"grid-LS {H}x{W} ss={ss} sr={sr}: max-abs {err:.3e}")
+    assert err <= TOL_FP32
+
+
+def test_grid_rgb_joint_normalize_range_off():
+    f = voronoi_rgb(64, 96, 5)
+    u, fin = _grid(f, lam=30.0, sigma_s=4.0, sigma_r=0.05)
+    assert np.max(np.abs(u - oracle.smooth(fin, 30.0, 4.0, 0.05, filter="grid"))) <= TOL_FP32
+    t, g = joint_pair(96, 128, 5)
+    u, tin = _grid(t, g, lam=30.0, sigma_s=4.0, sigma_r=0.08)
+    gin = np.asarray(g, np.float32).astype(np.float64)
+    assert np.max(np.abs(u - oracle.smooth(tin, 30.0, 4.0, 0.08, guide=gin, filter="grid"))) <= TOL_FP32
+    f1 = voronoi_image(72, 90, 92)
+    u, fin = _grid(f1, lam=20.0, sigma_s=3.0, sigma_r=0.3, normalize=True)
+    assert np.max(np.abs(u - oracle.smooth(fin, 20.0, 3.0, 0.3, normalize=True, filter="grid"))) <= TOL_FP32
+    u, fin = _grid(f1, lam=20.0, sigma_s=3.0, sigma_r=math.inf)
+    assert np.max(np.abs(u - oracle.smooth(fin, 20.0, 3.0, math.inf, filter="grid"))) <= TOL_FP32
+
+
+def test_grid_rolling_step_is_joint_filtering_guided_by_the_previous_output():
+    f = voronoi_image(96, 128, 94)
+    u1, fin = _grid(f, lam=20.0, sigma_s=4.0, sigma_r=0.02, iterations=1)
+    u2, _ = _grid(f, lam=20.0, sigma_s=4.0, sigma_r=0.02, iterations=2)
+    assert np.max(np.abs(u1 - oracle.smooth(fin, 20.0, 4.0, 0.02, filter="grid"))) <= TOL_FP32
+    assert np.max(np.abs(u2 - oracle.smooth(fin, 20.0, 4.0, 0.02, guide=u1, filter="grid"))) <= TOL_FP32
+
+
+def test_grid_exact_special_cases():
+    f = voronoi_image(48, 64, 96)
+    f32 = np.asarray(f, dtype=np.float32)
+    u, _ = _grid(f, lam=0.0, sigma_s=4.0, sigma_r=0.05)
+    assert np.array_equal(u.astype(np.float32), f32)
+    c = np.full((32, 40), 0.4, dtype=np.float32)
+    u, _ = _grid(c, lam=50.0, sigma_s=4.0, sigma_r=0.05)
+    assert np.array_equal(u.astype(np.float32), c)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp16"])
+def test_grid_mixed_precision_fields(precision):
+    f = voronoi_rgb(128, 160, 6)
+    u, fin = _grid(f, lam=30.0, sigma_s=6.0, sigma_r=0.05, precision=precision)
+    ref = oracle.smooth(fin, 30.0, 6.0, 0.05, filter="grid")
+    err = float(np.max(np.abs(u - ref)))
+    psnr = _psnr(u, ref)
+    print(f"grid-LS {precision}: max-abs {err:.3e}, PSNR {psnr:.1f} dB")
+    assert err <= TOL_MIXED and psnr >= 50.0
+
+
+def test_grid_rgb_1024_channel_full_size_and_distance_to_exact():
+    f = voronoi_rgb(1024, 1024, 1)
+    u, fin = _grid(f, lam=20.0, sigma_s=8.0, sigma_r=0.05)
+    ref0 = oracle.smooth(fin[0], 20.0, 8.0, 0.05, filter="grid")
+    err = float(np.max(np.abs(u[0] - ref0)))
+    print(f"grid-LS 1024x1024 channel 0: max-abs vs oracle {err:.3e}")
+    assert err <= TOL_FP32
+    exact = blfls().smooth(_gpu(fin), lam=20.0, sigma_s=8.0, sigma_r=0.05).cpu().numpy().astype(np.float64)
+    print(f"grid-LS vs exact BLF-LS: PSNR {_psnr(u, exact):.1f} dB, max-abs {np.max(np.abs(u - exact)):.3e}")
+    assert _psnr(u, exact) > 30.0
+
+
+def test_grid_abi_errors():
+    b = blfls()
+    f = _gpu(voronoi_image(16, 16, 1))
+    with pytest.raises(b.BlflsError) as e:
+        b.smooth(f, lam=1.0, sigma_s=33.0, sigma_r=0.1, filter="grid")   # cell above 32 pixels
+    assert e.value.status == -1
+    with pytest.raises(b.BlflsError) as e:
+        b.smooth(f, lam=1.0, sigma_s=2.0, sigma_r=0.1, filter="grid", filter_iterations=2)
+    assert e.value.status == -1
+    srv = b.Server(1 << 26)
+    try:
+        with pytest.raises(b.BlflsError) as e:
+            srv.submit(f, 1.0, 2.0, 0.1, filter="grid")
+        assert e.value.status == -2
+    finally:
+        srv.close()
