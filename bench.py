@@ -17,6 +17,8 @@ Other workloads (each prints its own JSON line):
          sigma_r = 0.08) through the server
   nc     NC-LS (the domain transform's normalized convolution in place of the
          BLF, Section III-D) on the 1024x1024 RGB image, plain and rolling
+  grid   the bilateral-grid approximation on the 3840x2160 RGB workload, against
+         the exact filter
 """
 from __future__ import annotations
 
@@ -45,7 +47,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="rgb1024", choices=["rgb1024", "uhd", "serve", "joint", "nc", "copy"])
+    ap.add_argument("--workload", default="rgb1024", choices=["rgb1024", "uhd", "serve", "joint", "nc", "grid", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=2000)
     return ap.parse_args()

@@ -81,6 +81,16 @@ def prepare(args):
             state["t_oracle0"] = time.perf_counter()
             state["oracle"] = pool.map_async(_oracle_channel, jobs)
             state["pool"] = pool
+    elif args.workload == "grid":
+        f = synth.voronoi_rgb(2160, 3840, 2)
+        state["f"] = f.astype(np.float32)
+        if not args.no_cpu_baseline:
+            pool = _pool(1)
+            c = GRID_CONFIG
+            jobs = [(state["f"][0].astype(np.float64), None, c["lam"], c["sigma_s"], c["sigma_r"], {"filter": "grid"})]
+            state["t_oracle0"] = time.perf_counter()
+            state["oracle"] = pool.map_async(_oracle_channel, jobs)
+            state["pool"] = pool
     elif args.workload == "joint":
         pairs = [synth.joint_pair(2048, 2048, i) for i in range(64 if args.requests >= 64 else args.requests)]
         state["pairs"] = [(t.astype(np.float32), g.astype(np.float32)) for t, g in pairs]
@@ -211,6 +221,49 @@ def run_uhd(args, torch, blfls, state):
         out["cpu_baseline"] = {"value": round(H * W / t / 1e6, 5), "unit": "MPix/s", "cores": 3, "kind": "oracle",
                                "sample": f"whole image, 3 channels in 3 worker processes, {t:.0f} s wall "
                                          "(includes time overlapped with the GPU runs)"}
+    return out
+
+
+# the bilateral grid where it pays: the 3840x2160 RGB workload (sigma_s = 8, 2401 taps
+# per pixel-field for the exact filter)
+GRID_CONFIG = dict(lam=50.0, sigma_s=8.0, sigma_r=0.05)
+
+
+def run_grid(args, torch, blfls, state):
+    from bench import time_plan
+    H, W, C = 2160, 3840, 3
+    f = torch.from_numpy(state["f"]).cuda()
+    u = torch.empty_like(f)
+    steps = max(1, min(args.steps, 20))
+    res = {}
+    outs = {}
+    for name, prm in (("grid", dict(GRID_CONFIG, filter="grid")), ("exact", dict(GRID_CONFIG))):
+        plan = blfls.Plan(H, W, C, "fp32")
+        n = steps if name == "grid" else max(1, min(steps, 3))
+        ms, stages = time_plan(plan, f, u, prm, n, min(args.warmup, 2), torch, blfls)
+        outs[name] = plan.smooth(f, **prm).cpu().numpy().astype(np.float64)
+        torch.cuda.synchronize()
+        filt_ms = stages["blf"][0] / max(stages["blf"][1], 1)
+        res[name] = {"MPix/s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_image": round(ms, 4),
+                     "filter_ms": round(filt_ms, 4), "steps": n}
+        plan.close()
+    d = outs["grid"] - outs["exact"]
+    res["grid"]["vs_exact_blf_ls"] = {"psnr_db": round(_psnr(outs["grid"], outs["exact"]), 2),
+                                      "max_abs": float(np.max(np.abs(d))),
+                                      "rms": float(np.sqrt(np.mean(d * d)))}
+    out = {"metric": "MPix/s grid-approximated BLF-LS at 1 GPU", "value": res["grid"]["MPix/s"], "unit": "MPix/s",
+           "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 2), "ms_per_step": res["grid"]["ms_per_image"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "grid: 3840x2160 RGB, lambda=50, sigma_s=8, sigma_r=0.05, bilateral-grid filter "
+                                  "(cells of 8 pixels by one range cell) against the exact windowed filter (r=24)",
+                      "H": H, "W": W, "C": C},
+           "filters": res}
+    ref, t = _collect(state)
+    if ref is not None:
+        out["max_abs_vs_oracle_ch0"] = float(np.max(np.abs(outs["grid"][0] - ref[0])))
+        out["cpu_baseline"] = {"value": round(H * W / (3 * t) / 1e6, 5), "unit": "MPix/s", "cores": 1,
+                               "kind": "oracle", "sample": f"channel 0 of the image ({t:.1f} s wall, overlapping the "
+                                                           "GPU runs); rate scaled to RGB images"}
     return out
 
 

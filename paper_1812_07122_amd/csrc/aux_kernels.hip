@@ -34,22 +34,21 @@ hipError_t launch_desc_copy(const void* host_src, size_t bytes, void* dev_dst, h
 }
 
 // partial[b] = (min D_x, max D_x, min D_y, max D_y) over the elements of block b
-// (kMinmaxBlocks blocks per plane, elements strided over the blocks).
+// (kMinmaxBlocks blocks per plane, rows strided over the blocks).
 __device__ __forceinline__ void minmax_item(const AuxPlane& P, int blk) {
   const int H = P.H, W = P.W;
-  const int64_t n = static_cast<int64_t>(H) * W;
   float lx = INFINITY, hx = -INFINITY, ly = INFINITY, hy = -INFINITY;
-  for (int64_t idx = static_cast<int64_t>(blk) * 256 + threadIdx.x; idx < n;
-       idx += static_cast<int64_t>(kMinmaxBlocks) * 256) {
-    const int i = static_cast<int>(idx / W);
-    const int j = static_cast<int>(idx - static_cast<int64_t>(i) * W);
+  // block blk takes rows blk, blk + kMinmaxBlocks, ...; threads stride the columns
+  for (int i = blk; i < H; i += kMinmaxBlocks) {
     const float* row = P.src + static_cast<int64_t>(i) * P.pitch;
     const float* rown = P.src + static_cast<int64_t>(i + 1 == H ? 0 : i + 1) * P.pitch;
-    const float v = row[j];
-    const float gx = row[j + 1 == W ? 0 : j + 1] - v;
-    const float gy = rown[j] - v;
-    lx = fminf(lx, gx); hx = fmaxf(hx, gx);
-    ly = fminf(ly, gy); hy = fmaxf(hy, gy);
+    for (int j = threadIdx.x; j < W; j += 256) {
+      const float v = row[j];
+      const float gx = row[j + 1 == W ? 0 : j + 1] - v;
+      const float gy = rown[j] - v;
+      lx = fminf(lx, gx); hx = fmaxf(hx, gx);
+      ly = fminf(ly, gy); hy = fmaxf(hy, gy);
+    }
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {

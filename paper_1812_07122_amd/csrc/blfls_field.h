@@ -22,22 +22,33 @@ __device__ __forceinline__ void store_field(void* base, int64_t idx, float v, in
   }
 }
 
-// Reduce the minmax partials of one field: returns max - min of the range source.
-__device__ inline float field_span(const float* partial, int field) {
+// Reduce the minmax partials of one field to the range source's extrema
+// (block-wide call: every thread of the workgroup must reach it).
+__device__ inline void field_extrema(const float* partial, int field, float* lo_out, float* hi_out) {
   __shared__ float red[2];
   if (threadIdx.x < 64) {
-    const int i = threadIdx.x;
-    float lo = partial[i * 4 + field * 2 + 0];
-    float hi = partial[i * 4 + field * 2 + 1];
+    float lo = INFINITY, hi = -INFINITY;
+    for (int i = threadIdx.x; i < kMinmaxBlocks; i += 64) {
+      lo = fminf(lo, partial[i * 4 + field * 2 + 0]);
+      hi = fmaxf(hi, partial[i * 4 + field * 2 + 1]);
+    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       lo = fminf(lo, __shfl_xor(lo, off));
       hi = fmaxf(hi, __shfl_xor(hi, off));
     }
-    if (i == 0) { red[0] = lo; red[1] = hi; }
+    if (threadIdx.x == 0) { red[0] = lo; red[1] = hi; }
   }
   __syncthreads();
-  return red[1] - red[0];
+  *lo_out = red[0];
+  *hi_out = red[1];
+}
+
+// max - min of the range source field (block-wide call).
+__device__ inline float field_span(const float* partial, int field) {
+  float lo, hi;
+  field_extrema(partial, field, &lo, &hi);
+  return hi - lo;
 }
 
 }  // namespace blfls

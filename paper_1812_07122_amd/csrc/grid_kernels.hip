@@ -54,25 +54,6 @@ __device__ __forceinline__ float grad_px(const float* __restrict__ x, int64_t pi
   return x[static_cast<int64_t>(i + 1 == H ? 0 : i + 1) * pitch + j] - v;
 }
 
-// Range source extrema of one field from the minmax partials (block-wide call).
-__device__ __forceinline__ void field_extrema(const float* partial, int field, float* lo_out, float* hi_out) {
-  __shared__ float red[2];
-  if (threadIdx.x < 64) {
-    const int i = threadIdx.x;
-    float lo = partial[i * 4 + field * 2 + 0];
-    float hi = partial[i * 4 + field * 2 + 1];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      lo = fminf(lo, __shfl_xor(lo, off));
-      hi = fmaxf(hi, __shfl_xor(hi, off));
-    }
-    if (i == 0) { red[0] = lo; red[1] = hi; }
-  }
-  __syncthreads();
-  *lo_out = red[0];
-  *hi_out = red[1];
-}
-
 __device__ __forceinline__ int find_grid_plane(const GridPlane* planes, int nplanes, int item) {
   int lo = 0, hi = nplanes - 1;
   while (lo < hi) {
