@@ -79,24 +79,62 @@ __device__ __forceinline__ bool field_scale(const NcPlane& P, int field, float* 
 
 // Mean of the values within transformed distance r of position t0 of a staged
 // line (values v[], increments d[]: d[t] joins t-1 and t); `right` / `left`
-// bound the walk (pixels to the image border and the halo radius).
+// bound the walk (pixels to the image border and the halo radius).  The walk
+// reads four steps' values and increments at a time (one LDS round trip per
+// four steps) and then applies them strictly in order, so the FP32 distance
+// is the same running sum as one step at a time.
 __device__ __forceinline__ float nc_window_mean(const float* v, const float* d, int stride, int t0, int right,
                                                 int left, float r) {
+  constexpr int kU = 4;
   float sum = v[t0 * stride];
   int cnt = 1;
   float dist = 0.0f;
-  for (int k = 1; k <= right; ++k) {
-    dist = __fadd_rn(dist, d[(t0 + k) * stride]);
-    if (!(dist <= r)) break;
-    sum += v[(t0 + k) * stride];
-    ++cnt;
+  bool live = right > 0;
+  for (int k = 1; live; k += kU) {
+    float dd[kU], vv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + min(k + u, right);
+      dd[u] = d[t * stride];
+      vv[u] = v[t * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (live) {
+        dist = __fadd_rn(dist, dd[u]);
+        if (dist <= r) {
+          sum += vv[u];
+          ++cnt;
+        } else {
+          live = false;
+        }
+        if (k + u >= right) live = false;
+      }
+    }
   }
   dist = 0.0f;
-  for (int k = 1; k <= left; ++k) {
-    dist = __fadd_rn(dist, d[(t0 - k + 1) * stride]);
-    if (!(dist <= r)) break;
-    sum += v[(t0 - k) * stride];
-    ++cnt;
+  live = left > 0;
+  for (int k = 1; live; k += kU) {
+    float dd[kU], vv[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int kk = min(k + u, left);
+      dd[u] = d[(t0 - kk + 1) * stride];
+      vv[u] = v[(t0 - kk) * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      if (live) {
+        dist = __fadd_rn(dist, dd[u]);
+        if (dist <= r) {
+          sum += vv[u];
+          ++cnt;
+        } else {
+          live = false;
+        }
+        if (k + u >= left) live = false;
+      }
+    }
   }
   return sum / static_cast<float>(cnt);
 }
@@ -174,13 +212,30 @@ __global__ void __launch_bounds__(256) nc_cols_kernel(const NcPlane* __restrict_
   const int64_t gp = P.g ? P.gpitch : P.pitch;
   const float* __restrict__ in = P.buf[src][field];
   if (j < W) {
-    for (int t = wave; t < rows; t += 4) {
-      const int m = i0 - R + t;
-      if (m >= 0 && m < H) {
-        sv[t * kSeg + lane] = in[static_cast<int64_t>(m) * W + j];
-        if (m >= 1)
-          sd[t * kSeg + lane] = dt_increment(grad_at(g, gp, H, W, m, j, field), grad_at(g, gp, H, W, m - 1, j, field),
-                                             P.a, inv, scaled);
+    // four rows per round: all loads of a round are issued before its LDS stores
+    for (int t0 = wave; t0 < rows; t0 += 16) {
+      float fv[4], dv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + 4 * u;
+        const int m = i0 - R + t;
+        fv[u] = 0.0f;
+        dv[u] = 0.0f;
+        if (t < rows && m >= 0 && m < H) {
+          fv[u] = in[static_cast<int64_t>(m) * W + j];
+          if (m >= 1)
+            dv[u] = dt_increment(grad_at(g, gp, H, W, m, j, field), grad_at(g, gp, H, W, m - 1, j, field), P.a, inv,
+                                 scaled);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int t = t0 + 4 * u;
+        const int m = i0 - R + t;
+        if (t < rows && m >= 0 && m < H) {
+          sv[t * kSeg + lane] = fv[u];
+          if (m >= 1) sd[t * kSeg + lane] = dv[u];
+        }
       }
     }
   }
