@@ -35,6 +35,8 @@ Readings taken where the paper is silent (each one is listed in the design notes
     of the domain transform on the same fields and guides; its borders do not
     wrap, it runs three iterations, and its window-membership decisions are
     taken in FP32 (see the NC section below);
+  * AMF-LS (Section III-D) replaces it by the adaptive-manifold filter, whose
+    recursive passes start at the borders (see the AMF section below);
   * iterations > 1 follow the rolling-guidance extension: iteration k filters
     the input's gradients with range weights from the gradients of u_{k-1}, and
     u_0 is the guidance image if one is given (optionally Gaussian-smoothed
@@ -55,6 +57,8 @@ __all__ = [
     "gaussian_blur", "smooth", "smooth_channel",
     "nc_schedule", "nc_increments", "nc_box_pass", "nc_filter", "nc_filter_bruteforce",
     "grid_cell", "grid_range", "grid_filter", "grid_filter_bruteforce",
+    "AMF_MAX_HEIGHT", "AMF_TAU", "amf_tree_height", "amf_rf_line_rows", "amf_blur",
+    "amf_filter", "amf_filter_dense",
 ]
 
 
@@ -470,6 +474,239 @@ def grid_filter_bruteforce(p, q, sigma_s, sigma_r):
 
 
 # ---------------------------------------------------------------------------
+# Adaptive-manifold filter (Section III-D: AMF-LS embeds it in place of the
+# BLF; its definition is Gastal and Oliveira, "Adaptive Manifolds for
+# Real-Time High-Dimensional Filtering", 2012)
+# ---------------------------------------------------------------------------
+#
+# The AMF approximates a Gaussian bilateral filter of p with range source q by
+# filtering on a few smooth images eta_k ("manifolds") that sample the range:
+# every pixel is splatted onto each manifold with the Gaussian weight
+# psi_k = exp(-(eta_k - q)^2 / (2 sigma_r'^2)), the splatted values (psi p and
+# psi) are blurred along the manifold by a recursive filter whose steps lengthen
+# with the manifold's own range differences, and each pixel reads the blurred
+# values back with the same weight: g = sum_k psi_k B_k(psi_k p) / sum_k psi_k
+# B_k(psi_k).  The manifolds form a binary tree: the root is a spatial low-pass
+# of q; the two children of a manifold are low-passes of q over the pixels
+# below and above it, each pixel weighted by 1 - psi (how poorly the parent
+# represents it).  Readings (listed in the design notes):
+#   * the range is a scalar, so the split of a cluster is the sign of q - eta;
+#   * sigma_r' = sigma_r / sqrt(2) in the splat, the slice and the blur's range
+#     term (the splat and slice weights multiply to the sigma_r Gaussian);
+#   * the blur is the domain transform's first-order recursive filter:
+#     y_j = (1 - a^{d_j}) x_j + a^{d_j} y_{j-1}, a = exp(-sqrt(2) / sigma_s), then
+#     the same from the right (step j -> j-1 uses d_j), along rows and then
+#     along columns, once; d_j = 1 + (sigma_s / sigma_r') |eta_j - eta_{j-1}| on a
+#     manifold and d_j = 1 for the low-passes; lines start at the image borders
+#     (no wrap), y_0 = x_0;
+#   * everything at full resolution (no downsampled manifolds);
+#   * tree height max(2, ceil(H_s L)), H_s = floor(log2 sigma_s) - 1,
+#     L = 1 - sigma_r, each clamped at 0, at most AMF_MAX_HEIGHT; 2^height - 1
+#     manifolds;
+#   * a child manifold is absent at pixels where its low-passed weight is below
+#     AMF_TAU (no cluster pixel within reach): there it takes no splat and no
+#     children, and the blur steps across it with d = 1;
+#   * pixels far from every manifold keep their value: g = p + alpha (num / den
+#     - p) with alpha = max_k psi_k, and g = p where den = 0;
+#   * with the normalisation flag the range differences (eta - q and the
+#     manifold steps) are scaled by 1/span(q), the guide field mapped to [0, 1];
+#   * sigma_r = inf: psi = 1, no children, d = 1: the normalised recursive
+#     filter of p.
+
+AMF_MAX_HEIGHT = 6
+AMF_TAU = 1e-20
+
+
+def amf_tree_height(sigma_s: float, sigma_r: float) -> int:
+    """max(2, ceil(H_s L)), H_s = floor(log2 sigma_s) - 1 and L = 1 - sigma_r clamped at 0,
+    capped at AMF_MAX_HEIGHT; the sigmas are the FP32 parameters, the arithmetic FP64."""
+    s = float(np.float32(sigma_s))
+    r = float(np.float32(sigma_r))
+    hs = max(0.0, math.floor(math.log2(s)) - 1.0)
+    lr = 0.0 if math.isinf(r) else max(0.0, 1.0 - r)
+    return int(min(AMF_MAX_HEIGHT, max(2, math.ceil(hs * lr))))
+
+
+def amf_rf_line_rows(X, alpha):
+    """Recursive filter along each row of every array in X: alpha[i, j] is the step
+    coefficient between columns j-1 and j (alpha[:, 0] unused); left to right, then right to
+    left."""
+    out = []
+    W = alpha.shape[1]
+    for x in X:
+        y = np.array(x, dtype=np.float64, copy=True)
+        for j in range(1, W):
+            y[:, j] = (1.0 - alpha[:, j]) * y[:, j] + alpha[:, j] * y[:, j - 1]
+        for j in range(W - 2, -1, -1):
+            y[:, j] = (1.0 - alpha[:, j + 1]) * y[:, j] + alpha[:, j + 1] * y[:, j + 1]
+        out.append(y)
+    return out
+
+
+def _amf_alpha(eta, sigma_s, sigma_r, axis, inv_span):
+    """Step coefficients a^d along `axis` (1: rows, 0: columns) over manifold eta; sigma_r = inf
+    gives the plain low-pass (d = 1).  Absent samples (NaN) step as if flat."""
+    a_log = -math.sqrt(2.0) / sigma_s
+    shape = eta.shape
+    if math.isinf(sigma_r):
+        return np.full(shape, math.exp(a_log))
+    diff = np.zeros(shape)
+    if axis == 1:
+        diff[:, 1:] = eta[:, 1:] - eta[:, :-1]
+    else:
+        diff[1:, :] = eta[1:, :] - eta[:-1, :]
+    diff = np.where(np.isnan(diff), 0.0, np.abs(diff)) * (1.0 if inv_span is None else float(inv_span))
+    sr1 = sigma_r / math.sqrt(2.0)
+    return np.exp(a_log * (1.0 + (sigma_s / sr1) * diff))
+
+
+def amf_blur(X, eta, sigma_s, sigma_r, inv_span=None):
+    """Rows then columns recursive filtering of the arrays in X over manifold eta (None: the
+    plain low-pass)."""
+    shape = X[0].shape
+    ref = np.zeros(shape) if eta is None else eta
+    ah = _amf_alpha(ref, sigma_s, math.inf if eta is None else sigma_r, 1, inv_span)
+    av = _amf_alpha(ref, sigma_s, math.inf if eta is None else sigma_r, 0, inv_span)
+    Y = amf_rf_line_rows(X, ah)
+    return [z.T for z in amf_rf_line_rows([y.T for y in Y], av.T)]
+
+
+def amf_filter(p: np.ndarray, q, sigma_s: float, sigma_r: float, height: int = 0,
+               inv_span=None, return_manifolds=False):
+    """Adaptive-manifold filter of field p with range source q (None: p itself).  height 0
+    takes amf_tree_height(sigma_s, sigma_r).  The sigmas are taken as FP32 values."""
+    p = np.asarray(p, dtype=np.float64)
+    qq = p if q is None else np.asarray(q, dtype=np.float64)
+    s = float(np.float32(sigma_s))
+    r = float(np.float32(sigma_r))
+    ht = amf_tree_height(s, r) if not height else int(height)
+    scale = 1.0 if inv_span is None else float(inv_span)
+    inf = math.isinf(r)
+    k = 0.0 if inf else 1.0 / (r * r)          # psi = exp(-(eta - q)^2 / (2 (r / sqrt 2)^2))
+    num = np.zeros_like(p)
+    den = np.zeros_like(p)
+    amax = np.zeros_like(p)
+    manifolds = []
+    stack = [(amf_blur([qq], None, s, r)[0], 1)]
+    while stack:
+        eta, level = stack.pop()
+        manifolds.append(eta)
+        present = ~np.isnan(eta)
+        dq = np.where(present, (eta - qq) * scale, 0.0)
+        psi = np.where(present, np.exp(-k * dq * dq), 0.0)
+        bn, bd = amf_blur([psi * p, psi], eta, s, r, inv_span)
+        num += psi * bn
+        den += psi * bd
+        amax = np.maximum(amax, psi)
+        if level < ht:
+            for below in (True, False):
+                side = (qq < eta) if below else (qq >= eta)
+                w = np.where(present & side, 1.0 - psi, 0.0)
+                hq, hw = amf_blur([w * qq, w], None, s, r)
+                child = np.full_like(p, np.nan)
+                ok = hw >= AMF_TAU
+                child[ok] = hq[ok] / hw[ok]
+                stack.append((child, level + 1))
+    safe = np.where(den > 0.0, den, 1.0)
+    g = np.where(den > 0.0, p + amax * (num / safe - p), p)
+    return (g, manifolds) if return_manifolds else g
+
+
+def amf_filter_dense(p, q, sigma_s, sigma_r, height=0, inv_span=None):
+    """The same filter through explicit linear operators (tiny inputs only): each recursive
+    pass is the dense matrix of its closed form, y = B F x with
+    F[i, k] = (1 - c_k) prod_{m=k+1..i} c_m (F[i, 0] = prod_{m=1..i} c_m) and
+    B[i, k] = (1 - c_{k+1}) prod_{m=i+1..k} c_m (B[i, n-1] = prod_{m=i+1..n-1} c_m); the
+    tree is walked breadth first with per-pixel loops."""
+    p = np.asarray(p, dtype=np.float64)
+    qq = p if q is None else np.asarray(q, dtype=np.float64)
+    Hn, Wn = p.shape
+    s = float(np.float32(sigma_s))
+    r = float(np.float32(sigma_r))
+    ht = amf_tree_height(s, r) if not height else int(height)
+    scale = 1.0 if inv_span is None else float(inv_span)
+    a = math.exp(-math.sqrt(2.0) / s)
+
+    def line_op(c):
+        n = len(c)
+        F = np.zeros((n, n))
+        B = np.zeros((n, n))
+        for i in range(n):
+            for kk in range(i + 1):
+                w = 1.0 if kk == 0 else 1.0 - c[kk]
+                for m in range(kk + 1, i + 1):
+                    w *= c[m]
+                F[i, kk] = w
+            for kk in range(i, n):
+                w = 1.0 if kk == n - 1 else 1.0 - c[kk + 1]
+                for m in range(i + 1, kk + 1):
+                    w *= c[m]
+                B[i, kk] = w
+        return B @ F
+
+    def coef(e0, e1):
+        if e0 is None or math.isinf(r) or math.isnan(e0) or math.isnan(e1):
+            return a
+        return a ** (1.0 + (s / (r / math.sqrt(2.0))) * abs(e1 - e0) * scale)
+
+    def blur2d(x, eta):
+        y = np.zeros((Hn, Wn))
+        for i in range(Hn):
+            c = [0.0] + [coef(None if eta is None else eta[i, j - 1], None if eta is None else eta[i, j])
+                         for j in range(1, Wn)]
+            y[i, :] = line_op(c) @ x[i, :]
+        z = np.zeros((Hn, Wn))
+        for j in range(Wn):
+            c = [0.0] + [coef(None if eta is None else eta[i - 1, j], None if eta is None else eta[i, j])
+                         for i in range(1, Hn)]
+            z[:, j] = line_op(c) @ y[:, j]
+        return z
+
+    num = np.zeros((Hn, Wn))
+    den = np.zeros((Hn, Wn))
+    amax = np.zeros((Hn, Wn))
+    level = [blur2d(qq, None)]
+    for depth in range(1, ht + 1):
+        nxt = []
+        for eta in level:
+            psi = np.zeros((Hn, Wn))
+            for i in range(Hn):
+                for j in range(Wn):
+                    if math.isnan(eta[i, j]):
+                        continue
+                    d = (eta[i, j] - qq[i, j]) * scale
+                    psi[i, j] = 1.0 if math.isinf(r) else math.exp(-d * d / (r * r))
+            bn = blur2d(psi * p, eta)
+            bd = blur2d(psi, eta)
+            num += psi * bn
+            den += psi * bd
+            amax = np.maximum(amax, psi)
+            if depth < ht:
+                for below in (True, False):
+                    w = np.zeros((Hn, Wn))
+                    for i in range(Hn):
+                        for j in range(Wn):
+                            e = eta[i, j]
+                            if not math.isnan(e) and ((qq[i, j] < e) if below else (qq[i, j] >= e)):
+                                w[i, j] = 1.0 - psi[i, j]
+                    hq = blur2d(w * qq, None)
+                    hw = blur2d(w, None)
+                    child = np.full((Hn, Wn), np.nan)
+                    for i in range(Hn):
+                        for j in range(Wn):
+                            if hw[i, j] >= AMF_TAU:
+                                child[i, j] = hq[i, j] / hw[i, j]
+                    nxt.append(child)
+        level = nxt
+    g = p.copy()
+    for i in range(Hn):
+        for j in range(Wn):
+            if den[i, j] > 0.0:
+                g[i, j] = p[i, j] + amax[i, j] * (num[i, j] / den[i, j] - p[i, j])
+    return g
+
+
+# ---------------------------------------------------------------------------
 # Fourier-domain least-squares solves, Eq. (6) and Eq. (8)
 # ---------------------------------------------------------------------------
 
@@ -579,10 +816,14 @@ def _field_inv_span(p, q, sigma_r, normalize):
     return np.float32(np.float32(1.0) / span32) if span32 > 0 else None
 
 
-def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iterations=3):
+def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iterations=3, amf_height=0):
     if filt == "grid":
         # the bilateral-grid approximation in place of the exact filter
         return grid_filter(p, q, sigma_s, sigma_r, _field_inv_span(p, q, sigma_r, normalize))
+    if filt == "amf":
+        # AMF-LS (Section III-D): the adaptive-manifold filter in place of the BLF
+        # (amf_height 0: the default tree-height rule)
+        return amf_filter(p, q, sigma_s, sigma_r, amf_height, _field_inv_span(p, q, sigma_r, normalize))
     if filt == "nc":
         # NC-LS (Section III-D): the NC filter in place of the BLF.  With the
         # normalisation of the experiments section the guide field g is mapped
@@ -606,17 +847,18 @@ def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iter
 
 
 def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None,
-                   normalize=False, sigma_guide=0.0, return_fields=False, filter="blf", nc_iterations=3):
+                   normalize=False, sigma_guide=0.0, return_fields=False, filter="blf", nc_iterations=3,
+                   amf_height=0):
     """BLF-LS on one channel (Section III-A two-step procedure, Section III-D extensions).
 
     Step 1 filters p_x, p_y with Eq. (1) (``filter="nc"``: the NC filter of the domain
-    transform, NC-LS; ``filter="grid"``: the bilateral-grid approximation of Eq. (1));
-    step 2 solves Eq. (8).  ``guide`` switches to joint filtering;
+    transform, NC-LS; ``filter="grid"``: the bilateral-grid approximation of Eq. (1);
+    ``filter="amf"``: the adaptive-manifold filter, AMF-LS); step 2 solves Eq. (8).  ``guide`` switches to joint filtering;
     ``iterations`` > 1 is rolling guidance.
     """
     f = np.asarray(f, dtype=np.float64)
     r = default_radius(sigma_s) if radius is None or radius < 0 else int(radius)
-    nc = filter in ("nc", "grid")   # these normalise through the guide field's span
+    nc = filter in ("nc", "grid", "amf")   # these normalise through the guide field's span
     lo, span = 0.0, 1.0
     if normalize and not nc:
         f, lo, span = _normalise_unit(f)
@@ -639,8 +881,8 @@ def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None
             qx = qy = None
         else:
             qx, qy = grad_x(prev), grad_y(prev)
-        gx = _filter_field(px, qx, sigma_s, sigma_r, r, normalize, filter, nc_iterations)
-        gy = _filter_field(py, qy, sigma_s, sigma_r, r, normalize, filter, nc_iterations)
+        gx = _filter_field(px, qx, sigma_s, sigma_r, r, normalize, filter, nc_iterations, amf_height)
+        gy = _filter_field(py, qy, sigma_s, sigma_r, r, normalize, filter, nc_iterations, amf_height)
         u = blfls_solve(f, gx, gy, lam)
         prev = u
     out = u * span + lo
@@ -650,17 +892,19 @@ def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None
 
 
 def smooth(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None, normalize=False,
-           sigma_guide=0.0, filter="blf", nc_iterations=3):
-    """BLF-LS (or NC-LS with ``filter="nc"``) on a (H, W) or (C, H, W) image; channels are
-    independent."""
+           sigma_guide=0.0, filter="blf", nc_iterations=3, amf_height=0):
+    """BLF-LS (or NC-LS, grid BLF-LS, AMF-LS with ``filter="nc"``, ``"grid"``, ``"amf"``) on a
+    (H, W) or (C, H, W) image; channels are independent."""
     f = np.asarray(f, dtype=np.float64)
     if f.ndim == 2:
         return smooth_channel(f, lam, sigma_s, sigma_r, radius, iterations, guide, normalize,
-                              sigma_guide, filter=filter, nc_iterations=nc_iterations)
+                              sigma_guide, filter=filter, nc_iterations=nc_iterations,
+                              amf_height=amf_height)
     g = None if guide is None else np.asarray(guide, dtype=np.float64)
     outs = []
     for c in range(f.shape[0]):
         gc = None if g is None else (g[c] if g.ndim == 3 else g)
         outs.append(smooth_channel(f[c], lam, sigma_s, sigma_r, radius, iterations, gc,
-                                   normalize, sigma_guide, filter=filter, nc_iterations=nc_iterations))
+                                   normalize, sigma_guide, filter=filter, nc_iterations=nc_iterations,
+                                   amf_height=amf_height))
     return np.stack(outs)

@@ -3,7 +3,9 @@
 Each mutation swaps one oracle function for a subtly wrong version: a backward
 difference, a missing conjugate, a wrong range-kernel sign, a dropped term, an
 NC filter with a wrong box schedule, wrapping windows or wrong increments, a
-bilateral grid with a wrong Gaussian or without the periodic extension.
+bilateral grid with a wrong Gaussian or without the periodic extension, an
+adaptive-manifold filter with a shifted backward coefficient, the unhalved range
+sigma in its blur, no column pass or no blend for far pixels.
 The pins of ``test_oracle.py`` must reject every one of them.
 """
 import math
@@ -16,6 +18,7 @@ from oracle import blfls_oracle as ob
 import tests.test_oracle as pins
 import tests.test_oracle_nc as nc_pins
 import tests.test_oracle_grid as grid_pins
+import tests.test_oracle_amf as amf_pins
 
 
 def _patch(monkeypatch, name, fn):
@@ -132,6 +135,58 @@ def _bad_grid_zero_border(p, q, sigma_s, sigma_r, inv_span=None):
     return _orig_grid_filter(big, qbig, sigma_s, sigma_r, inv_span)[H:2 * H, W:2 * W]
 
 
+def _bad_amf_rf_backward_index(X, alpha):
+    # the right-to-left pass takes the coefficient of its own sample, not of the step
+    out = []
+    W = alpha.shape[1]
+    for x in X:
+        y = np.array(x, dtype=np.float64, copy=True)
+        for j in range(1, W):
+            y[:, j] = (1.0 - alpha[:, j]) * y[:, j] + alpha[:, j] * y[:, j - 1]
+        for j in range(W - 2, -1, -1):
+            y[:, j] = (1.0 - alpha[:, j]) * y[:, j] + alpha[:, j] * y[:, j + 1]
+        out.append(y)
+    return out
+
+
+_orig_amf_alpha = ob._amf_alpha
+_orig_amf_blur = ob.amf_blur
+_orig_amf_filter = ob.amf_filter
+
+
+def _bad_amf_alpha_sigma(eta, sigma_s, sigma_r, axis, inv_span):
+    # the blur's range term with sigma_r instead of sigma_r / sqrt(2)
+    return _orig_amf_alpha(eta, sigma_s, sigma_r * math.sqrt(2.0), axis, inv_span)
+
+
+def _bad_amf_rows_only(X, eta, sigma_s, sigma_r, inv_span=None):
+    ref = np.zeros(X[0].shape) if eta is None else eta
+    ah = _orig_amf_alpha(ref, sigma_s, math.inf if eta is None else sigma_r, 1, inv_span)
+    return ob.amf_rf_line_rows(X, ah)
+
+
+def _bad_amf_no_blend(p, q, sigma_s, sigma_r, height=0, inv_span=None, return_manifolds=False):
+    # num / den everywhere: pixels far from every manifold are not kept
+    g, mans = _orig_amf_filter(p, q, sigma_s, sigma_r, height, inv_span, return_manifolds=True)
+    p = np.asarray(p, dtype=np.float64)
+    qq = p if q is None else np.asarray(q, dtype=np.float64)
+    s = float(np.float32(sigma_s))
+    r = float(np.float32(sigma_r))
+    k = 0.0 if math.isinf(r) else 1.0 / (r * r)
+    scale = 1.0 if inv_span is None else float(inv_span)
+    num = np.zeros_like(p)
+    den = np.zeros_like(p)
+    for eta in mans:
+        present = ~np.isnan(eta)
+        dq = np.where(present, (eta - qq) * scale, 0.0)
+        psi = np.where(present, np.exp(-k * dq * dq), 0.0)
+        bn, bd = ob.amf_blur([psi * p, psi], eta, s, r, inv_span)
+        num += psi * bn
+        den += psi * bd
+    g = np.where(den > 0, num / np.where(den > 0, den, 1.0), p)
+    return (g, mans) if return_manifolds else g
+
+
 MUTATIONS = {
     "backward_grad_x": ("grad_x", lambda f: f - np.roll(f, 1, axis=-1)),
     "grad_y_along_x": ("grad_y", lambda f: np.roll(f, -1, axis=-1) - f),
@@ -145,6 +200,10 @@ MUTATIONS = {
     "nc_increments_from_values": ("nc_increments", _bad_nc_increments),
     "grid_sigma_not_squared": ("_grid_taps", _bad_grid_taps),
     "grid_zero_border": ("grid_filter", _bad_grid_zero_border),
+    "amf_backward_coefficient_index": ("amf_rf_line_rows", _bad_amf_rf_backward_index),
+    "amf_blur_sigma_not_halved": ("_amf_alpha", _bad_amf_alpha_sigma),
+    "amf_blur_rows_only": ("amf_blur", _bad_amf_rows_only),
+    "amf_no_far_pixel_blend": ("amf_filter", _bad_amf_no_blend),
 }
 
 PIN_SUITE = [
@@ -163,6 +222,9 @@ PIN_SUITE = [
     nc_pins.test_nc_keeps_constants_and_clean_steps,
     lambda: grid_pins.test_grid_with_unit_cells_and_no_range_is_the_exact_gaussian(0.75),
     grid_pins.test_grid_commutes_with_whole_cell_shifts,
+    lambda: amf_pins.test_amf_matches_explicit_operators(6, 6, 3.0, 0.05, 3),
+    amf_pins.test_rf_step_that_cannot_be_crossed_splits_the_line,
+    amf_pins.test_range_off_is_the_separable_exponential_kernel,
 ]
 
 
