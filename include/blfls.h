@@ -78,7 +78,7 @@ typedef enum {
                             distance, r_k = 3 sigma_s 2^(N-k) / sqrt(4^N - 1) for round
                             k = 1..N, windows stopping at the image borders.  Window
                             membership is decided in FP32. */
-  BLFLS_FILTER_GRID = 2  /* the bilateral-grid approximation of Eq. (1) (Paris and Durand
+  BLFLS_FILTER_GRID = 2, /* the bilateral-grid approximation of Eq. (1) (Paris and Durand
                             2006), the fast filter of the paper's experiments: p and 1 are
                             splatted into cells of s = floor(sigma_s + 1/2) pixels by one
                             range cell (1/sigma_r, widened so that at most 32 bins span the
@@ -86,6 +86,21 @@ typedef enum {
                             cells across and one range cell deep (taps to +-2 cells), and
                             read back by trilinear interpolation; periodic like the exact
                             filter.  Ignores radius; s at most 32 pixels. */
+  BLFLS_FILTER_AMF = 3   /* the adaptive-manifold filter (Gastal and Oliveira 2012) in its
+                            place: AMF-LS (Section III-D).  A binary tree of manifolds
+                            (images in the range space): the root is a spatial low-pass of q;
+                            the two children of a manifold eta are low-passes of q over the
+                            pixels with q < eta and q >= eta, weighted by 1 - psi and divided
+                            (absent where that weight's low-pass is under 1e-20).  On each
+                            manifold, psi = exp(-(eta - q)^2 / sigma_r^2) weights a splat of
+                            (psi p, psi), a recursive blur along the manifold and a slice:
+                            g = p + max_k psi_k (sum psi_k Bn_k / sum psi_k Bd_k - p).
+                            Blur and low-passes are the domain transform's first-order
+                            recursive filter y_j = c y_{j-1} + (1 - c) x_j with
+                            c = exp(-sqrt(2) d / sigma_s), left to right then right to left,
+                            rows then columns, not wrapping; d = 1 + (sqrt(2) sigma_s / sigma_r)
+                            |eta_j - eta_{j-1}| on a manifold, 1 for the low-passes.  Full
+                            resolution.  Ignores radius.  Needs blfls_workspace_size bytes. */
 } blfls_filter;
 
 /* Parameters of Eq. (1) and Eq. (7). */
@@ -107,8 +122,11 @@ typedef struct {
   int32_t filter;    /* blfls_filter.  BLFLS_FILTER_NC ignores radius; its first box
                         radius r_1 must be at most BLFLS_MAX_RADIUS pixels
                         (sigma_s <= 21 for N = 3), else BLFLS_E_INVALID. */
-  int32_t filter_iterations; /* NC rounds N of a horizontal and a vertical box pass,
-                        1..8; 0 selects 3.  Must be 0 for the other filters. */
+  int32_t filter_iterations; /* NC: rounds N of a horizontal and a vertical box pass,
+                        1..8; 0 selects 3.  AMF: manifold tree height 1..6 (2^h - 1
+                        manifolds); 0 selects max(2, ceil(H_s L)), H_s = floor(log2
+                        sigma_s) - 1, L = 1 - sigma_r, both clamped at 0, at most 6.
+                        Must be 0 for the other filters. */
 } blfls_params;
 
 #define BLFLS_MAX_RADIUS 32
@@ -130,8 +148,16 @@ typedef struct blfls_plan_s *blfls_plan_t;
 blfls_status blfls_plan(blfls_plan_t *out, int32_t H, int32_t W, int32_t C,
                         blfls_precision precision, size_t *workspace_bytes);
 
-/* Workspace bytes a plan needs (same value blfls_plan reported). */
+/* Workspace bytes a plan needs (same value blfls_plan reported).  Enough for
+ * every filter except BLFLS_FILTER_AMF. */
 blfls_status blfls_plan_workspace_size(blfls_plan_t plan, size_t *workspace_bytes);
+
+/* Workspace bytes blfls_smooth needs for these parameters: the plan's size, plus
+ * for BLFLS_FILTER_AMF the manifold arrays ((6 + 2 h) x H x W floats per gradient field
+ * and a little more, h the tree height).  Validates params like
+ * blfls_smooth (BLFLS_E_INVALID). */
+blfls_status blfls_workspace_size(blfls_plan_t plan, const blfls_params *params,
+                                  size_t *workspace_bytes);
 
 /* Release a plan's tables.  The caller must ensure no queued work uses it. */
 blfls_status blfls_plan_destroy(blfls_plan_t plan);
@@ -145,8 +171,9 @@ blfls_status blfls_plan_destroy(blfls_plan_t plan);
  *              gradients of the guide, the filtered values from f's gradients.
  *   u          device, [C][H][pitch] FP32, written.  Must not overlap f, guide
  *              or the workspace (BLFLS_E_INVALID).
- *   workspace  device, at least the plan's workspace bytes, 256-byte aligned;
- *              its contents on entry are ignored.
+ *   workspace  device, at least blfls_workspace_size(plan, params) bytes (the
+ *              plan's workspace bytes for every filter but the AMF), 256-byte
+ *              aligned; its contents on entry are ignored.
  *   stream     hipStream_t to queue on (NULL = the null stream).
  * All work is queued asynchronously; the call does not synchronise.  Errors
  * found on the host are returned before anything is queued. */

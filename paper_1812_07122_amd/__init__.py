@@ -97,6 +97,8 @@ SIGNATURES = [
     ("blfls_plan", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32,
                                   ctypes.c_int32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]),
     ("blfls_plan_workspace_size", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    ("blfls_workspace_size", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params),
+                                            ctypes.POINTER(ctypes.c_size_t)]),
     ("blfls_plan_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("blfls_smooth", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
@@ -143,15 +145,16 @@ def _check(status: int):
         raise BlflsError(status, msg.decode() if msg else "")
 
 
-FILTERS = {"blf": 0, "nc": 1, "grid": 2}
+FILTERS = {"blf": 0, "nc": 1, "grid": 2, "amf": 3}
 
 
 def make_params(lam: float, sigma_s: float, sigma_r: float, radius: int = -1, iterations: int = 1,
                 normalize: bool = False, sigma_guide: float = 0.0, filter: str = "blf",
                 filter_iterations: int = 0) -> Params:
     """``filter``: "blf" (BLF-LS), "nc" (NC-LS: the domain transform's normalized
-    convolution in place of the BLF; ``filter_iterations`` rounds, 0 = 3) or "grid" (the
-    bilateral-grid approximation of the BLF)."""
+    convolution in place of the BLF; ``filter_iterations`` rounds, 0 = 3), "grid" (the
+    bilateral-grid approximation of the BLF) or "amf" (AMF-LS: the adaptive-manifold
+    filter; ``filter_iterations`` is the manifold tree height, 0 = the default rule)."""
     if filter not in FILTERS:
         raise ValueError(f"filter must be one of {sorted(FILTERS)}")
     return Params(float(lam), float(sigma_s), float(sigma_r), int(radius), int(iterations),
@@ -190,11 +193,21 @@ class Plan:
             _check(lib().blfls_plan(ctypes.byref(self._handle), self.H, self.W, self.C, self.precision,
                                     ctypes.byref(ws)))
         self.device = dev
-        self.workspace_bytes = int(ws.value)
+        self._alloc_workspace(int(ws.value))
+
+    def _alloc_workspace(self, nbytes: int):
+        import torch
         # 256-byte alignment: over-allocate and offset
-        self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        self.workspace_bytes = nbytes
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self._ws.data_ptr()
         self.workspace_ptr = (base + 255) // 256 * 256
+
+    def workspace_for(self, prm: Params) -> int:
+        """Workspace bytes ``blfls_smooth`` needs for these parameters (larger for the AMF)."""
+        n = ctypes.c_size_t()
+        _check(lib().blfls_workspace_size(self._handle, ctypes.byref(prm), ctypes.byref(n)))
+        return int(n.value)
 
     def smooth(self, f, lam: float, sigma_s: float, sigma_r: float, radius: int = -1, iterations: int = 1,
                guide=None, normalize: bool = False, sigma_guide: float = 0.0, out=None, stream=None,
@@ -214,6 +227,11 @@ class Plan:
         u = torch.empty_like(f3) if out is None else out
         prm = make_params(lam, sigma_s, sigma_r, radius, iterations, normalize, sigma_guide, filter,
                           filter_iterations)
+        need = self.workspace_for(prm)
+        if need > self.workspace_bytes:
+            # work queued earlier (on any stream) may still use the old buffer
+            torch.cuda.synchronize(self.device)
+            self._alloc_workspace(need)
         _check(lib().blfls_smooth(self._handle, ctypes.byref(prm), ctypes.c_void_p(f3.data_ptr()),
                                   ctypes.c_void_p(g3.data_ptr() if g3 is not None else 0),
                                   ctypes.c_void_p(u.data_ptr()), self.W, ctypes.c_void_p(self.workspace_ptr),
@@ -242,7 +260,9 @@ def smooth(f, lam: float = 1024.0, sigma_s: float = 3.0, sigma_r: float = 0.1, r
 
     lam is lambda of Eq. (7) (the paper's default is 1024), sigma_s / sigma_r the
     spatial and range sigmas of Eq. (1), radius -1 means ceil(3 sigma_s).
-    filter="nc" runs NC-LS (Section III-D) with filter_iterations rounds (0 = 3).
+    filter="nc" runs NC-LS (Section III-D) with filter_iterations rounds (0 = 3);
+    filter="grid" the bilateral-grid approximation; filter="amf" AMF-LS with a manifold
+    tree of height filter_iterations (0 = the default rule).
     """
     C, H, W = (1, *f.shape) if f.dim() == 2 else tuple(f.shape)
     key = (C, H, W, _PRECISIONS[precision], f.device.index)

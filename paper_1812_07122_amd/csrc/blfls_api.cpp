@@ -8,6 +8,7 @@
 // kernels on the caller's stream without synchronising.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -111,6 +112,46 @@ double nc_box_radius(float sigma_s, int n, int k) {
 // Farthest pixel offset an NC box of FP32 radius r can reach (increments are >= 1).
 int nc_pixel_radius(float r) { return static_cast<int>(std::floor(static_cast<double>(r))); }
 
+// Manifold tree height: filter_iterations if set, else max(2, ceil(H_s L)) with
+// H_s = floor(log2 sigma_s) - 1 and L = 1 - sigma_r, each clamped at 0, capped
+// at kAmfMaxHeight (FP64 from the FP32 sigmas).
+int amf_tree_height(const blfls_params& p) {
+  if (p.filter_iterations > 0) return p.filter_iterations;
+  const double hs = std::max(0.0, std::floor(std::log2(static_cast<double>(p.sigma_s))) - 1.0);
+  const double lr = std::isinf(p.sigma_r) ? 0.0 : std::max(0.0, 1.0 - static_cast<double>(p.sigma_r));
+  return static_cast<int>(std::min<double>(kAmfMaxHeight, std::max(2.0, std::ceil(hs * lr))));
+}
+
+namespace {
+// Layout of the adaptive-manifold arrays after the plan's workspace: offsets
+// in floats from the region's start (each array 64-float aligned).
+struct AmfLayout {
+  size_t acc, tmp, slots, sum, carry_f, carry_b, inv, floats;
+};
+
+AmfLayout amf_layout(const blfls_plan_s* plan, int height) {
+  const size_t P = 2 * static_cast<size_t>(plan->C), N = static_cast<size_t>(plan->H) * plan->W;
+  const size_t line = P * amf_segments(plan->H) * static_cast<size_t>(plan->W);
+  AmfLayout L{};
+  size_t w = 0;
+  auto take = [&](size_t n) { const size_t at = w; w = (w + n + 63) / 64 * 64; return at; };
+  L.acc = take(3 * P * N);
+  L.tmp = take(4 * P * N);
+  L.slots = take(static_cast<size_t>(amf_slots(height)) * P * N);
+  L.sum = take(5 * line);
+  L.carry_f = take(4 * line);
+  L.carry_b = take(4 * line);
+  L.inv = take(P);
+  L.floats = w;
+  return L;
+}
+}  // namespace
+
+size_t request_workspace_bytes(const blfls_plan_s* plan, const blfls_params& p) {
+  if (p.filter != BLFLS_FILTER_AMF) return plan->ws_bytes;
+  return plan->ws_bytes + amf_layout(plan, amf_tree_height(p)).floats * sizeof(float);
+}
+
 blfls_status set_error(blfls_status st, const std::string& msg) {
   g_last_error = msg;
   return st;
@@ -140,17 +181,20 @@ blfls_status check_params(const blfls_params* p, int* radius_out) {
   if (p->iterations < 1) return set_error(BLFLS_E_INVALID, "iterations must be >= 1");
   if (!std::isfinite(p->sigma_guide) || p->sigma_guide < 0.0f) return set_error(BLFLS_E_INVALID, "sigma_guide must be finite and >= 0");
   if (p->flags & ~BLFLS_F_NORMALIZE) return set_error(BLFLS_E_INVALID, "unknown flag bits");
-  if (p->filter != BLFLS_FILTER_BLF && p->filter != BLFLS_FILTER_NC && p->filter != BLFLS_FILTER_GRID)
+  if (p->filter != BLFLS_FILTER_BLF && p->filter != BLFLS_FILTER_NC && p->filter != BLFLS_FILTER_GRID &&
+      p->filter != BLFLS_FILTER_AMF)
     return set_error(BLFLS_E_INVALID, "unknown filter");
   if (p->filter_iterations < 0 || p->filter_iterations > 8)
     return set_error(BLFLS_E_INVALID, "filter_iterations must be in [0, 8]");
-  if (p->filter != BLFLS_FILTER_NC && p->filter_iterations != 0)
-    return set_error(BLFLS_E_INVALID, "filter_iterations applies to the NC filter only");
+  if (p->filter == BLFLS_FILTER_AMF && p->filter_iterations > kAmfMaxHeight)
+    return set_error(BLFLS_E_INVALID, "the AMF tree height (filter_iterations) must be in [0, 6]");
+  if (p->filter != BLFLS_FILTER_NC && p->filter != BLFLS_FILTER_AMF && p->filter_iterations != 0)
+    return set_error(BLFLS_E_INVALID, "filter_iterations applies to the NC and AMF filters only");
   if (p->filter == BLFLS_FILTER_GRID && grid_cell_size(p->sigma_s) > kGridMaxCell)
     return set_error(BLFLS_E_INVALID, "sigma_s too large for the bilateral grid (cell above 32 pixels)");
   int r = p->radius;
   if (r < -1) return set_error(BLFLS_E_INVALID, "radius must be >= 0 or -1");
-  if (p->filter == BLFLS_FILTER_GRID) {
+  if (p->filter == BLFLS_FILTER_GRID || p->filter == BLFLS_FILTER_AMF) {
     r = 0;
   } else if (p->filter == BLFLS_FILTER_NC) {
     const int n = p->filter_iterations ? p->filter_iterations : 3;
@@ -177,8 +221,9 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   std::call_once(init_once, [] {
     init_err = fft_init_kernels();
     if (init_err == hipSuccess) init_err = nc_init_kernels();
+    if (init_err == hipSuccess) init_err = amf_init_kernels();
   });
-  if (init_err != hipSuccess) return hip_error(init_err, "FFT kernel attributes");
+  if (init_err != hipSuccess) return hip_error(init_err, "kernel attributes");
   auto* p = new (std::nothrow) blfls_plan_s();
   if (!p) return set_error(BLFLS_E_NOMEM, "host allocation failed");
   p->H = H; p->W = W; p->C = C; p->M = W / 2; p->precision = prec;
@@ -329,6 +374,8 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
   out->grid_next.assign(C, GridPlane{});
   out->nc_first.assign(C, NcPlane{});
   out->nc_next.assign(C, NcPlane{});
+  out->amf_first.assign(2 * C, AmfPlane{});
+  out->amf_next.assign(2 * C, AmfPlane{});
   out->filter = prm.filter;
   out->nc_rounds = prm.filter == BLFLS_FILTER_NC ? (prm.filter_iterations ? prm.filter_iterations : 3) : 0;
   for (int k = 1; k <= out->nc_rounds; ++k) {
@@ -431,6 +478,19 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
       G2.sig_xy = static_cast<float>(static_cast<double>(prm.sigma_s) / sc);
       G2.normalize = (prm.flags & BLFLS_F_NORMALIZE) != 0 ? 1 : 0;
     }
+    for (int it = 0; it < 2; ++it) {
+      const BlfPlane& B = it == 0 ? out->blf_first[ch] : out->blf_next[ch];
+      for (int field = 0; field < 2; ++field) {
+        AmfPlane& A = (it == 0 ? out->amf_first : out->amf_next)[2 * ch + field];
+        A.f = fc;
+        A.g = B.g;
+        A.pitch = pitch;
+        A.gpitch = B.gpitch;
+        A.out = field ? ry : rx;
+        A.minmax = B.minmax;
+        A.field = field;
+      }
+    }
     FftPlane& F = out->fft[ch];
     F.rx = rx; F.ry = ry;
     F.spec = reinterpret_cast<float2*>(wsb + plan->off_spec) + static_cast<size_t>(ch) * (M + 1) * H;
@@ -446,6 +506,29 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
     F.m_div = make_fastdiv(static_cast<uint32_t>(M));
     F.h_div = make_fastdiv(static_cast<uint32_t>(H));
     F.rb_div = make_fastdiv(static_cast<uint32_t>(plan->rb));
+  }
+  if (prm.filter == BLFLS_FILTER_AMF) {
+    // the manifold arrays follow the plan's workspace
+    const int height = amf_tree_height(prm);
+    const AmfLayout L = amf_layout(plan, height);
+    float* base = reinterpret_cast<float*>(wsb + plan->ws_bytes);
+    AmfGeom& G = out->amf_geom;
+    G = AmfGeom{};
+    G.P = 2 * C; G.H = H; G.W = W; G.S = amf_segments(H);
+    G.a = static_cast<float>(std::exp(-std::sqrt(2.0) / ss));
+    G.c0 = static_cast<float>(-std::sqrt(2.0) * log2e / ss);
+    G.c1 = range_on ? static_cast<float>(-2.0 * log2e / static_cast<double>(prm.sigma_r)) : 0.0f;
+    G.kpsi = range_on ? static_cast<float>(log2e / (static_cast<double>(prm.sigma_r) * prm.sigma_r)) : 0.0f;
+    G.tau = 1e-20f;
+    G.acc = base + L.acc;
+    G.tmp = base + L.tmp;
+    G.sum = base + L.sum;
+    G.carry_f = base + L.carry_f;
+    G.carry_b = base + L.carry_b;
+    G.inv = base + L.inv;
+    G.ft = plan->precision == BLFLS_FP32 ? kF32 : plan->precision == BLFLS_MIXED_BF16 ? kBF16 : kF16;
+    out->amf_slots = base + L.slots;
+    out->amf_height = height;
   }
 }
 
@@ -472,6 +555,12 @@ hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, cons
       const GridPlane* gp = first ? dev.grid_first : dev.grid_next;
       const GridPlane& g0 = first ? rd.grid_first[0] : rd.grid_next[0];
       e = launch_grid(gp, C, 2 * C * g0.tile_count, ft, s);
+      if (e != hipSuccess) return e;
+    } else if (rd.filter == BLFLS_FILTER_AMF) {
+      StageTimer t(BLFLS_STAGE_BLF, s);
+      AmfGeom G = rd.amf_geom;
+      G.planes = first ? dev.amf_first : dev.amf_next;
+      e = launch_amf(G, rd.amf_slots, rd.amf_height, s);
       if (e != hipSuccess) return e;
     } else if (rd.filter == BLFLS_FILTER_NC) {
       StageTimer t(BLFLS_STAGE_BLF, s);
@@ -537,6 +626,17 @@ blfls_status blfls_plan_workspace_size(blfls_plan_t plan, size_t* workspace_byte
   return BLFLS_OK;
 }
 
+blfls_status blfls_workspace_size(blfls_plan_t plan, const blfls_params* params, size_t* workspace_bytes) {
+  g_last_error.clear();
+  if (plan == nullptr || params == nullptr || workspace_bytes == nullptr)
+    return set_error(BLFLS_E_INVALID, "NULL argument");
+  int radius = 0;
+  const blfls_status st = check_params(params, &radius);
+  if (st != BLFLS_OK) return st;
+  *workspace_bytes = request_workspace_bytes(plan, *params);
+  return BLFLS_OK;
+}
+
 blfls_status blfls_plan_destroy(blfls_plan_t plan) {
   g_last_error.clear();
   if (plan == nullptr) return set_error(BLFLS_E_INVALID, "plan is NULL");
@@ -562,7 +662,7 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   if (st != BLFLS_OK) return st;
   const size_t img_bytes = static_cast<size_t>(plan->C) * plan->H * pitch * sizeof(float);
   if (overlaps(u, img_bytes, f, img_bytes) || (guide && overlaps(u, img_bytes, guide, img_bytes)) ||
-      overlaps(u, img_bytes, workspace, plan->ws_bytes))
+      overlaps(u, img_bytes, workspace, request_workspace_bytes(plan, *params)))
     return set_error(BLFLS_E_INVALID, "u must not overlap f, guide or the workspace");
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
@@ -597,6 +697,9 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   } else if (rd.filter == BLFLS_FILTER_GRID) {
     o_n1 = place(rd.grid_first.data(), C * sizeof(GridPlane));
     o_n2 = place(rd.grid_next.data(), C * sizeof(GridPlane));
+  } else if (rd.filter == BLFLS_FILTER_AMF) {
+    o_n1 = place(rd.amf_first.data(), 2 * C * sizeof(AmfPlane));
+    o_n2 = place(rd.amf_next.data(), 2 * C * sizeof(AmfPlane));
   }
   if (blob.size() > kDescBytes) return set_error(BLFLS_E_INVALID, "descriptor area overflow");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -618,6 +721,9 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   } else if (rd.filter == BLFLS_FILTER_GRID) {
     dd.grid_first = reinterpret_cast<const GridPlane*>(dbase + o_n1);
     dd.grid_next = reinterpret_cast<const GridPlane*>(dbase + o_n2);
+  } else if (rd.filter == BLFLS_FILTER_AMF) {
+    dd.amf_first = reinterpret_cast<const AmfPlane*>(dbase + o_n1);
+    dd.amf_next = reinterpret_cast<const AmfPlane*>(dbase + o_n2);
   }
   e = enqueue_request(plan, rd, dd, s);
   if (e != hipSuccess) return hip_error(e, "kernel launch");

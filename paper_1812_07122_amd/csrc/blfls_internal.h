@@ -122,6 +122,41 @@ struct NcPlane {
   int pad_;
 };
 
+// One gradient field of one channel for the adaptive-manifold filter.
+constexpr int kAmfMaxHeight = 6;        // manifold tree height at most
+constexpr int kAmfSeg = 32;             // rows per segment of the column scans
+struct AmfPlane {
+  const float* f;        // image whose gradients are filtered, [H][pitch]
+  const float* g;        // range-source image or nullptr = f
+  int64_t pitch;
+  int64_t gpitch;
+  void* out;             // residual r = AMF(p) - p of this field, packed [H][W], field type
+  const float* minmax;   // range-source gradient extrema partials (normalise flag) or nullptr
+  int field;             // 0: x, 1: y
+  int pad_;
+};
+
+// One launch's view of the adaptive-manifold workspace (passed by value).
+// Every array holds the P = 2C fields back to back, [P][H][W] per plane.
+struct AmfGeom {
+  const AmfPlane* planes;
+  int P, H, W, S;        // fields, image size, column-scan segments (ceil(H / kAmfSeg))
+  float a;               // step coefficient of the low-passes, exp(-sqrt(2) / sigma_s)
+  float c0, c1;          // manifold step exp2(c0 + c1 |d eta| inv)
+  float kpsi;            // splat / slice weight exp2(-kpsi ((eta - q) inv)^2)
+  float tau;             // a child manifold exists where its low-passed weight is >= tau
+  float* acc;            // [3][P][H][W]: sum psi Bn, sum psi Bd, max psi
+  float* tmp;            // [4][P][H][W]: row-pass outputs
+  const float* eta;      // manifold being splatted or split
+  float* eta_out;        // root pass: the root manifold; split: [2][P][H][W] children
+  float* sum;            // [P][S][5][W] segment summaries of a column scan
+  float* carry_f;        // [P][S][4][W] carries into each segment, top to bottom
+  float* carry_b;        // [P][S][4][W] and bottom to top
+  float* inv;            // [P] range scale of each field (1/span with the normalise flag, else 1)
+  int ft;                // residual field type
+  int first, last;       // this slice starts / completes the sums
+};
+
 // One channel plane for the bilateral-grid approximation of Eq. (1): both
 // gradient fields of one channel, tiles of 8 x 8 grid cells per field.
 constexpr int kGridZMax = 32;           // range bins at most

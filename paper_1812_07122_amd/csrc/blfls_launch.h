@@ -50,6 +50,15 @@ int grid_cell_size(float sigma_s);
 int grid_tiles_x(int W, int s);
 int grid_tiles_y(int H, int s);
 hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int field_type, hipStream_t s);
+
+// Adaptive-manifold filter: manifold slots of a tree of the given height,
+// column-scan segments of an image of H rows, the kernels' LDS limits, and
+// the whole filter (prep, root low-pass, depth-first walk of the manifolds;
+// the last slice writes the residual fields).
+int amf_slots(int height);
+int amf_segments(int H);
+hipError_t amf_init_kernels();
+hipError_t launch_amf(const AmfGeom& geom, float* slots, int height, hipStream_t s);
 hipError_t launch_minmax(const AuxPlane* planes, int nplanes, hipStream_t s, WorkHeader* work = nullptr,
                          int grid = 0);
 hipError_t launch_gauss(const AuxPlane* planes, int nplanes, int64_t max_pixels, hipStream_t s,

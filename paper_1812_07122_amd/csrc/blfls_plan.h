@@ -54,6 +54,12 @@ int nc_pixel_radius(float r);
 blfls_status check_shape(int H, int W, int C);
 blfls_status check_params(const blfls_params* p, int* radius_out);
 
+// Adaptive-manifold filter: tree height of a request (filter_iterations, or
+// the default rule from sigma_s and sigma_r), and the workspace bytes a
+// request needs (the plan's, plus the manifold arrays for the AMF).
+int amf_tree_height(const blfls_params& p);
+size_t request_workspace_bytes(const blfls_plan_s* plan, const blfls_params& p);
+
 // Plans keyed by shape, created on demand (used by the server).
 blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s** out);
 void plan_free(blfls_plan_s* p);
@@ -71,6 +77,11 @@ struct RequestDesc {
   std::vector<GridPlane> grid_next;  // and iterations 2..n
   std::vector<NcPlane> nc_first;     // NC-LS: the NC passes of iteration 1
   std::vector<NcPlane> nc_next;      // and of iterations 2..n
+  std::vector<AmfPlane> amf_first;   // AMF-LS: both fields of each channel, iteration 1
+  std::vector<AmfPlane> amf_next;    // and iterations 2..n
+  AmfGeom amf_geom{};                // workspace arrays and constants (planes set at launch)
+  float* amf_slots = nullptr;        // manifold slots
+  int amf_height = 0;                // manifold tree height
   int filter = BLFLS_FILTER_BLF;
   int nc_rounds = 0;                 // NC rounds (a row and a column pass each)
   float nc_r[8] = {};                // box radius of each round (FP32)
@@ -103,6 +114,8 @@ struct DeviceDesc {
   const GridPlane* grid_next = nullptr;
   const NcPlane* nc_first = nullptr;
   const NcPlane* nc_next = nullptr;
+  const AmfPlane* amf_first = nullptr;
+  const AmfPlane* amf_next = nullptr;
 };
 hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, const DeviceDesc& dev,
                            hipStream_t s);

@@ -55,6 +55,7 @@ def test_null_arguments():
     assert L.blfls_smooth(None, ctypes.byref(prm), None, None, None, 8, None, None) == -1
     assert L.blfls_plan(None, 8, 8, 1, 0, None) == -1
     assert L.blfls_plan_destroy(None) == -1
+    assert L.blfls_workspace_size(None, ctypes.byref(prm), None) == -1
     assert L.blfls_poll(None, 1, None, None) == -1
     assert L.blfls_submit(None, None, None) == -1
     assert L.blfls_server_destroy(None) == -1
