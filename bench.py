@@ -1,6 +1,6 @@
 """Benchmark of the BLF-LS hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rgb1024|uhd|serve|joint|copy]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rgb1024|uhd|serve|joint|nc|grid|amf|copy]
 
 A step is one whole BLF-LS pass (Eq. (1) on both gradient fields of every
 channel, then the Eq. (8) solve) over one image whose input already sits in
@@ -19,6 +19,8 @@ Other workloads (each prints its own JSON line):
          BLF, Section III-D) on the 1024x1024 RGB image, plain and rolling
   grid   the bilateral-grid approximation on the 3840x2160 RGB workload, against
          the exact filter
+  amf    AMF-LS (the adaptive-manifold filter in place of the BLF) on the
+         1024x1024 RGB image, trees of height 2 and 3
 """
 from __future__ import annotations
 
@@ -47,7 +49,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="rgb1024", choices=["rgb1024", "uhd", "serve", "joint", "nc", "grid", "copy"])
+    ap.add_argument("--workload", default="rgb1024", choices=["rgb1024", "uhd", "serve", "joint", "nc", "grid", "amf", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=2000)
     return ap.parse_args()

@@ -236,10 +236,13 @@ __global__ void __launch_bounds__(kThreads) amf_cols_kernel(AmfGeom G) {
   const size_t col = static_cast<size_t>(p) * HW + j;
   const float inv = G.inv[p];
 
-  // k[t]: step into row i0 + t from the row above (0 at the image's first row
-  // and below its last); t = n is the step into the next segment
-  float k[kAmfSeg + 1];
-  float ev[kAmfSeg];
+  // kk(t): step into row i0 + t from the row above (0 at the image's first row
+  // and below its last); t = n is the step into the next segment.  The
+  // manifold blur keeps its per-column steps in registers; the low-passes'
+  // uniform steps are formed where they are used (an array of them would sit
+  // in scalar registers).
+  float k[STEPS ? kAmfSeg + 1 : 1];
+  float ev[STEPS ? kAmfSeg : 1];
   if constexpr (STEPS) {
     float e_prev = i0 > 0 ? G.eta[col + static_cast<size_t>(i0 - 1) * W] : 0.0f;
 #pragma unroll
@@ -254,10 +257,11 @@ __global__ void __launch_bounds__(kThreads) amf_cols_kernel(AmfGeom G) {
         if (t < kAmfSeg) ev[t] = 0.0f;
       }
     }
-  } else {
-#pragma unroll
-    for (int t = 0; t <= kAmfSeg; ++t) k[t] = (i0 + t == 0 || i0 + t >= H || t > n) ? 0.0f : G.a;
   }
+  auto kk = [&](int t) -> float {
+    if constexpr (STEPS) return k[t];
+    return (i0 + t == 0 || i0 + t >= H) ? 0.0f : G.a;
+  };
 
   float* sum = G.sum + static_cast<size_t>(p * S + s) * 5 * W + j;
   if constexpr (PHASE == 0) {
@@ -271,9 +275,9 @@ __global__ void __launch_bounds__(kThreads) amf_cols_kernel(AmfGeom G) {
 #pragma unroll
         for (int c = 0; c < N; ++c) {
           const float x = G.tmp[c * PN + idx];
-          y[c] = fmaf(k[t], y[c] - x, x);
+          y[c] = fmaf(kk(t), y[c] - x, x);
         }
-        A *= k[t];
+        A *= kk(t);
       }
     }
     sum[0] = A;
@@ -292,7 +296,7 @@ __global__ void __launch_bounds__(kThreads) amf_cols_kernel(AmfGeom G) {
 #pragma unroll
         for (int c = 0; c < N; ++c) {
           const float x = G.tmp[c * PN + idx];
-          y[c] = fmaf(k[t], y[c] - x, x);
+          y[c] = fmaf(kk(t), y[c] - x, x);
           ys[t][c] = y[c];
         }
       }
@@ -305,8 +309,8 @@ __global__ void __launch_bounds__(kThreads) amf_cols_kernel(AmfGeom G) {
       for (int t = kAmfSeg - 1; t >= 0; --t) {
         if (t < n) {
 #pragma unroll
-          for (int c = 0; c < N; ++c) z[c] = fmaf(k[t + 1], z[c] - ys[t][c], ys[t][c]);
-          A *= k[t + 1];
+          for (int c = 0; c < N; ++c) z[c] = fmaf(kk(t + 1), z[c] - ys[t][c], ys[t][c]);
+          A *= kk(t + 1);
         }
       }
       sum[0] = A;
@@ -322,7 +326,7 @@ __global__ void __launch_bounds__(kThreads) amf_cols_kernel(AmfGeom G) {
       for (int t = kAmfSeg - 1; t >= 0; --t) {
         if (t < n) {
 #pragma unroll
-          for (int c = 0; c < N; ++c) z[c] = fmaf(k[t + 1], z[c] - ys[t][c], ys[t][c]);
+          for (int c = 0; c < N; ++c) z[c] = fmaf(kk(t + 1), z[c] - ys[t][c], ys[t][c]);
           const int i = i0 + t;
           const size_t idx = col + static_cast<size_t>(i) * W;
           if constexpr (MODE == kRoot) {
