@@ -127,6 +127,12 @@ typedef struct {
                         manifolds); 0 selects max(2, ceil(H_s L)), H_s = floor(log2
                         sigma_s) - 1, L = 1 - sigma_r, both clamped at 0, at most 6.
                         Must be 0 for the other filters. */
+  float detail_gain; /* finite.  0: the output is u.  m != 0: the output is the
+                        detail-enhanced u + m (f - u), the detail layer f - u boosted m
+                        times over the smoothed base (the experiments section boosts it
+                        5 times).  Applied to the last iteration; since u = f + delta it
+                        is folded into the spectral divide (delta scaled by 1 - m), at no
+                        extra pass. */
 } blfls_params;
 
 #define BLFLS_MAX_RADIUS 32

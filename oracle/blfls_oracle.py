@@ -848,15 +848,17 @@ def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iter
 
 def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None,
                    normalize=False, sigma_guide=0.0, return_fields=False, filter="blf", nc_iterations=3,
-                   amf_height=0):
+                   amf_height=0, detail_gain=0.0):
     """BLF-LS on one channel (Section III-A two-step procedure, Section III-D extensions).
 
     Step 1 filters p_x, p_y with Eq. (1) (``filter="nc"``: the NC filter of the domain
     transform, NC-LS; ``filter="grid"``: the bilateral-grid approximation of Eq. (1);
     ``filter="amf"``: the adaptive-manifold filter, AMF-LS); step 2 solves Eq. (8).  ``guide`` switches to joint filtering;
-    ``iterations`` > 1 is rolling guidance.
+    ``iterations`` > 1 is rolling guidance.  ``detail_gain`` m != 0 returns the detail-enhanced
+    u + m (f - u) of the experiments section (the detail layer f - u boosted m times).
     """
     f = np.asarray(f, dtype=np.float64)
+    f_in = f
     r = default_radius(sigma_s) if radius is None or radius < 0 else int(radius)
     nc = filter in ("nc", "grid", "amf")   # these normalise through the guide field's span
     lo, span = 0.0, 1.0
@@ -886,25 +888,27 @@ def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None
         u = blfls_solve(f, gx, gy, lam)
         prev = u
     out = u * span + lo
+    if detail_gain:
+        out = out + detail_gain * (f_in - out)
     if return_fields:
         return out, gx * span, gy * span
     return out
 
 
 def smooth(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None, normalize=False,
-           sigma_guide=0.0, filter="blf", nc_iterations=3, amf_height=0):
+           sigma_guide=0.0, filter="blf", nc_iterations=3, amf_height=0, detail_gain=0.0):
     """BLF-LS (or NC-LS, grid BLF-LS, AMF-LS with ``filter="nc"``, ``"grid"``, ``"amf"``) on a
     (H, W) or (C, H, W) image; channels are independent."""
     f = np.asarray(f, dtype=np.float64)
     if f.ndim == 2:
         return smooth_channel(f, lam, sigma_s, sigma_r, radius, iterations, guide, normalize,
                               sigma_guide, filter=filter, nc_iterations=nc_iterations,
-                              amf_height=amf_height)
+                              amf_height=amf_height, detail_gain=detail_gain)
     g = None if guide is None else np.asarray(guide, dtype=np.float64)
     outs = []
     for c in range(f.shape[0]):
         gc = None if g is None else (g[c] if g.ndim == 3 else g)
         outs.append(smooth_channel(f[c], lam, sigma_s, sigma_r, radius, iterations, gc,
                                    normalize, sigma_guide, filter=filter, nc_iterations=nc_iterations,
-                                   amf_height=amf_height))
+                                   amf_height=amf_height, detail_gain=detail_gain))
     return np.stack(outs)

@@ -53,6 +53,7 @@ class Params(ctypes.Structure):
         ("sigma_guide", ctypes.c_float),
         ("filter", ctypes.c_int32),
         ("filter_iterations", ctypes.c_int32),
+        ("detail_gain", ctypes.c_float),
     ]
 
 
@@ -150,15 +151,17 @@ FILTERS = {"blf": 0, "nc": 1, "grid": 2, "amf": 3}
 
 def make_params(lam: float, sigma_s: float, sigma_r: float, radius: int = -1, iterations: int = 1,
                 normalize: bool = False, sigma_guide: float = 0.0, filter: str = "blf",
-                filter_iterations: int = 0) -> Params:
+                filter_iterations: int = 0, detail_gain: float = 0.0) -> Params:
     """``filter``: "blf" (BLF-LS), "nc" (NC-LS: the domain transform's normalized
     convolution in place of the BLF; ``filter_iterations`` rounds, 0 = 3), "grid" (the
     bilateral-grid approximation of the BLF) or "amf" (AMF-LS: the adaptive-manifold
-    filter; ``filter_iterations`` is the manifold tree height, 0 = the default rule)."""
+    filter; ``filter_iterations`` is the manifold tree height, 0 = the default rule).
+    ``detail_gain`` m != 0 returns the detail-enhanced u + m (f - u) instead of u."""
     if filter not in FILTERS:
         raise ValueError(f"filter must be one of {sorted(FILTERS)}")
     return Params(float(lam), float(sigma_s), float(sigma_r), int(radius), int(iterations),
-                  F_NORMALIZE if normalize else 0, float(sigma_guide), FILTERS[filter], int(filter_iterations))
+                  F_NORMALIZE if normalize else 0, float(sigma_guide), FILTERS[filter], int(filter_iterations),
+                  float(detail_gain))
 
 
 def _stream_handle(stream) -> int:
@@ -211,7 +214,7 @@ class Plan:
 
     def smooth(self, f, lam: float, sigma_s: float, sigma_r: float, radius: int = -1, iterations: int = 1,
                guide=None, normalize: bool = False, sigma_guide: float = 0.0, out=None, stream=None,
-               filter: str = "blf", filter_iterations: int = 0):
+               filter: str = "blf", filter_iterations: int = 0, detail_gain: float = 0.0):
         import torch
         shape = (self.C, self.H, self.W)
         f3 = f.reshape(shape) if f.dim() == 2 else f
@@ -226,7 +229,7 @@ class Plan:
                 raise ValueError(f"guide must be a contiguous float32 CUDA tensor of shape {shape}")
         u = torch.empty_like(f3) if out is None else out
         prm = make_params(lam, sigma_s, sigma_r, radius, iterations, normalize, sigma_guide, filter,
-                          filter_iterations)
+                          filter_iterations, detail_gain)
         need = self.workspace_for(prm)
         if need > self.workspace_bytes:
             # work queued earlier (on any stream) may still use the old buffer
@@ -255,14 +258,16 @@ _plan_cache: dict = {}
 
 def smooth(f, lam: float = 1024.0, sigma_s: float = 3.0, sigma_r: float = 0.1, radius: int = -1,
            iterations: int = 1, guide=None, normalize: bool = False, sigma_guide: float = 0.0,
-           precision="fp32", out=None, stream=None, filter: str = "blf", filter_iterations: int = 0):
+           precision="fp32", out=None, stream=None, filter: str = "blf", filter_iterations: int = 0,
+           detail_gain: float = 0.0):
     """BLF-LS of a float32 CUDA image of shape (H, W) or (C, H, W); returns u (same shape).
 
     lam is lambda of Eq. (7) (the paper's default is 1024), sigma_s / sigma_r the
     spatial and range sigmas of Eq. (1), radius -1 means ceil(3 sigma_s).
     filter="nc" runs NC-LS (Section III-D) with filter_iterations rounds (0 = 3);
     filter="grid" the bilateral-grid approximation; filter="amf" AMF-LS with a manifold
-    tree of height filter_iterations (0 = the default rule).
+    tree of height filter_iterations (0 = the default rule).  detail_gain m != 0 returns
+    u + m (f - u) (the experiments' detail enhancement uses m = 5).
     """
     C, H, W = (1, *f.shape) if f.dim() == 2 else tuple(f.shape)
     key = (C, H, W, _PRECISIONS[precision], f.device.index)
@@ -271,7 +276,7 @@ def smooth(f, lam: float = 1024.0, sigma_s: float = 3.0, sigma_r: float = 0.1, r
         plan = Plan(H, W, C, precision, device=f.device)
         _plan_cache[key] = plan
     return plan.smooth(f, lam, sigma_s, sigma_r, radius, iterations, guide, normalize, sigma_guide, out, stream,
-                       filter, filter_iterations)
+                       filter, filter_iterations, detail_gain)
 
 
 class Server:
@@ -298,7 +303,7 @@ class Server:
 
     def submit(self, f, lam: float, sigma_s: float, sigma_r: float, radius: int = -1, iterations: int = 1,
                guide=None, normalize: bool = False, sigma_guide: float = 0.0, out=None, filter: str = "blf",
-               filter_iterations: int = 0):
+               filter_iterations: int = 0, detail_gain: float = 0.0):
         """Queue one image; returns (ticket, u).  u is valid once poll(ticket) reports DONE.
 
         Raises BlflsError with status E_AGAIN when the queue is full.
@@ -308,7 +313,7 @@ class Server:
         u = torch.empty_like(f) if out is None else out
         req = Request(H, W, C, f.data_ptr(), guide.data_ptr() if guide is not None else 0, u.data_ptr(), W,
                       make_params(lam, sigma_s, sigma_r, radius, iterations, normalize, sigma_guide, filter,
-                                  filter_iterations))
+                                  filter_iterations, detail_gain))
         ticket = ctypes.c_uint64()
         _check(lib().blfls_submit(self._handle, ctypes.byref(req), ctypes.byref(ticket)))
         self._keep[ticket.value] = (f, guide, u)

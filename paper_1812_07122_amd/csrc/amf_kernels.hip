@@ -362,24 +362,42 @@ __global__ void __launch_bounds__(kThreads) amf_cols_kernel(AmfGeom G) {
 }
 
 // Fold the segment maps of each column into the carry entering every segment.
+// The maps of 8 segments are loaded before they are folded, so the loads
+// overlap instead of waiting one after another.
 template <int N, bool BACKWARD>
 __global__ void __launch_bounds__(kThreads) amf_carry_kernel(AmfGeom G) {
+  constexpr int kBatch = 8;
   const int j = blockIdx.x * kThreads + threadIdx.x, p = blockIdx.y;
   if (j >= G.W) return;
   const int S = G.S, W = G.W;
-  float* carry = BACKWARD ? G.carry_b : G.carry_f;
+  const float* __restrict__ sum = G.sum;
+  float* __restrict__ carry = BACKWARD ? G.carry_b : G.carry_f;
   float y[N];
 #pragma unroll
   for (int c = 0; c < N; ++c) y[c] = 0.0f;
-  for (int t = 0; t < S; ++t) {
-    const int s = BACKWARD ? S - 1 - t : t;
-    const float* sm = G.sum + static_cast<size_t>(p * S + s) * 5 * W + j;
-    float* cr = carry + static_cast<size_t>(p * S + s) * 4 * W + j;
+  for (int t0 = 0; t0 < S; t0 += kBatch) {
+    float m[kBatch][1 + N];
 #pragma unroll
-    for (int c = 0; c < N; ++c) cr[c * W] = y[c];
-    const float A = sm[0];
+    for (int b = 0; b < kBatch; ++b) {
+      if (t0 + b < S) {
+        const int s = BACKWARD ? S - 1 - (t0 + b) : t0 + b;
+        const float* sm = sum + static_cast<size_t>(p * S + s) * 5 * W + j;
 #pragma unroll
-    for (int c = 0; c < N; ++c) y[c] = fmaf(A, y[c], sm[(1 + c) * W]);
+        for (int c = 0; c <= N; ++c) m[b][c] = sm[c * W];
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      if (t0 + b < S) {
+        const int s = BACKWARD ? S - 1 - (t0 + b) : t0 + b;
+        float* cr = carry + static_cast<size_t>(p * S + s) * 4 * W + j;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+          cr[c * W] = y[c];
+          y[c] = fmaf(m[b][0], y[c], m[b][1 + c]);
+        }
+      }
+    }
   }
 }
 

@@ -181,6 +181,7 @@ blfls_status check_params(const blfls_params* p, int* radius_out) {
   if (p->iterations < 1) return set_error(BLFLS_E_INVALID, "iterations must be >= 1");
   if (!std::isfinite(p->sigma_guide) || p->sigma_guide < 0.0f) return set_error(BLFLS_E_INVALID, "sigma_guide must be finite and >= 0");
   if (p->flags & ~BLFLS_F_NORMALIZE) return set_error(BLFLS_E_INVALID, "unknown flag bits");
+  if (!std::isfinite(p->detail_gain)) return set_error(BLFLS_E_INVALID, "detail_gain must be finite");
   if (p->filter != BLFLS_FILTER_BLF && p->filter != BLFLS_FILTER_NC && p->filter != BLFLS_FILTER_GRID &&
       p->filter != BLFLS_FILTER_AMF)
     return set_error(BLFLS_E_INVALID, "unknown filter");
@@ -506,7 +507,10 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
     F.m_div = make_fastdiv(static_cast<uint32_t>(M));
     F.h_div = make_fastdiv(static_cast<uint32_t>(H));
     F.rb_div = make_fastdiv(static_cast<uint32_t>(plan->rb));
+    F.gain = 1.0f;
   }
+  out->fft_last = out->fft;
+  for (FftPlane& F : out->fft_last) F.gain = static_cast<float>(1.0 - static_cast<double>(prm.detail_gain));
   if (prm.filter == BLFLS_FILTER_AMF) {
     // the manifold arrays follow the plan's workspace
     const int height = amf_tree_height(prm);
@@ -577,19 +581,20 @@ hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, cons
       e = launch_blf(rd.R, first ? dev.blf_first : dev.blf_next, C, items, first ? rd.joint_first : true, ft, s);
       if (e != hipSuccess) return e;
     }
+    const FftPlane* fp = it + 1 == rd.iterations ? dev.fft_last : dev.fft;
     {
       StageTimer t(BLFLS_STAGE_ROWS_FWD, s);
-      e = launch_fft_rows_fwd(dev.fft, C, plan->row_blocks * C, plan->lds_rows, ft, s);
+      e = launch_fft_rows_fwd(fp, C, plan->row_blocks * C, plan->lds_rows, ft, s);
       if (e != hipSuccess) return e;
     }
     {
       StageTimer t(BLFLS_STAGE_COLS, s);
-      e = launch_fft_cols(dev.fft, C, plan->col_blocks * C, plan->lds_cols, s);
+      e = launch_fft_cols(fp, C, plan->col_blocks * C, plan->lds_cols, s);
       if (e != hipSuccess) return e;
     }
     {
       StageTimer t(BLFLS_STAGE_ROWS_INV, s);
-      e = launch_fft_rows_inv(dev.fft, C, plan->row_blocks * C, plan->lds_rows, s);
+      e = launch_fft_rows_inv(fp, C, plan->row_blocks * C, plan->lds_rows, s);
       if (e != hipSuccess) return e;
     }
   }
@@ -690,6 +695,7 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   const size_t o_m2 = place(rd.mm_next.data(), C * sizeof(AuxPlane));
   const size_t o_g = place(rd.gauss.data(), C * sizeof(AuxPlane));
   const size_t o_f = place(rd.fft.data(), C * sizeof(FftPlane));
+  const size_t o_fl = params->detail_gain != 0.0f ? place(rd.fft_last.data(), C * sizeof(FftPlane)) : o_f;
   size_t o_n1 = 0, o_n2 = 0;
   if (rd.filter == BLFLS_FILTER_NC) {
     o_n1 = place(rd.nc_first.data(), C * sizeof(NcPlane));
@@ -715,6 +721,7 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   dd.mm_next = reinterpret_cast<const AuxPlane*>(dbase + o_m2);
   dd.gauss = reinterpret_cast<const AuxPlane*>(dbase + o_g);
   dd.fft = reinterpret_cast<const FftPlane*>(dbase + o_f);
+  dd.fft_last = reinterpret_cast<const FftPlane*>(dbase + o_fl);
   if (rd.filter == BLFLS_FILTER_NC) {
     dd.nc_first = reinterpret_cast<const NcPlane*>(dbase + o_n1);
     dd.nc_next = reinterpret_cast<const NcPlane*>(dbase + o_n2);

@@ -84,6 +84,7 @@ struct FftPlane {
   int64_t pitch;
   int H, W;
   float lambda;
+  float gain;            // scale of delta: 1, or 1 - m for detail gain m on the last iteration
   int rb;                // rows per row-pass workgroup
   int cb;                // spectrum columns per column-pass workgroup
   int row_begin, row_count;   // workgroups of the row passes

@@ -73,6 +73,7 @@ struct RequestDesc {
   std::vector<AuxPlane> mm_next;
   std::vector<AuxPlane> gauss;       // guide smoothing
   std::vector<FftPlane> fft;
+  std::vector<FftPlane> fft_last;    // the last iteration's (detail gain folded in)
   std::vector<GridPlane> grid_first; // bilateral grid: iteration 1
   std::vector<GridPlane> grid_next;  // and iterations 2..n
   std::vector<NcPlane> nc_first;     // NC-LS: the NC passes of iteration 1
@@ -110,6 +111,7 @@ struct DeviceDesc {
   const AuxPlane* mm_next = nullptr;
   const AuxPlane* gauss = nullptr;
   const FftPlane* fft = nullptr;
+  const FftPlane* fft_last = nullptr;
   const GridPlane* grid_first = nullptr;
   const GridPlane* grid_next = nullptr;
   const NcPlane* nc_first = nullptr;

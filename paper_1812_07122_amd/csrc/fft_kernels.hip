@@ -344,7 +344,8 @@ struct ColIO {
   __device__ __forceinline__ void store(int b, int n, float2 v) const { spec[static_cast<int64_t>(b) * H + n] = v; }
 };
 
-// LDS destination that applies the Eq. (8) divide, 1 / (H W (1 + lam (sx + sy))).
+// LDS destination that applies the Eq. (8) divide, 1 / (H W (1 + lam (sx + sy)))
+// (times the detail gain's 1 - m on the last iteration: u + m (f - u) = f + (1 - m) delta).
 struct ScaledLds {
   static constexpr bool kLds = true;
   float2* buf;
@@ -439,7 +440,7 @@ __device__ __forceinline__ void cols_item(const FftPlane* __restrict__ planes, i
   const ColIO col{P.spec + static_cast<int64_t>(k0) * H, H};
   const LdsIO lds{buf, H};
   const ScaledLds scaled{buf, H, k0, P.sx, P.sy, P.lambda,
-                         1.0f / (static_cast<float>(H) * static_cast<float>(W))};
+                         P.gain * (1.0f / (static_cast<float>(H) * static_cast<float>(W)))};
   fft_run<T, kFftLdsComplex>(*P.szH, twS, -1.0f, ncols, col, lds, scaled);
   fft_run<T, kFftLdsComplex>(*P.szH, twS, 1.0f, ncols, lds, lds, col);
 }

@@ -225,7 +225,7 @@ static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
         bg.items += 2 * b.tile_count;
         push_desc(bg, b);
       }
-      for (auto fp : rd.fft) {
+      for (auto fp : (it + 1 == rd.iterations ? rd.fft_last : rd.fft)) {
         fp.row_begin = fft.items;
         fp.col_begin = fft.items2;
         fft.items += fp.row_count;

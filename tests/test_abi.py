@@ -89,7 +89,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     import paper_1812_07122_amd as b
     checks = {
         "blfls_params": (b.Params, ["lambda", "sigma_s", "sigma_r", "radius", "iterations", "flags", "sigma_guide",
-                                    "filter", "filter_iterations"]),
+                                    "filter", "filter_iterations", "detail_gain"]),
         "blfls_request": (b.Request, ["H", "W", "C", "f", "guide", "u", "pitch", "params"]),
         "blfls_stats": (b.Stats, [n for n, _ in b.Stats._fields_]),
     }
