@@ -187,6 +187,29 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params *params, const f
                           const float *guide, float *u, int64_t pitch, void *workspace,
                           void *stream);
 
+/* HDR tone mapping in the log domain (experiments section: the framework of
+ * Durand and Dorsey 2002 with BLF-LS as the base/detail decomposition).
+ *   I = max((20 R + 40 G + B) / 61, 1e-6), L = log10 I,
+ *   base = blfls_smooth(L) with `params` (one channel), detail = L - base,
+ *   out_c = c / I * 10^((base - max base) cf + detail),
+ *   cf = log10(contrast) / (max base - min base)  (1 if the base is constant):
+ * the compressed base spans `contrast` with its maximum at 1, the detail layer
+ * and the colour ratios pass unchanged.  Linear in, linear out (no gamma).
+ *   plan       a plan with C = 1 for the image's H x W (else BLFLS_E_INVALID)
+ *   rgb        device [3][H][pitch] FP32 linear radiance, read only
+ *   out        device [3][H][pitch] FP32, written; must not overlap rgb or the workspace
+ *   contrast   target contrast of the compressed base, finite and > 1 (Durand and
+ *              Dorsey use 5)
+ *   workspace  at least blfls_tonemap_workspace_size(plan, params) bytes, 256-byte aligned
+ * Queued on `stream` without synchronising, like blfls_smooth. */
+blfls_status blfls_tonemap(blfls_plan_t plan, const blfls_params *params, const float *rgb, float *out,
+                           int64_t pitch, float contrast, void *workspace, void *stream);
+
+/* Workspace bytes of blfls_tonemap: blfls_workspace_size plus two H x W planes
+ * and the extrema partials. */
+blfls_status blfls_tonemap_workspace_size(blfls_plan_t plan, const blfls_params *params,
+                                          size_t *workspace_bytes);
+
 /* ------------------------------------------------------------------------ */
 /* Serving: continuous batching of independent requests                      */
 /* ------------------------------------------------------------------------ */

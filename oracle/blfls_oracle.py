@@ -59,6 +59,7 @@ __all__ = [
     "grid_cell", "grid_range", "grid_filter", "grid_filter_bruteforce",
     "AMF_MAX_HEIGHT", "AMF_TAU", "amf_tree_height", "amf_rf_line_rows", "amf_blur",
     "amf_filter", "amf_filter_dense",
+    "TM_FLOOR", "tonemap",
 ]
 
 
@@ -912,3 +913,32 @@ def smooth(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None, normal
                                    normalize, sigma_guide, filter=filter, nc_iterations=nc_iterations,
                                    amf_height=amf_height, detail_gain=detail_gain))
     return np.stack(outs)
+
+
+# ---------------------------------------------------------------------------
+# HDR tone mapping in the log domain (experiments section: the framework of
+# Durand and Dorsey 2002, with BLF-LS as the base/detail decomposition)
+# ---------------------------------------------------------------------------
+#
+# Readings (listed in the design notes): the intensity is the weighted sum
+# (20 R + 40 G + B) / 61, floored at TM_FLOOR; its base layer is the BLF-LS
+# output of log10(intensity) and the detail layer the difference; the base is
+# compressed linearly so that its range spans log10(contrast) with its maximum
+# at 0 (a constant base is only shifted); the output intensity is
+# 10^(compressed base + detail) and each channel keeps its ratio to the input
+# intensity.  Linear output, no display gamma.
+
+TM_FLOOR = 1e-6
+
+
+def tonemap(rgb: np.ndarray, lam, sigma_s, sigma_r, contrast=5.0, **smooth_kw) -> np.ndarray:
+    """Tone-map a (3, H, W) linear HDR image; smooth_kw go to smooth() (normalize, filter, ...)."""
+    rgb = np.asarray(rgb, dtype=np.float64)
+    inten = np.maximum((20.0 * rgb[0] + 40.0 * rgb[1] + rgb[2]) / 61.0, TM_FLOOR)
+    L = np.log10(inten)
+    base = smooth(L, lam, sigma_s, sigma_r, **smooth_kw)
+    detail = L - base
+    lo, hi = float(base.min()), float(base.max())
+    cf = math.log10(contrast) / (hi - lo) if hi > lo else 1.0
+    out_log = (base - hi) * cf + detail
+    return rgb / inten * 10.0 ** out_log

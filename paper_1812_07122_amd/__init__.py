@@ -101,6 +101,10 @@ SIGNATURES = [
     ("blfls_workspace_size", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params),
                                             ctypes.POINTER(ctypes.c_size_t)]),
     ("blfls_plan_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("blfls_tonemap", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_int64, ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p]),
+    ("blfls_tonemap_workspace_size", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params),
+                                                    ctypes.POINTER(ctypes.c_size_t)]),
     ("blfls_smooth", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                     ctypes.c_void_p]),
@@ -277,6 +281,34 @@ def smooth(f, lam: float = 1024.0, sigma_s: float = 3.0, sigma_r: float = 0.1, r
         _plan_cache[key] = plan
     return plan.smooth(f, lam, sigma_s, sigma_r, radius, iterations, guide, normalize, sigma_guide, out, stream,
                        filter, filter_iterations, detail_gain)
+
+
+def tonemap(rgb, lam: float = 20.0, sigma_s: float = 8.0, sigma_r: float = 0.03, contrast: float = 5.0,
+            normalize: bool = True, out=None, stream=None, filter: str = "blf", **kw):
+    """Log-domain HDR tone mapping of a float32 CUDA image of shape (3, H, W) (``blfls_tonemap``):
+    the BLF-LS base of log10 intensity is compressed to ``contrast`` and recombined with the
+    detail layer and the colour ratios.  ``normalize`` maps the log intensity to [0, 1] before
+    smoothing (the experiments section's convention for sigma_r)."""
+    import torch
+    if rgb.dim() != 3 or rgb.shape[0] != 3 or rgb.dtype != torch.float32 or not rgb.is_cuda or not rgb.is_contiguous():
+        raise ValueError("rgb must be a contiguous float32 CUDA tensor of shape (3, H, W)")
+    _, H, W = rgb.shape
+    key = (1, H, W, _PRECISIONS["fp32"], rgb.device.index)
+    plan = _plan_cache.get(key)
+    if plan is None:
+        plan = Plan(H, W, 1, "fp32", device=rgb.device)
+        _plan_cache[key] = plan
+    prm = make_params(lam, sigma_s, sigma_r, normalize=normalize, filter=filter, **kw)
+    n = ctypes.c_size_t()
+    _check(lib().blfls_tonemap_workspace_size(plan._handle, ctypes.byref(prm), ctypes.byref(n)))
+    if int(n.value) > plan.workspace_bytes:
+        torch.cuda.synchronize(plan.device)
+        plan._alloc_workspace(int(n.value))
+    out = torch.empty_like(rgb) if out is None else out
+    _check(lib().blfls_tonemap(plan._handle, ctypes.byref(prm), ctypes.c_void_p(rgb.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), W, float(contrast),
+                               ctypes.c_void_p(plan.workspace_ptr), ctypes.c_void_p(_stream_handle(stream))))
+    return out
 
 
 class Server:

@@ -642,6 +642,63 @@ blfls_status blfls_workspace_size(blfls_plan_t plan, const blfls_params* params,
   return BLFLS_OK;
 }
 
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb);
+
+// Tone-mapping workspace: the smooth's own, then L, the base and the partials.
+static size_t tonemap_bytes(const blfls_plan_s* plan, const blfls_params& p, size_t* off_l, size_t* off_base,
+                            size_t* off_part) {
+  const size_t plane = align_up(static_cast<size_t>(plan->H) * plan->W * sizeof(float), 256);
+  *off_l = align_up(request_workspace_bytes(plan, p), 256);
+  *off_base = *off_l + plane;
+  *off_part = *off_base + plane;
+  return *off_part + align_up(2 * static_cast<size_t>(tm_extrema_blocks()) * sizeof(float), 256);
+}
+
+blfls_status blfls_tonemap_workspace_size(blfls_plan_t plan, const blfls_params* params, size_t* workspace_bytes) {
+  g_last_error.clear();
+  if (plan == nullptr || params == nullptr || workspace_bytes == nullptr)
+    return set_error(BLFLS_E_INVALID, "NULL argument");
+  int radius = 0;
+  const blfls_status st = check_params(params, &radius);
+  if (st != BLFLS_OK) return st;
+  size_t a, b, c;
+  *workspace_bytes = tonemap_bytes(plan, *params, &a, &b, &c);
+  return BLFLS_OK;
+}
+
+blfls_status blfls_tonemap(blfls_plan_t plan, const blfls_params* params, const float* rgb, float* out,
+                           int64_t pitch, float contrast, void* workspace, void* stream) {
+  g_last_error.clear();
+  if (plan == nullptr || params == nullptr) return set_error(BLFLS_E_INVALID, "NULL argument");
+  if (rgb == nullptr || out == nullptr || workspace == nullptr) return set_error(BLFLS_E_INVALID, "NULL buffer");
+  if (plan->C != 1) return set_error(BLFLS_E_INVALID, "tone mapping smooths one channel: the plan must have C = 1");
+  if (!std::isfinite(contrast) || !(contrast > 1.0f)) return set_error(BLFLS_E_INVALID, "contrast must be finite and > 1");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return set_error(BLFLS_E_INVALID, "workspace must be 256-byte aligned");
+  if (pitch < plan->W) return set_error(BLFLS_E_INVALID, "pitch must be >= W");
+  int radius = 0;
+  blfls_status st = check_params(params, &radius);
+  if (st != BLFLS_OK) return st;
+  size_t off_l, off_base, off_part;
+  const size_t ws_bytes = tonemap_bytes(plan, *params, &off_l, &off_base, &off_part);
+  const size_t img_bytes = 3 * static_cast<size_t>(plan->H) * pitch * sizeof(float);
+  if (overlaps(out, img_bytes, rgb, img_bytes) || overlaps(out, img_bytes, workspace, ws_bytes))
+    return set_error(BLFLS_E_INVALID, "out must not overlap rgb or the workspace");
+  uint8_t* ws = static_cast<uint8_t*>(workspace);
+  float* L = reinterpret_cast<float*>(ws + off_l);
+  float* base = reinterpret_cast<float*>(ws + off_base);
+  float* part = reinterpret_cast<float*>(ws + off_part);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const float floor_i = 1e-6f;
+  hipError_t e = launch_tm_log(rgb, pitch, plan->H, plan->W, floor_i, L, s);
+  if (e != hipSuccess) return hip_error(e, "kernel launch");
+  st = blfls_smooth(plan, params, L, nullptr, base, plan->W, workspace, stream);
+  if (st != BLFLS_OK) return st;
+  e = launch_tm_finish(rgb, out, pitch, plan->H, plan->W, floor_i, L, base, part,
+                       static_cast<float>(std::log10(static_cast<double>(contrast))), s);
+  if (e != hipSuccess) return hip_error(e, "kernel launch");
+  return BLFLS_OK;
+}
+
 blfls_status blfls_plan_destroy(blfls_plan_t plan) {
   g_last_error.clear();
   if (plan == nullptr) return set_error(BLFLS_E_INVALID, "plan is NULL");

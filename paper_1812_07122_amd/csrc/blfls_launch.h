@@ -59,6 +59,13 @@ int amf_slots(int height);
 int amf_segments(int H);
 hipError_t amf_init_kernels();
 hipError_t launch_amf(const AmfGeom& geom, float* slots, int height, hipStream_t s);
+
+// Log-domain tone mapping around one smooth of the log intensity: the log
+// intensity of an RGB image, then the base's extrema and the recombination.
+int tm_extrema_blocks();
+hipError_t launch_tm_log(const float* rgb, int64_t pitch, int H, int W, float floor_i, float* L, hipStream_t s);
+hipError_t launch_tm_finish(const float* rgb, float* out, int64_t pitch, int H, int W, float floor_i, const float* L,
+                            const float* base, float* partial, float log_contrast, hipStream_t s);
 hipError_t launch_minmax(const AuxPlane* planes, int nplanes, hipStream_t s, WorkHeader* work = nullptr,
                          int grid = 0);
 hipError_t launch_gauss(const AuxPlane* planes, int nplanes, int64_t max_pixels, hipStream_t s,
