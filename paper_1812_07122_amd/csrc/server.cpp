@@ -99,6 +99,7 @@ struct Job {
   uint64_t id = 0;
   double t_submit = 0.0;
   size_t desc_bytes = 0;  // staging bytes of this request's tables and descriptors
+  size_t ws_bytes = 0;    // arena bytes of its workspace (the AMF's is larger than the plan's)
   blfls_request req{};
   int radius = 0;
   blfls_plan_s* plan = nullptr;
@@ -107,10 +108,12 @@ struct Job {
 };
 
 // One launch group of a step: a kernel family over an array of plane descriptors.
+// Kind 4 is one request's NC, grid or AMF filter stage, launched directly.
 struct Group {
-  int kind;  // 0 gauss, 1 minmax, 2 blf, 3 fft
+  int kind;  // 0 gauss, 1 minmax, 2 blf, 3 fft, 4 other filter (one request)
   int R = 0;
   bool joint = false;
+  const Job* job = nullptr;     // kind 4: the request
   std::vector<uint8_t> planes;  // descriptor array bytes
   int n = 0;                    // planes
   int items = 0, items2 = 0;    // work items (fft: rows, cols)
@@ -174,6 +177,7 @@ struct blfls_server_s {
   void admit(std::vector<Job*>* admitted);
   hipError_t launch_step(Step& st, int slot);
   hipError_t launch_direct(std::vector<Group>& groups, int slot, int ft, size_t tables_used);
+  hipError_t launch_other_filter(const Job& jb, const uint8_t* planes, int ft);
   hipError_t build_graph(const std::vector<Group>& groups, int slot, int ft, hipGraphExec_t* out);
 };
 
@@ -205,12 +209,24 @@ static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
     const bool first = it == 0;
     Group mm{1};
     std::map<std::pair<int, bool>, Group> blf;
+    std::vector<Group> other;
     Group fft{3};
     for (Job* jb : jobs) {
       RequestDesc& rd = jb->rd;
       if (it >= rd.iterations) continue;
-      if (rd.normalize)
+      if (rd.normalize || rd.filter == BLFLS_FILTER_GRID)
         for (auto& a : (first ? rd.mm_first : rd.mm_next)) push_desc(mm, a);
+      if (rd.filter != BLFLS_FILTER_BLF) {
+        Group g{4};
+        g.job = jb;
+        if (rd.filter == BLFLS_FILTER_NC)
+          for (const auto& d : (first ? rd.nc_first : rd.nc_next)) push_desc(g, d);
+        else if (rd.filter == BLFLS_FILTER_GRID)
+          for (const auto& d : (first ? rd.grid_first : rd.grid_next)) push_desc(g, d);
+        else
+          for (const auto& d : (first ? rd.amf_first : rd.amf_next)) push_desc(g, d);
+        other.push_back(std::move(g));
+      }
       const std::pair<int, bool> key{rd.R, first ? rd.joint_first : true};
       auto found = blf.find(key);
       if (found == blf.end()) {
@@ -220,10 +236,12 @@ static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
         found = blf.emplace(key, std::move(g)).first;
       }
       Group& bg = found->second;
-      for (auto b : (first ? rd.blf_first : rd.blf_next)) {
-        b.tile_begin = bg.items / 2;
-        bg.items += 2 * b.tile_count;
-        push_desc(bg, b);
+      if (rd.filter == BLFLS_FILTER_BLF) {
+        for (auto b : (first ? rd.blf_first : rd.blf_next)) {
+          b.tile_begin = bg.items / 2;
+          bg.items += 2 * b.tile_count;
+          push_desc(bg, b);
+        }
       }
       for (auto fp : (it + 1 == rd.iterations ? rd.fft_last : rd.fft)) {
         fp.row_begin = fft.items;
@@ -237,7 +255,9 @@ static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
     }
     mm.items = mm.n * kMinmaxBlocks;
     if (mm.n) groups.push_back(std::move(mm));
-    for (auto& kv : blf) groups.push_back(std::move(kv.second));
+    for (auto& kv : blf)
+      if (kv.second.n) groups.push_back(std::move(kv.second));
+    for (auto& g : other) groups.push_back(std::move(g));
     if (fft.n) groups.push_back(std::move(fft));
   }
   return groups;
@@ -287,6 +307,7 @@ hipError_t blfls_server_s::launch_direct(std::vector<Group>& groups, int slot, i
       case 0: e = launch_gauss(reinterpret_cast<const AuxPlane*>(d), g.n, g.max_pix, stream); break;
       case 1: e = launch_minmax(reinterpret_cast<const AuxPlane*>(d), g.n, stream); break;
       case 2: e = launch_blf(g.R, reinterpret_cast<const BlfPlane*>(d), g.n, g.items, g.joint, ft, stream); break;
+      case 4: e = launch_other_filter(*g.job, d, ft); break;
       default: {
         const FftPlane* fp = reinterpret_cast<const FftPlane*>(d);
         e = launch_fft_rows_fwd(fp, g.n, g.items, g.lds_rows, ft, stream);
@@ -297,6 +318,30 @@ hipError_t blfls_server_s::launch_direct(std::vector<Group>& groups, int slot, i
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// One request's NC, grid or AMF stage, as blfls_smooth queues it, reading the
+// descriptors staged at `planes`.
+hipError_t blfls_server_s::launch_other_filter(const Job& jb, const uint8_t* planes, int ft) {
+  const RequestDesc& rd = jb.rd;
+  const blfls_plan_s* plan = jb.plan;
+  const int C = plan->C;
+  if (rd.filter == BLFLS_FILTER_NC) {
+    const NcPlane* np = reinterpret_cast<const NcPlane*>(planes);
+    const int passes = 2 * rd.nc_rounds;
+    for (int pass = 0; pass < passes; ++pass) {
+      const int k = pass / 2;
+      const int n_items = (pass & 1) ? C * nc_col_items(plan->H, plan->W) : C * nc_row_items(plan->H, plan->W);
+      const hipError_t e = launch_nc_pass(np, C, n_items, pass, passes, rd.nc_r[k], rd.nc_R[k], ft, stream);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+  if (rd.filter == BLFLS_FILTER_GRID)
+    return launch_grid(reinterpret_cast<const GridPlane*>(planes), C, 2 * C * rd.grid_first[0].tile_count, ft, stream);
+  AmfGeom G = rd.amf_geom;
+  G.planes = reinterpret_cast<const AmfPlane*>(planes);
+  return launch_amf(G, rd.amf_slots, rd.amf_height, stream);
 }
 
 // Capture the persistent launches of one step signature for one staging slot.
@@ -350,7 +395,9 @@ hipError_t blfls_server_s::launch_step(Step& st, int slot) {
   }
   size_t used = tables_base + st.jobs.size() * sizeof(RequestTables);
   std::vector<Group> groups = build_groups(st.jobs);
-  if (static_cast<int>(groups.size()) > kMaxGroups) {
+  bool direct = static_cast<int>(groups.size()) > kMaxGroups;
+  for (const Group& g : groups) direct = direct || g.kind == 4;   // per-request filters launch directly
+  if (direct) {
     stats_direct_steps++;
     const hipError_t e = launch_direct(groups, slot, ft, used);
     return e == hipSuccess ? hipEventRecord(st.done, stream) : e;
@@ -401,7 +448,7 @@ void blfls_server_s::retire(Step& st) {
     } else {
       stats.failed++;
     }
-    arena_alloc.release(jb->ws_off, jb->plan->ws_bytes);
+    arena_alloc.release(jb->ws_off, jb->ws_bytes);
     running--;
     delete jb;
   }
@@ -418,7 +465,7 @@ void blfls_server_s::admit(std::vector<Job*>* admitted) {
     Job* jb = queue.front();
     if (desc + jb->desc_bytes > stage_bytes) break;  // the rest waits for the next step
     size_t off = 0;
-    if (!arena_alloc.alloc(jb->plan->ws_bytes, &off)) break;  // FIFO: the head waits for space
+    if (!arena_alloc.alloc(jb->ws_bytes, &off)) break;  // FIFO: the head waits for space
     desc += jb->desc_bytes;
     jb->ws_off = off;
     queue.pop_front();
@@ -523,8 +570,6 @@ blfls_status blfls_submit(blfls_server_t s, const blfls_request* r, uint64_t* ti
   int radius = 0;
   st = check_params(&r->params, &radius);
   if (st != BLFLS_OK) return st;
-  if (r->params.filter != BLFLS_FILTER_BLF)
-    return set_error(BLFLS_E_UNSUPPORTED, "the server runs the exact BLF; other filters run through blfls_smooth");
   if (r->f == nullptr || r->u == nullptr) return set_error(BLFLS_E_INVALID, "f and u must not be NULL");
   if (r->pitch < r->W) return set_error(BLFLS_E_INVALID, "pitch must be >= W");
   const size_t img = static_cast<size_t>(r->C) * r->H * r->pitch * sizeof(float);
@@ -547,18 +592,27 @@ blfls_status blfls_submit(blfls_server_t s, const blfls_request* r, uint64_t* ti
   } else {
     plan = it->second;
   }
-  if (plan->ws_bytes > s->arena_bytes - s->desc_region)
+  const size_t ws_bytes = request_workspace_bytes(plan, r->params);
+  if (ws_bytes > s->arena_bytes - s->desc_region)
     return set_error(BLFLS_E_NOMEM, "request workspace exceeds the arena");
-  // staging bytes: tables, the Gaussian descriptors, and per iteration one
-  // filter, one FFT and one extrema descriptor per channel
-  const size_t desc_bytes = sizeof(RequestTables) + 16 +
-                            static_cast<size_t>(r->C) * (sizeof(AuxPlane) + static_cast<size_t>(r->params.iterations) *
-                                                         (sizeof(BlfPlane) + sizeof(FftPlane) + sizeof(AuxPlane)));
+  // staging bytes: tables, the Gaussian descriptors, and per iteration the
+  // filter's descriptors (one group of its own, aligned, for the filters other
+  // than the BLF), one FFT and one extrema descriptor per channel
+  const int filt = r->params.filter;
+  const size_t C = static_cast<size_t>(r->C);
+  const size_t filter_group = filt == BLFLS_FILTER_NC     ? C * sizeof(NcPlane) + 256
+                              : filt == BLFLS_FILTER_GRID ? C * sizeof(GridPlane) + 256
+                              : filt == BLFLS_FILTER_AMF  ? 2 * C * sizeof(AmfPlane) + 256
+                                                          : C * sizeof(BlfPlane);
+  const size_t desc_bytes = sizeof(RequestTables) + 16 + C * sizeof(AuxPlane) +
+                            static_cast<size_t>(r->params.iterations) *
+                                (filter_group + C * (sizeof(FftPlane) + sizeof(AuxPlane)));
   if (desc_bytes + blfls_server_s::kHeaderBytes + blfls_server_s::kMaxGroups * 256 > s->stage_bytes)
     return set_error(BLFLS_E_NOMEM, "too many iterations for one server step");
   auto* jb = new (std::nothrow) Job();
   if (!jb) return set_error(BLFLS_E_NOMEM, "host allocation failed");
   jb->desc_bytes = desc_bytes;
+  jb->ws_bytes = ws_bytes;
   jb->id = s->next_id++;
   jb->t_submit = now_ms();
   jb->req = *r;

@@ -128,10 +128,3 @@ def test_grid_abi_errors():
     with pytest.raises(b.BlflsError) as e:
         b.smooth(f, lam=1.0, sigma_s=2.0, sigma_r=0.1, filter="grid", filter_iterations=2)
     assert e.value.status == -1
-    srv = b.Server(1 << 26)
-    try:
-        with pytest.raises(b.BlflsError) as e:
-            srv.submit(f, 1.0, 2.0, 0.1, filter="grid")
-        assert e.value.status == -2
-    finally:
-        srv.close()
