@@ -260,6 +260,57 @@ def test_rgb_1024_full_size():
         assert np.max(np.abs(res)) <= (1 + 8 * lam) * TOL_FP32
 
 
+def _sampled_normal_equations(u, f, g, lam, ss, sr, n, seed):
+    """Max |residual| of the normal equations of Eq. (7) at n random pixels, with the filtered
+    fields there (and at the left / upper neighbours) evaluated by the oracle pixel by pixel."""
+    H, W = f.shape
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, H, n)
+    cols = rng.integers(0, W, n)
+    r = oracle.default_radius(ss)
+    px, py = oracle.grad_x(f), oracle.grad_y(f)
+    qx = qy = None
+    if g is not None:
+        qx, qy = oracle.grad_x(g), oracle.grad_y(g)
+    gx = [oracle.bilateral_filter_at(px, qx, ss, sr, r, rows, cols),
+          oracle.bilateral_filter_at(px, qx, ss, sr, r, rows, (cols - 1) % W)]
+    gy = [oracle.bilateral_filter_at(py, qy, ss, sr, r, rows, cols),
+          oracle.bilateral_filter_at(py, qy, ss, sr, r, (rows - 1) % H, cols)]
+    return float(np.max(np.abs(_stencil_residual_at(u, f, gx, gy, lam, rows, cols))))
+
+
+def test_uhd_rgb_full_size_sampled():
+    # the 3840x2160 RGB workload (lambda = 50, sigma_s = 8: r = 24) in the launch bench.py times
+    lam, ss, sr = 50.0, 8.0, 0.05
+    f = voronoi_rgb(2160, 3840, 2)
+    u, fin, _ = _run(f, lam=lam, sigma_s=ss, sigma_r=sr)
+    for c in range(3):
+        res = _sampled_normal_equations(u[c], fin[c], None, lam, ss, sr, 300, 77 + c)
+        print(f"3840x2160 channel {c}: max normal-equation residual {res:.3e}")
+        assert res <= (1 + 8 * lam) * TOL_FP32
+
+
+def test_joint_2048_full_size_sampled():
+    # one pair of the guided 2048x2048 workload (lambda = 30, sigma_s = 4, sigma_r = 0.08)
+    lam, ss, sr = 30.0, 4.0, 0.08
+    t, g = joint_pair(2048, 2048, 0)
+    u, tin, gin = _run(t, g, lam=lam, sigma_s=ss, sigma_r=sr)
+    res = _sampled_normal_equations(u, tin, gin, lam, ss, sr, 400, 81)
+    print(f"2048x2048 joint: max normal-equation residual {res:.3e}")
+    assert res <= (1 + 8 * lam) * TOL_FP32
+
+
+def test_largest_plan_sampled():
+    # the largest transform sizes a plan accepts: W/2 = H = 4096
+    lam, ss, sr = 10.0, 1.0, 0.1
+    f = voronoi_image(4096, 8192, 5)
+    u, fin, _ = _run(f, lam=lam, sigma_s=ss, sigma_r=sr)
+    res = _sampled_normal_equations(u, fin, None, lam, ss, sr, 300, 83)
+    print(f"4096x8192: max normal-equation residual {res:.3e}")
+    assert res <= (1 + 8 * lam) * TOL_FP32
+    assert abs(float(u.mean()) - float(fin.mean())) < 1e-6
+
+
 # ---------------------------------------------------------------------------
 # Serving: every result equals the same request run alone
 # ---------------------------------------------------------------------------
