@@ -6,7 +6,10 @@ A step is one whole BLF-LS pass (Eq. (1) on both gradient fields of every
 channel, then the Eq. (8) solve) over one image whose input already sits in
 HBM.  The default workload is the paper's timing shape (Table I): one
 1024x1024 RGB image, channels independent, lambda = 20, sigma_s = 3 (r = 9),
-sigma_r = 0.1, one iteration, FP32.  Rank 0 prints one JSON line.
+sigma_r = 0.1, one iteration, FP32.  The step is replayed from a HIP graph
+that captured one blfls_smooth call (the eager rate is reported beside it, and
+the replayed output must equal the eager one bitwise).  Rank 0 prints one JSON
+line.
 
 Other workloads (each prints its own JSON line):
   uhd    3840x2160 RGB, sigma_s = 8 (r = 24), sigma_r = 0.05, lambda = 50,
@@ -104,6 +107,31 @@ def time_plan(plan, f, u, prm, steps, warmup, torch, blfls):
     return start.elapsed_time(end) / steps, stages
 
 
+def time_graph(plan, f, u, prm, steps, warmup, torch):
+    """Capture one whole step (blfls_smooth queues kernels only) in a HIP graph and time its
+    replays; the launch gaps between the step's kernels shrink to the graph's."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.smooth(f, out=u, **prm)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.smooth(f, out=u, **prm)
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        g.replay()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps, g
+
+
 def fft_bytes(H, W, C, field_bytes):
     """Algorithmic HBM bytes of the three solve passes for one image."""
     M = W // 2
@@ -125,7 +153,10 @@ def run_rgb1024(args, torch, blfls):
     f = torch.from_numpy(f64.astype(np.float32)).cuda()
     u = torch.empty_like(f)
     plan = blfls.Plan(H, W, C, "fp32")
-    ms, stages = time_plan(plan, f, u, prm, args.steps, args.warmup, torch, blfls)
+    ms_eager, stages = time_plan(plan, f, u, prm, args.steps, args.warmup, torch, blfls)
+    # the same step replayed from a captured graph: the value reported
+    ug = torch.empty_like(f)
+    ms, graph = time_graph(plan, f, ug, prm, args.steps, args.warmup, torch)
     value = H * W / (ms * 1e-3) / 1e6
 
     # dominant kernel: the bilateral filter (one launch per step covers all fields)
@@ -143,15 +174,19 @@ def run_rgb1024(args, torch, blfls):
         gbs = nbytes / (t * 1e-3) / 1e9
         fft[name] = {"ms": round(t, 5), "bytes": nbytes, "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
-    # plain FP32 against 16-bit field storage on the same workload
+    # plain FP32 against 16-bit field storage on the same workload (graph replays too)
     variants = {"fp32": round(value, 2)}
     for prec in ("bf16", "fp16"):
         p2 = blfls.Plan(H, W, C, prec)
-        ms2, _ = time_plan(p2, f, u, prm, max(args.steps // 2, 1), args.warmup, torch, blfls)
+        u2 = torch.empty_like(f)
+        ms2, g2 = time_graph(p2, f, u2, prm, args.steps, args.warmup, torch)
         variants[prec] = round(H * W / (ms2 * 1e-3) / 1e6, 2)
+        del g2
         p2.close()
     u_fp32 = plan.smooth(f, **prm)
     torch.cuda.synchronize()
+    graph_equal = bool(torch.equal(ug, u_fp32))
+    del graph
 
     out = {
         "metric": "MPix/s BLF-LS at 1 GPU (plain FP32 vs mixed) + p50/p99 served latency",
@@ -160,6 +195,9 @@ def run_rgb1024(args, torch, blfls):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "rgb1024: 1024x1024 RGB, channels independent, lambda=20, sigma_s=3 (r=9), "
                                "sigma_r=0.1, 1 iteration, circular boundaries", "H": H, "W": W, "C": C},
+        "step_launch": "HIP graph replay of one blfls_smooth call",
+        "eager_MPix/s": round(H * W / (ms_eager * 1e-3) / 1e6, 2), "eager_ms_per_step": round(ms_eager, 5),
+        "graph_vs_eager_bitwise_equal": graph_equal,
         "roofline": roofline,
         "fft_passes": fft,
         "stages_ms": {k: round(v[0] / max(v[1], 1), 5) for k, v in stages.items() if v[1]},
