@@ -233,6 +233,10 @@ def run_uhd(args, torch, blfls, state):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "uhd: 3840x2160 RGB, lambda=50, sigma_s=8 (r=24), sigma_r=0.05, 1 iteration",
                       "H": H, "W": W, "C": C},
+           "roofline": {"kernel": "blf_field_kernel<R=24>", "bound": "alu",
+                        "achieved": results["fp32"]["blf_Ttap_s"], "peak": round(BLF_TAP_PEAK_T, 4), "unit": "Ttap/s",
+                        "frac": results["fp32"]["blf_frac"], "traffic": None,
+                        "launch_ms": results["fp32"]["blf_ms"], "taps_per_launch": C * H * W * 2 * (2 * r + 1) ** 2},
            "precisions": results}
     if ref is not None:
         refs = np.stack(ref)
@@ -279,6 +283,11 @@ def run_grid(args, torch, blfls, state):
                                   "(cells of 8 pixels by one range cell) against the exact windowed filter (r=24)",
                       "H": H, "W": W, "C": C},
            "filters": res}
+    ops = grid_ops(H, W, C, max(1, int(math.floor(GRID_CONFIG["sigma_s"] + 0.5))))
+    gfrac = ops / (res["grid"]["filter_ms"] * 1e-3) / 1e12
+    out["roofline"] = {"kernel": "grid_filter_kernel", "bound": "alu", "achieved": round(gfrac, 3),
+                       "peak": VALU_PEAK_T, "unit": "T lane-ops/s", "frac": round(gfrac / VALU_PEAK_T, 4),
+                       "traffic": None, "launch_ms": res["grid"]["filter_ms"], "ops_per_launch": ops}
     ref, t = _collect(state)
     if ref is not None:
         out["max_abs_vs_oracle_ch0"] = float(np.max(np.abs(outs["grid"][0] - ref[0])))
@@ -286,6 +295,23 @@ def run_grid(args, torch, blfls, state):
                                "kind": "oracle", "sample": f"channel 0 of the image ({t:.1f} s wall, overlapping the "
                                                            "GPU runs); rate scaled to RGB images"}
     return out
+
+
+# single-issue VOP2 lane rate: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz
+VALU_PEAK_T = 78.6432
+
+
+def grid_ops(H, W, C, s, zbins=36):
+    """VALU lane-operations of the bilateral-grid kernel by a count of its code, per launch
+    (both fields of every channel).  Per workgroup (8 x 8 output cells of one field): the
+    splat of the 14 x 14 reachable cells' s x s pixels (two gradients, the bin, two LDS
+    read-add-writes: about 25 ops each), the blur (3 axes x 196 lines of the range axis x
+    2 grids x 5 taps over zbins bins), and the slice of the 64 s^2 output pixels (two
+    gradients, the cell coordinates, 8 cells x 2 grids trilinear, the division: about 60
+    ops each)."""
+    tiles = (((W - 1 + s // 2) // s + 1 + 7) // 8) * (((H - 1 + s // 2) // s + 1 + 7) // 8)
+    per_wg = 196 * s * s * 25 + 3 * 196 * zbins * 2 * 5 + 64 * s * s * 60
+    return 2 * C * tiles * per_wg
 
 
 def nc_bytes(H, W, C, field_bytes, rounds):
@@ -328,6 +354,9 @@ def run_nc(args, torch, blfls, state):
            "config": {"workload": "nc: 1024x1024 RGB NC-LS, lambda=20, sigma_s=12, sigma_r=0.05, 3 NC rounds; "
                                   "nc_rolling: sigma_s=8, sigma_r=0.02, 3 iterations, Gaussian guide sigma=2.5",
                       "H": H, "W": W, "C": C},
+           "roofline": {"kernel": "NC passes (nc_rows_kernel, nc_cols_kernel)", "bound": "hbm",
+                        "achieved": main["nc_passes"]["GB/s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": main["nc_passes"]["frac"], "traffic": None},
            "configs": configs,
            "paper_context": {"value": 2.5, "unit": "MPix/s", "note": "Table I: NC-LS 0.42 s per 1024x1024 RGB image "
                              "(CPU Python with OpenCV's NC filter, hardware unstated)"}}
