@@ -24,6 +24,8 @@ Other workloads (each prints its own JSON line):
          the exact filter
   amf    AMF-LS (the adaptive-manifold filter in place of the BLF) on the
          1024x1024 RGB image, trees of height 2 and 3
+The single-image lines (default, nc, amf, grid) replay the step from a captured
+graph and report the eager rate beside it.
 """
 from __future__ import annotations
 

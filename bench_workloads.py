@@ -255,7 +255,7 @@ GRID_CONFIG = dict(lam=50.0, sigma_s=8.0, sigma_r=0.05)
 
 
 def run_grid(args, torch, blfls, state):
-    from bench import time_plan
+    from bench import time_plan, time_graph
     H, W, C = 2160, 3840, 3
     f = torch.from_numpy(state["f"]).cuda()
     u = torch.empty_like(f)
@@ -265,11 +265,17 @@ def run_grid(args, torch, blfls, state):
     for name, prm in (("grid", dict(GRID_CONFIG, filter="grid")), ("exact", dict(GRID_CONFIG))):
         plan = blfls.Plan(H, W, C, "fp32")
         n = steps if name == "grid" else max(1, min(steps, 3))
-        ms, stages = time_plan(plan, f, u, prm, n, min(args.warmup, 2), torch, blfls)
+        ms_eager, stages = time_plan(plan, f, u, prm, n, min(args.warmup, 2), torch, blfls)
+        ug = torch.empty_like(f)
+        ms, graph = time_graph(plan, f, ug, prm, n, min(args.warmup, 2), torch)
         outs[name] = plan.smooth(f, **prm).cpu().numpy().astype(np.float64)
         torch.cuda.synchronize()
+        same = bool(np.array_equal(ug.cpu().numpy().astype(np.float64), outs[name]))
+        del graph
         filt_ms = stages["blf"][0] / max(stages["blf"][1], 1)
         res[name] = {"MPix/s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_image": round(ms, 4),
+                     "eager_MPix/s": round(H * W / (ms_eager * 1e-3) / 1e6, 2),
+                     "graph_vs_eager_bitwise_equal": same,
                      "filter_ms": round(filt_ms, 4), "steps": n}
         plan.close()
     d = outs["grid"] - outs["exact"]
@@ -323,7 +329,7 @@ def nc_bytes(H, W, C, field_bytes, rounds):
 
 
 def run_nc(args, torch, blfls, state):
-    from bench import time_plan, fft_bytes
+    from bench import time_plan, time_graph, fft_bytes
     H, W, C = 1024, 1024, 3
     f = torch.from_numpy(state["f"]).cuda()
     u = torch.empty_like(f)
@@ -332,15 +338,21 @@ def run_nc(args, torch, blfls, state):
     for name, prm in NC_CONFIGS.items():
         iters = prm.get("iterations", 1)
         plan = blfls.Plan(H, W, C, "fp32")
-        ms, stages = time_plan(plan, f, u, prm, args.steps, args.warmup, torch, blfls)
+        ms_eager, stages = time_plan(plan, f, u, prm, args.steps, args.warmup, torch, blfls)
+        ug = torch.empty_like(f)
+        ms, graph = time_graph(plan, f, ug, prm, args.steps, args.warmup, torch)
         outs[name] = plan.smooth(f, **prm).cpu().numpy().astype(np.float64)
         torch.cuda.synchronize()
+        same = bool(np.array_equal(ug.cpu().numpy().astype(np.float64), outs[name]))
+        del graph
         nc_ms = stages["blf"][0] / max(stages["blf"][1], 1)          # one iteration's NC passes
         nb = nc_bytes(H, W, C, 4, 3)
         rf, cl, ri = fft_bytes(H, W, C, 4)
         fft_ms = sum(stages[k][0] / max(stages[k][1], 1) for k in ("rows_fwd", "cols", "rows_inv"))
         configs[name] = {"params": {k: v for k, v in prm.items()}, "MPix/s": round(H * W / (ms * 1e-3) / 1e6, 2),
                          "ms_per_image": round(ms, 4), "iterations": iters,
+                         "eager_MPix/s": round(H * W / (ms_eager * 1e-3) / 1e6, 2),
+                         "graph_vs_eager_bitwise_equal": same,
                          "nc_passes_ms": round(nc_ms, 4),
                          "nc_passes": {"bound": "hbm", "bytes": nb, "GB/s": round(nb / (nc_ms * 1e-3) / 1e9, 1),
                                        "frac": round(nb / (nc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
@@ -403,7 +415,7 @@ def amf_bytes(H, W, C, field_bytes, height):
 
 
 def run_amf(args, torch, blfls, state):
-    from bench import time_plan, fft_bytes
+    from bench import time_plan, time_graph, fft_bytes
     H, W, C = 1024, 1024, 3
     f = torch.from_numpy(state["f"]).cuda()
     u = torch.empty_like(f)
@@ -411,9 +423,13 @@ def run_amf(args, torch, blfls, state):
     outs = {}
     for name, prm in AMF_CONFIGS.items():
         plan = blfls.Plan(H, W, C, "fp32")
-        ms, stages = time_plan(plan, f, u, prm, args.steps, args.warmup, torch, blfls)
+        ms_eager, stages = time_plan(plan, f, u, prm, args.steps, args.warmup, torch, blfls)
+        ug = torch.empty_like(f)
+        ms, graph = time_graph(plan, f, ug, prm, args.steps, args.warmup, torch)
         outs[name] = plan.smooth(f, **prm).cpu().numpy().astype(np.float64)
         torch.cuda.synchronize()
+        same = bool(np.array_equal(ug.cpu().numpy().astype(np.float64), outs[name]))
+        del graph
         amf_ms = stages["blf"][0] / max(stages["blf"][1], 1)
         height = amf_tree_height(prm["sigma_s"], prm["sigma_r"])
         nb = amf_bytes(H, W, C, 4, height)
@@ -421,6 +437,8 @@ def run_amf(args, torch, blfls, state):
         fft_ms = sum(stages[k][0] / max(stages[k][1], 1) for k in ("rows_fwd", "cols", "rows_inv"))
         configs[name] = {"params": dict(prm), "tree_height": height, "manifolds": 2 ** height - 1,
                          "MPix/s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_image": round(ms, 4),
+                         "eager_MPix/s": round(H * W / (ms_eager * 1e-3) / 1e6, 2),
+                         "graph_vs_eager_bitwise_equal": same,
                          "amf_ms": round(amf_ms, 4),
                          "amf_passes": {"bound": "hbm", "bytes": nb, "GB/s": round(nb / (amf_ms * 1e-3) / 1e9, 1),
                                         "frac": round(nb / (amf_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
