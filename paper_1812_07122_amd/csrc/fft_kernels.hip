@@ -355,7 +355,9 @@ struct ScaledLds {
   float lam, inv_hw;
   __device__ __forceinline__ void store(int b, int n, float2 v) const {
     const float den = fmaf(lam, sx[k0 + b] + sy[n], 1.0f);
-    buf[pad(b * H + n)] = cscale(v, inv_hw / den);
+    // den >= 1: the hardware reciprocal (1 ulp) instead of a correctly rounded
+    // division, which costs ten instructions per spectrum value
+    buf[pad(b * H + n)] = cscale(v, inv_hw * __builtin_amdgcn_rcpf(den));
   }
 };
 
