@@ -399,9 +399,9 @@ def amf_bytes(H, W, C, field_bytes, height):
                      residual in the field type and reads f's image instead);
       inner ones     rows: manifold and image in, 4 values out; columns: 4 values in 3
                      times, 2 children out;
-    plus the column scans' segment summaries and carries (32-row segments)."""
+    plus the column scans' segment summaries and carries (16-row segments)."""
     def scan(n):   # per pixel: summaries, carry folds and carries of an n-channel column scan
-        return (2 * (1 + n) + 2 * (1 + n) + 2 * n + 2 * n) / 32.0
+        return (2 * (1 + n) + 2 * (1 + n) + 2 * n + 2 * n) / 16.0
     K = 2 ** height - 1
     inner = 2 ** (height - 1) - 1
     per = (2 + 4 + scan(1))                                    # root

@@ -24,8 +24,9 @@
 //     carry, and the chunk is walked again with it (then the same from the
 //     right).  One HBM read and one write per value.
 //   * columns: 256 adjacent columns per workgroup (coalesced rows), the height
-//     cut into 32-row segments: (0) each segment's composed map, (carry) a
-//     sequential fold over the segments of each column, (1) the forward scan
+//     cut into 16-row segments: (0) each segment's composed map, (carry) a
+//     fold of the maps down each column (eight threads per column, their
+//     shares combined in LDS), (1) the forward scan
 //     from the carry plus the backward map of the segment, (carry) the
 //     backward fold, (2) both scans again and the consumer: the root manifold,
 //     the slice into the running sums (the last slice writes the residual in
@@ -362,41 +363,63 @@ __global__ void __launch_bounds__(kThreads) amf_cols_kernel(AmfGeom G) {
 }
 
 // Fold the segment maps of each column into the carry entering every segment.
-// The maps of 8 segments are loaded before they are folded, so the loads
-// overlap instead of waiting one after another.
+// A workgroup takes 32 adjacent columns (coalesced rows of the map arrays)
+// and splits each column's segments, in scan order, over 8 threads: each
+// composes its share, the shares' compositions are combined in LDS, and each
+// thread walks its share again from its carry, writing the carries.
+constexpr int kCarryCols = 32;
+constexpr int kCarryGroups = kThreads / kCarryCols;   // 8
+
 template <int N, bool BACKWARD>
 __global__ void __launch_bounds__(kThreads) amf_carry_kernel(AmfGeom G) {
-  constexpr int kBatch = 8;
-  const int j = blockIdx.x * kThreads + threadIdx.x, p = blockIdx.y;
-  if (j >= G.W) return;
+  __shared__ float tot[kCarryGroups][1 + N][kCarryCols];
+  const int jj = threadIdx.x % kCarryCols, g = threadIdx.x / kCarryCols;
+  const int j = blockIdx.x * kCarryCols + jj, p = blockIdx.y;
+  const bool live = j < G.W;
   const int S = G.S, W = G.W;
+  const int share = (S + kCarryGroups - 1) / kCarryGroups;
+  const int q0 = min(S, g * share), q1 = min(S, q0 + share);   // scan positions of this thread
   const float* __restrict__ sum = G.sum;
   float* __restrict__ carry = BACKWARD ? G.carry_b : G.carry_f;
+  auto seg = [&](int q) { return BACKWARD ? S - 1 - q : q; };
+  // composition of this thread's share
+  float A = 1.0f, B[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) B[c] = 0.0f;
+  if (live) {
+#pragma unroll 4
+    for (int q = q0; q < q1; ++q) {
+      const float* sm = sum + static_cast<size_t>(p * S + seg(q)) * 5 * W + j;
+      const float a = sm[0];
+#pragma unroll
+      for (int c = 0; c < N; ++c) B[c] = fmaf(a, B[c], sm[(1 + c) * W]);
+      A *= a;
+    }
+  }
+  tot[g][0][jj] = A;
+#pragma unroll
+  for (int c = 0; c < N; ++c) tot[g][1 + c][jj] = B[c];
+  __syncthreads();
+  if (!live) return;
+  // carry into the share: the shares before it, in scan order, applied to 0
   float y[N];
 #pragma unroll
   for (int c = 0; c < N; ++c) y[c] = 0.0f;
-  for (int t0 = 0; t0 < S; t0 += kBatch) {
-    float m[kBatch][1 + N];
+  for (int h = 0; h < g; ++h) {
+    const float a = tot[h][0][jj];
 #pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      if (t0 + b < S) {
-        const int s = BACKWARD ? S - 1 - (t0 + b) : t0 + b;
-        const float* sm = sum + static_cast<size_t>(p * S + s) * 5 * W + j;
+    for (int c = 0; c < N; ++c) y[c] = fmaf(a, y[c], tot[h][1 + c][jj]);
+  }
+#pragma unroll 4
+  for (int q = q0; q < q1; ++q) {
+    const size_t at = static_cast<size_t>(p * S + seg(q));
+    const float* sm = sum + at * 5 * W + j;
+    float* cr = carry + at * 4 * W + j;
+    const float a = sm[0];
 #pragma unroll
-        for (int c = 0; c <= N; ++c) m[b][c] = sm[c * W];
-      }
-    }
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      if (t0 + b < S) {
-        const int s = BACKWARD ? S - 1 - (t0 + b) : t0 + b;
-        float* cr = carry + static_cast<size_t>(p * S + s) * 4 * W + j;
-#pragma unroll
-        for (int c = 0; c < N; ++c) {
-          cr[c * W] = y[c];
-          y[c] = fmaf(m[b][0], y[c], m[b][1 + c]);
-        }
-      }
+    for (int c = 0; c < N; ++c) {
+      cr[c * W] = y[c];
+      y[c] = fmaf(a, y[c], sm[(1 + c) * W]);
     }
   }
 }
@@ -429,7 +452,7 @@ template <int MODE>
 hipError_t launch_cols(const AmfGeom& G, hipStream_t s) {
   constexpr int N = Chans<MODE>::n;
   const dim3 seg((G.W + kThreads - 1) / kThreads, G.S, G.P);
-  const dim3 lines((G.W + kThreads - 1) / kThreads, G.P);
+  const dim3 lines((G.W + kCarryCols - 1) / kCarryCols, G.P);
   hipLaunchKernelGGL((amf_cols_kernel<MODE, 0>), seg, dim3(kThreads), 0, s, G);
   hipLaunchKernelGGL((amf_carry_kernel<N, false>), lines, dim3(kThreads), 0, s, G);
   hipLaunchKernelGGL((amf_cols_kernel<MODE, 1>), seg, dim3(kThreads), 0, s, G);

@@ -125,7 +125,7 @@ struct NcPlane {
 
 // One gradient field of one channel for the adaptive-manifold filter.
 constexpr int kAmfMaxHeight = 6;        // manifold tree height at most
-constexpr int kAmfSeg = 32;             // rows per segment of the column scans
+constexpr int kAmfSeg = 16;             // rows per segment of the column scans
 struct AmfPlane {
   const float* f;        // image whose gradients are filtered, [H][pitch]
   const float* g;        // range-source image or nullptr = f

@@ -4,7 +4,7 @@ the BLF) against the FP64 oracle, through the C ABI.
 The filter is a chain of recursive passes and smooth weights; the GPU runs it
 in FP32 (manifolds, weights and sums) and differs from the FP64 oracle only by
 rounding: max-abs 1e-5 for FP32 fields, 2e-3 and PSNR >= 50 dB for 16-bit
-fields.  The sizes span several row chunks, column workgroups and 32-row scan
+fields.  The sizes span several row chunks, column workgroups and 16-row scan
 segments with ragged tails; trees of height 1 to 4 are covered.  Rolling
 guidance makes iteration k's range source the previous output, which differs
 in its last bits between the two sides; iteration 2 is therefore checked
@@ -49,8 +49,8 @@ def _psnr(a, b):
 
 @pytest.mark.parametrize("H,W,ss,sr,lam", [
     (96, 128, 4.0, 0.05, 20.0),
-    (72, 90, 8.0, 0.05, 20.0),      # ragged: 3 segments (32, 32, 8), W below one column workgroup
-    (270, 300, 3.0, 0.08, 30.0),    # 9 segments (the last 14 rows), 2 column workgroups, 2 values per row chunk
+    (72, 90, 8.0, 0.05, 20.0),      # ragged: 5 scan segments (4 x 16, 8), W below one column workgroup
+    (270, 300, 3.0, 0.08, 30.0),    # 17 segments (the last 14 rows), 2 column workgroups, 2 values per row chunk
     (8, 12, 3.0, 0.05, 10.0),       # image smaller than one segment
     (2, 4, 1.0, 0.1, 5.0),
     (160, 30, 1.5, 0.08, 100.0),
