@@ -198,6 +198,7 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params *params, const f
  *   plan       a plan with C = 1 for the image's H x W (else BLFLS_E_INVALID)
  *   rgb        device [3][H][pitch] FP32 linear radiance, read only
  *   out        device [3][H][pitch] FP32, written; must not overlap rgb or the workspace
+ *              (nor may rgb overlap the workspace)
  *   contrast   target contrast of the compressed base, finite and > 1 (Durand and
  *              Dorsey use 5)
  *   workspace  at least blfls_tonemap_workspace_size(plan, params) bytes, 256-byte aligned

@@ -683,6 +683,8 @@ blfls_status blfls_tonemap(blfls_plan_t plan, const blfls_params* params, const 
   const size_t img_bytes = 3 * static_cast<size_t>(plan->H) * pitch * sizeof(float);
   if (overlaps(out, img_bytes, rgb, img_bytes) || overlaps(out, img_bytes, workspace, ws_bytes))
     return set_error(BLFLS_E_INVALID, "out must not overlap rgb or the workspace");
+  if (overlaps(rgb, img_bytes, workspace, ws_bytes))
+    return set_error(BLFLS_E_INVALID, "rgb must not overlap the workspace");
   uint8_t* ws = static_cast<uint8_t*>(workspace);
   float* L = reinterpret_cast<float*>(ws + off_l);
   float* base = reinterpret_cast<float*>(ws + off_base);
