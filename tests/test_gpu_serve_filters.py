@@ -74,3 +74,19 @@ def test_server_amf_workspace_admission():
         assert e.value.status == -3
     finally:
         small.close()
+
+
+@pytest.mark.parametrize("filt", ["nc", "grid", "amf"])
+def test_four_channel_plans_for_every_filter(filt):
+    # C = 4 (the largest plan): every filter's descriptors, item offsets and (AMF) workspace
+    # arrays cover the fourth channel, each channel matching the oracle on its own
+    import oracle
+    b = blfls()
+    f = np.stack([voronoi_image(48, 64, 1700 + c) for c in range(4)])
+    f32 = f.astype(np.float32)
+    u = b.smooth(_gpu(f32), lam=20.0, sigma_s=3.0, sigma_r=0.06, filter=filt)
+    torch.cuda.synchronize()
+    got = u.cpu().numpy().astype(np.float64)
+    for c in range(4):
+        ref = oracle.smooth(f32[c].astype(np.float64), 20.0, 3.0, 0.06, filter=filt)
+        assert np.max(np.abs(got[c] - ref)) <= 1e-5, (filt, c)
