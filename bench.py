@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="rgb1024", choices=["rgb1024", "uhd", "serve", "joint", "nc", "grid", "amf", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default=None,
+                    help="nc / amf workloads: run this configuration only (e.g. for a counter run)")
     ap.add_argument("--requests", type=int, default=2000)
     return ap.parse_args()
 
