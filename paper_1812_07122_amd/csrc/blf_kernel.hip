@@ -61,6 +61,7 @@ __device__ __forceinline__ void blf_item(const BlfPlane* __restrict__ planes, in
   __shared__ float p_lds[JOINT ? LH * LW : 1];
   __shared__ int rowmap[LH + 1];
   __shared__ int colmap[LW + 1];
+  __shared__ float ex_lds[2 * R + 1];
 
   const int pi = find_plane(planes, nplanes, item);
   const BlfPlane& P = planes[pi];
@@ -82,6 +83,8 @@ __device__ __forceinline__ void blf_item(const BlfPlane* __restrict__ planes, in
   // circular index maps of the halo tile (one extra row/column for the differences)
   for (int a = tid; a < LH + 1; a += T) rowmap[a] = wrap_index(y0 - R + a, H);
   for (int b = tid; b < LW + 1; b += T) colmap[b] = wrap_index(x0 - R + b, W);
+  // column weights in LDS: the dx loop reads them without a memory round trip
+  if (tid < 2 * R + 1) ex_lds[tid] = P.spatial[kSpan + kMaxR - R + tid];
   __syncthreads();
 
   const float* __restrict__ f = P.f;
@@ -132,9 +135,11 @@ __device__ __forceinline__ void blf_item(const BlfPlane* __restrict__ planes, in
   const int row0 = (tid >> 6) * K;
   const float* __restrict__ spatial = P.spatial;
 
+  // row weights are uniform over the workgroup: held in scalar registers
   float sy[2 * R + 1];
 #pragma unroll
-  for (int i = 0; i < 2 * R + 1; ++i) sy[i] = spatial[kMaxR - R + i];
+  for (int i = 0; i < 2 * R + 1; ++i)
+    sy[i] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(spatial[kMaxR - R + i])));
 
   float qs[K], ps[K], acc_n[K], acc_d[K];
 #pragma unroll
@@ -170,7 +175,7 @@ __device__ __forceinline__ void blf_item(const BlfPlane* __restrict__ planes, in
         }
       }
     }
-    const float e = spatial[kSpan + kMaxR + dx];
+    const float e = ex_lds[dx + R];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       acc_n[k] = fmaf(e, tn[k], acc_n[k]);
