@@ -40,6 +40,13 @@ __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2
 __device__ __forceinline__ float2 cmul_isg(float2 a, float sg) { return make_float2(-sg * a.y, sg * a.x); }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 
+// Product of two non-negative indices below 2^24 whose product fits 32 bits
+// (every LDS and per-plane spectrum index here): one full-rate 24-bit multiply
+// instead of the quarter-rate 32-bit one.
+__device__ __forceinline__ int imul(int a, int b) {
+  return static_cast<int>(__umul24(static_cast<uint32_t>(a), static_cast<uint32_t>(b)));
+}
+
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv d) {
   return (__umulhi(n, d.mul) + n) >> d.shift;
 }
@@ -174,8 +181,8 @@ struct LdsIO {  // in-place LDS buffer (padded layout)
   static constexpr bool kLds = true;
   float2* buf;
   int stride;
-  __device__ __forceinline__ float2 load(int b, int n) const { return buf[pad(b * stride + n)]; }
-  __device__ __forceinline__ void store(int b, int n, float2 v) const { buf[pad(b * stride + n)] = v; }
+  __device__ __forceinline__ float2 load(int b, int n) const { return buf[pad(imul(b, stride) + n)]; }
+  __device__ __forceinline__ void store(int b, int n, float2 v) const { buf[pad(imul(b, stride) + n)] = v; }
 };
 
 // One Stockham stage over `batch` transforms of length N.  Input element
@@ -199,20 +206,23 @@ __device__ __forceinline__ void fft_stage(const SRC& src, const DST& dst, int ba
     const int g = threadIdx.x + m * T;
     if (g < total) {
       const int b = static_cast<int>(fdiv(static_cast<uint32_t>(g), S.per_div));
-      const int j = g - b * per;
+      const int j = g - imul(b, per);
 #pragma unroll
       for (int t = 0; t < R; ++t) a[m][t] = src.load(b, j + t * per);
-      const int k = j - static_cast<int>(fdiv(static_cast<uint32_t>(j), S.ns_div)) * Ns;
+      const int k = j - imul(static_cast<int>(fdiv(static_cast<uint32_t>(j), S.ns_div)), Ns);
       outb[m] = b;
       outn[m] = (j - k) * R + k;
       if (Ns > 1) {
-        const int ek = k * S.es;
+        // w^t for t = 1..R-1 from one table lookup of w = W_N^(k es): squares
+        // for even t, one more factor w for odd t (at most 2 log2 t products
+        // deep, a few ulp), so a butterfly reads two table entries, not 2 (R-1)
+        float2 w[R];
+        w[1] = twiddle(tw, imul(k, S.es));
+        w[1].y = sg > 0.0f ? -w[1].y : w[1].y;  // the inverse takes the conjugate
 #pragma unroll
-        for (int t = 1; t < R; ++t) {
-          float2 wt = twiddle(tw, t * ek);
-          wt.y = sg > 0.0f ? -wt.y : wt.y;  // the inverse takes the conjugate
-          a[m][t] = cmul(a[m][t], wt);
-        }
+        for (int t = 2; t < R; ++t) w[t] = (t & 1) ? cmul(w[t - 1], w[1]) : cmul(w[t / 2], w[t / 2]);
+#pragma unroll
+        for (int t = 1; t < R; ++t) a[m][t] = cmul(a[m][t], w[t]);
       }
     }
   }
@@ -263,11 +273,34 @@ __device__ __forceinline__ void fft_run(const FftSize& sz, const float2* tw, flo
   fft_stage_r<T, MAXE>(lds, dst, batch, sz.st[n - 1], tw, sg);
 }
 
+// Global memory at a 32-bit byte offset from a base pointer: the load or store
+// takes the (workgroup-uniform) base in scalar registers and the offset in one
+// vector register, with no 64-bit address arithmetic per element.  Every plane,
+// field and spectrum here is far below 4 GiB.
+typedef float vf2 __attribute__((ext_vector_type(2)));
+template <class T>
+__device__ __forceinline__ T gload_raw(const void* base, uint32_t byte_off) {
+  return *(const __attribute__((address_space(1))) T*)((const __attribute__((address_space(1))) char*)base +
+                                                         byte_off);
+}
+template <class T>
+__device__ __forceinline__ T gload(const void* base, uint32_t byte_off) {
+  return gload_raw<T>(base, byte_off);
+}
+template <>
+__device__ __forceinline__ float2 gload<float2>(const void* base, uint32_t byte_off) {
+  const vf2 v = gload_raw<vf2>(base, byte_off);
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore(void* base, uint32_t byte_off, float2 v) {
+  *(__attribute__((address_space(1))) vf2*)((__attribute__((address_space(1))) char*)base + byte_off) = vf2{v.x, v.y};
+}
+
 // Two consecutive field values at an even index, as FP32.
 template <int FT>
-__device__ __forceinline__ float2 load_pair(const void* base, int64_t idx) {
-  if (FT == kF32) return *reinterpret_cast<const float2*>(static_cast<const float*>(base) + idx);
-  const uint32_t w = *reinterpret_cast<const uint32_t*>(static_cast<const uint16_t*>(base) + idx);
+__device__ __forceinline__ float2 load_pair(const void* base, uint32_t idx) {
+  if (FT == kF32) return gload<float2>(base, idx * 4u);
+  const uint32_t w = gload<uint32_t>(base, idx * 2u);
   if (FT == kBF16) return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xFFFF0000u));
   _Float16 h0, h1;
   const uint16_t lo = static_cast<uint16_t>(w & 0xFFFFu), hi = static_cast<uint16_t>(w >> 16);
@@ -277,9 +310,9 @@ __device__ __forceinline__ float2 load_pair(const void* base, int64_t idx) {
 }
 
 template <int FT>
-__device__ __forceinline__ float load_one(const void* base, int64_t idx) {
-  if (FT == kF32) return static_cast<const float*>(base)[idx];
-  const uint16_t v = static_cast<const uint16_t*>(base)[idx];
+__device__ __forceinline__ float load_one(const void* base, uint32_t idx) {
+  if (FT == kF32) return gload<float>(base, idx * 4u);
+  const uint16_t v = gload<uint16_t>(base, idx * 2u);
   if (FT == kBF16) return __uint_as_float(static_cast<uint32_t>(v) << 16);
   _Float16 h;
   __builtin_memcpy(&h, &v, 2);
@@ -326,10 +359,10 @@ struct RhsSrc {
     const int im1 = i == 0 ? H - 1 : i - 1;
     const int j0 = 2 * n;
     const int jm = j0 == 0 ? W - 1 : j0 - 1;
-    const int64_t ri = static_cast<int64_t>(i) * W;
+    const uint32_t ri = imul(i, W);
     const float2 x = load_pair<FT>(rx, ri + j0);
     const float2 y = load_pair<FT>(ry, ri + j0);
-    const float2 yp = load_pair<FT>(ry, static_cast<int64_t>(im1) * W + j0);
+    const float2 yp = load_pair<FT>(ry, imul(im1, W) + j0);
     const float xm = load_one<FT>(rx, ri + jm);
     return make_float2(lam * ((xm - x.x) + (yp.x - y.x)), lam * ((x.x - x.y) + (yp.y - y.y)));
   }
@@ -340,8 +373,8 @@ struct ColIO {
   static constexpr bool kLds = false;
   float2* spec;
   int H;
-  __device__ __forceinline__ float2 load(int b, int n) const { return spec[static_cast<int64_t>(b) * H + n]; }
-  __device__ __forceinline__ void store(int b, int n, float2 v) const { spec[static_cast<int64_t>(b) * H + n] = v; }
+  __device__ __forceinline__ float2 load(int b, int n) const { return gload<float2>(spec, 8u * (imul(b, H) + n)); }
+  __device__ __forceinline__ void store(int b, int n, float2 v) const { gstore(spec, 8u * (imul(b, H) + n), v); }
 };
 
 // LDS destination that applies the Eq. (8) divide, 1 / (H W (1 + lam (sx + sy)))
@@ -357,7 +390,7 @@ struct ScaledLds {
     const float den = fmaf(lam, sx[k0 + b] + sy[n], 1.0f);
     // den >= 1: the hardware reciprocal (1 ulp) instead of a correctly rounded
     // division, which costs ten instructions per spectrum value
-    buf[pad(b * H + n)] = cscale(v, inv_hw * __builtin_amdgcn_rcpf(den));
+    buf[pad(imul(b, H) + n)] = cscale(v, inv_hw * __builtin_amdgcn_rcpf(den));
   }
 };
 
@@ -411,12 +444,12 @@ __device__ __forceinline__ void rows_fwd_item(const FftPlane* __restrict__ plane
       k = idx / nrows;
       row = idx - k * nrows;
     }
-    const float2 zk = buf[pad(row * M + (k == M ? 0 : k))];
-    const float2 zm = buf[pad(row * M + (k == 0 ? 0 : M - k))];
+    const float2 zk = buf[pad(imul(row, M) + (k == M ? 0 : k))];
+    const float2 zm = buf[pad(imul(row, M) + (k == 0 ? 0 : M - k))];
     const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     // o = (zk - conj(zm)) / (2i)
     const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-    spec[static_cast<int64_t>(k) * H + i0 + row] = cadd(e, cmul(twiddle(twR, k), o));
+    gstore(spec, 8u * (imul(k, H) + i0 + row), cadd(e, cmul(twiddle(twR, k), o)));
   }
 }
 
@@ -485,8 +518,8 @@ __device__ __forceinline__ void rows_inv_item(const FftPlane* __restrict__ plane
           k = idx / nrows;
           row = idx - k * nrows;
         }
-        v[u] = spec[static_cast<int64_t>(k) * H + i0 + row];
-        dst[u] = pad(row * S + k);
+        v[u] = gload<float2>(spec, 8u * (imul(k, H) + i0 + row));
+        dst[u] = pad(imul(row, S) + k);
       }
     }
 #pragma unroll
@@ -500,7 +533,7 @@ __device__ __forceinline__ void rows_inv_item(const FftPlane* __restrict__ plane
   for (int idx = tid; idx < (half + 1) * nrows; idx += T) {
     const int row = idx / (half + 1);
     const int k = idx - row * (half + 1);
-    const int ia = pad(row * S + k), ib = pad(row * S + M - k);
+    const int ia = pad(imul(row, S) + k), ib = pad(imul(row, S) + M - k);
     const float2 a = buf[ia], b = buf[ib];
     const float2 wa = cconj(twiddle(twR, k));  // exp(+2 pi i k/W)
     const float2 wb = cconj(twiddle(twR, M - k));
