@@ -229,7 +229,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
-              "(independent images shard across GPUs without communication; see the design notes)",
+              "(independent images and requests shard across GPUs without communication)",
               file=sys.stderr)
         sys.exit(2)
     state = None
