@@ -13,10 +13,12 @@
 //
 // Since d >= 1, a window never reaches more than floor(r_k) pixels from its
 // centre, so each pass is a halo-tile kernel like the bilateral filter's:
-//   * row passes: a wave owns a 64-pixel row segment; the segment plus an
-//     R-pixel halo of values and increments is staged in LDS;
-//   * column passes: a workgroup owns a 64 x 64 tile (lane = column, each wave
-//     16 rows) with an R-row halo in LDS, so global loads stay coalesced;
+//   * row passes: a wave owns a 256-pixel row segment (four outputs per
+//     lane); the segment plus an R-pixel halo of values and increments is
+//     staged in LDS;
+//   * column passes: a workgroup owns a 32-column x 64-row tile (a wave holds
+//     32 columns x 2 row groups, each lane 8 rows) with an R-row halo in LDS,
+//     so global loads read whole 128-byte lines;
 //   * each output walks outward from its pixel, accumulating the increments in
 //     FP32 (one rounding per addition, no contraction) until the distance
 //     exceeds r_k, and averages the values it passed.  Window membership is an
@@ -33,10 +35,12 @@ namespace blfls {
 
 namespace {
 
-constexpr int kSeg = 64;        // pixels of a row segment (one wave) / columns of a tile
+constexpr int kColW = 32;       // columns of a column-pass tile
+constexpr int kRowSeg = 256;    // pixels of a row segment (one wave, four per lane)
 constexpr int kRowWaves = 4;    // row segments per row-pass workgroup
 constexpr int kColRows = 64;    // rows of a column-pass tile (16 per wave)
-constexpr int kLine = kSeg + 2 * kNcMaxR;
+constexpr int kLine = kRowSeg + 2 * kNcMaxR;
+constexpr int kLineLoads = (kLine + 63) / 64;  // staged values per lane
 
 __device__ __forceinline__ int next_wrap(int i, int n) { return i + 1 == n ? 0 : i + 1; }
 
@@ -155,10 +159,10 @@ __global__ void __launch_bounds__(256) nc_rows_kernel(const NcPlane* __restrict_
   const int field = local >= per_field ? 1 : 0;
   const int tile = local - field * per_field;
   const int H = P.H, W = P.W;
-  const int segs = (W + kSeg - 1) / kSeg;
+  const int segs = (W + kRowSeg - 1) / kRowSeg;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = (tile / segs) * kRowWaves + wave;
-  const int j0 = (tile % segs) * kSeg;
+  const int j0 = (tile % segs) * kRowSeg;
   float inv;
   const bool scaled = field_scale(P, field, &inv);
   const float* __restrict__ f = P.f;
@@ -166,34 +170,55 @@ __global__ void __launch_bounds__(256) nc_rows_kernel(const NcPlane* __restrict_
   const int64_t gp = P.g ? P.gpitch : P.pitch;
   const float* __restrict__ in = P.buf[src][field];
   if (i < H) {
-    for (int t = lane; t < kSeg + 2 * R; t += kSeg) {
+    // every load of the staged line is issued before the first LDS store
+    float vv[kLineLoads], dd[kLineLoads];
+#pragma unroll
+    for (int u = 0; u < kLineLoads; ++u) {
+      const int t = lane + 64 * u;
       const int m = j0 - R + t;
-      if (m >= 0 && m < W) {
-        sv[wave][t] = FIRST ? grad_at(f, P.pitch, H, W, i, m, field) : in[static_cast<int64_t>(i) * W + m];
+      vv[u] = 0.0f;
+      dd[u] = 0.0f;
+      if (t < kRowSeg + 2 * R && m >= 0 && m < W) {
+        vv[u] = FIRST ? grad_at(f, P.pitch, H, W, i, m, field) : in[static_cast<int64_t>(i) * W + m];
         if (m >= 1)
-          sd[wave][t] = dt_increment(grad_at(g, gp, H, W, i, m, field), grad_at(g, gp, H, W, i, m - 1, field), P.a,
-                                     inv, scaled);
+          dd[u] = dt_increment(grad_at(g, gp, H, W, i, m, field), grad_at(g, gp, H, W, i, m - 1, field), P.a, inv,
+                               scaled);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kLineLoads; ++u) {
+      const int t = lane + 64 * u;
+      if (t < kLine) {
+        sv[wave][t] = vv[u];
+        sd[wave][t] = dd[u];
       }
     }
   }
   __syncthreads();
-  const int j = j0 + lane;
-  if (i < H && j < W) {
-    const float out = nc_window_mean(sv[wave], sd[wave], 1, lane + R, min(R, W - 1 - j), min(R, j), r);
-    P.buf[src ^ 1][field][static_cast<int64_t>(i) * W + j] = out;
+  if (i < H) {
+#pragma unroll
+    for (int q = 0; q < kRowSeg / 64; ++q) {
+      const int j = j0 + lane + 64 * q;
+      if (j < W) {
+        const float out = nc_window_mean(sv[wave], sd[wave], 1, lane + 64 * q + R, min(R, W - 1 - j), min(R, j), r);
+        P.buf[src ^ 1][field][static_cast<int64_t>(i) * W + j] = out;
+      }
+    }
   }
 }
 
-// Column pass: items (plane, field, 64 x 64 tile).  Reads buf[src]; writes
-// buf[src ^ 1], or with LAST the residual NC(p) - p in field type FT.
-// Dynamic LDS: 2 x (64 + 2R) x 64 floats.
+// Column pass: items (plane, field, 32-column x 64-row tile).  Reads buf[src];
+// writes buf[src ^ 1], or with LAST the residual NC(p) - p in field type FT.
+// Lane l of a wave takes column l mod 32 and, of the wave's 16 rows, the 8
+// starting at 8 (l / 32).  Dynamic LDS: 2 x (64 + 2R) x 32 floats.
 template <bool LAST>
 __global__ void __launch_bounds__(256) nc_cols_kernel(const NcPlane* __restrict__ planes, int nplanes, int src,
                                                       float r, int R, int field_type) {
   extern __shared__ float smem[];
+  constexpr int kRowsPerLoad = 256 / kColW;   // staged rows per load instruction of the workgroup
   const int rows = kColRows + 2 * R;
   float* sv = smem;
-  float* sd = smem + rows * kSeg;
+  float* sd = smem + rows * kColW;
   const int item = blockIdx.x;
   const NcPlane& P = planes[find_nc_plane<true>(planes, nplanes, item)];
   const int local = item - P.cbegin;
@@ -201,23 +226,25 @@ __global__ void __launch_bounds__(256) nc_cols_kernel(const NcPlane* __restrict_
   const int field = local >= per_field ? 1 : 0;
   const int tile = local - field * per_field;
   const int H = P.H, W = P.W;
-  const int tiles_x = (W + kSeg - 1) / kSeg;
+  const int tiles_x = (W + kColW - 1) / kColW;
   const int i0 = (tile / tiles_x) * kColRows;
-  const int j0 = (tile % tiles_x) * kSeg;
+  const int j0 = (tile % tiles_x) * kColW;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int j = j0 + lane;
+  const int c = threadIdx.x & (kColW - 1);
+  const int j = j0 + c;
   float inv;
   const bool scaled = field_scale(P, field, &inv);
   const float* __restrict__ g = P.g ? P.g : P.f;
   const int64_t gp = P.g ? P.gpitch : P.pitch;
   const float* __restrict__ in = P.buf[src][field];
   if (j < W) {
-    // four rows per round: all loads of a round are issued before its LDS stores
-    for (int t0 = wave; t0 < rows; t0 += 16) {
+    // four staged rows per thread and round: all loads of a round are issued
+    // before its LDS stores
+    for (int tb = threadIdx.x / kColW; tb < rows; tb += 4 * kRowsPerLoad) {
       float fv[4], dv[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int t = t0 + 4 * u;
+        const int t = tb + kRowsPerLoad * u;
         const int m = i0 - R + t;
         fv[u] = 0.0f;
         dv[u] = 0.0f;
@@ -230,21 +257,22 @@ __global__ void __launch_bounds__(256) nc_cols_kernel(const NcPlane* __restrict_
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int t = t0 + 4 * u;
+        const int t = tb + kRowsPerLoad * u;
         const int m = i0 - R + t;
         if (t < rows && m >= 0 && m < H) {
-          sv[t * kSeg + lane] = fv[u];
-          if (m >= 1) sd[t * kSeg + lane] = dv[u];
+          sv[t * kColW + c] = fv[u];
+          if (m >= 1) sd[t * kColW + c] = dv[u];
         }
       }
     }
   }
   __syncthreads();
   if (j < W) {
-    for (int rr = 0; rr < kColRows / 4; ++rr) {
-      const int i = i0 + wave * (kColRows / 4) + rr;
+    const int rbase = wave * (kColRows / 4) + (lane / kColW) * (kColRows / 8);
+    for (int rr = 0; rr < kColRows / 8; ++rr) {
+      const int i = i0 + rbase + rr;
       if (i >= H) break;
-      const float out = nc_window_mean(sv + lane, sd + lane, kSeg, i - i0 + R, min(R, H - 1 - i), min(R, i), r);
+      const float out = nc_window_mean(sv + c, sd + c, kColW, i - i0 + R, min(R, H - 1 - i), min(R, i), r);
       const int64_t o = static_cast<int64_t>(i) * W + j;
       if (LAST) {
         const float res = out - grad_at(P.f, P.pitch, H, W, i, j, field);
@@ -256,12 +284,12 @@ __global__ void __launch_bounds__(256) nc_cols_kernel(const NcPlane* __restrict_
   }
 }
 
-int nc_row_items(int H, int W) { return 2 * ((H + kRowWaves - 1) / kRowWaves) * ((W + kSeg - 1) / kSeg); }
-int nc_col_items(int H, int W) { return 2 * ((H + kColRows - 1) / kColRows) * ((W + kSeg - 1) / kSeg); }
+int nc_row_items(int H, int W) { return 2 * ((H + kRowWaves - 1) / kRowWaves) * ((W + kRowSeg - 1) / kRowSeg); }
+int nc_col_items(int H, int W) { return 2 * ((H + kColRows - 1) / kColRows) * ((W + kColW - 1) / kColW); }
 
 hipError_t nc_init_kernels() {
-  // column passes stage up to 2 x 128 x 64 floats (64 KiB) of dynamic LDS
-  const int kMax = 2 * (kColRows + 2 * kNcMaxR) * kSeg * static_cast<int>(sizeof(float));
+  // column passes stage up to 2 x 128 x 32 floats (32 KiB) of dynamic LDS
+  const int kMax = 2 * (kColRows + 2 * kNcMaxR) * kColW * static_cast<int>(sizeof(float));
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&nc_cols_kernel<true>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, kMax);
   if (e == hipSuccess)
@@ -281,7 +309,7 @@ hipError_t launch_nc_pass(const NcPlane* planes, int nplanes, int items, int pas
     else
       hipLaunchKernelGGL(nc_rows_kernel<false>, dim3(items), dim3(256), 0, s, planes, nplanes, src, r, R);
   } else {
-    const size_t lds = static_cast<size_t>(2) * (kColRows + 2 * R) * kSeg * sizeof(float);
+    const size_t lds = static_cast<size_t>(2) * (kColRows + 2 * R) * kColW * sizeof(float);
     if (pass == npasses - 1)
       hipLaunchKernelGGL(nc_cols_kernel<true>, dim3(items), dim3(256), lds, s, planes, nplanes, src, r, R,
                          field_type);
