@@ -16,8 +16,8 @@
 //   * row passes: a wave owns a 256-pixel row segment (four outputs per
 //     lane); the segment plus an R-pixel halo of values and increments is
 //     staged in LDS;
-//   * column passes: a workgroup owns a 32-column x 64-row tile (a wave holds
-//     32 columns x 2 row groups, each lane 8 rows) with an R-row halo in LDS,
+//   * column passes: a workgroup owns a 32-column x 32-row tile (a wave holds
+//     32 columns x 2 row groups) with an R-row halo in LDS,
 //     so global loads read whole 128-byte lines;
 //   * each output walks outward from its pixel, accumulating the increments in
 //     FP32 (one rounding per addition, no contraction) until the distance
@@ -38,7 +38,7 @@ namespace {
 constexpr int kColW = 32;       // columns of a column-pass tile
 constexpr int kRowSeg = 256;    // pixels of a row segment (one wave, four per lane)
 constexpr int kRowWaves = 4;    // row segments per row-pass workgroup
-constexpr int kColRows = 64;    // rows of a column-pass tile (16 per wave)
+constexpr int kColRows = 32;    // rows of a column-pass tile (8 per wave)
 constexpr int kLine = kRowSeg + 2 * kNcMaxR;
 constexpr int kLineLoads = (kLine + 63) / 64;  // staged values per lane
 
@@ -207,10 +207,10 @@ __global__ void __launch_bounds__(256) nc_rows_kernel(const NcPlane* __restrict_
   }
 }
 
-// Column pass: items (plane, field, 32-column x 64-row tile).  Reads buf[src];
+// Column pass: items (plane, field, 32-column x 32-row tile).  Reads buf[src];
 // writes buf[src ^ 1], or with LAST the residual NC(p) - p in field type FT.
-// Lane l of a wave takes column l mod 32 and, of the wave's 16 rows, the 8
-// starting at 8 (l / 32).  Dynamic LDS: 2 x (64 + 2R) x 32 floats.
+// Lane l of a wave takes column l mod 32 and, of the wave's 8 rows, the 4
+// starting at 4 (l / 32).  Dynamic LDS: 2 x (32 + 2R) x 32 floats.
 template <bool LAST>
 __global__ void __launch_bounds__(256) nc_cols_kernel(const NcPlane* __restrict__ planes, int nplanes, int src,
                                                       float r, int R, int field_type) {
@@ -288,7 +288,7 @@ int nc_row_items(int H, int W) { return 2 * ((H + kRowWaves - 1) / kRowWaves) * 
 int nc_col_items(int H, int W) { return 2 * ((H + kColRows - 1) / kColRows) * ((W + kColW - 1) / kColW); }
 
 hipError_t nc_init_kernels() {
-  // column passes stage up to 2 x 128 x 32 floats (32 KiB) of dynamic LDS
+  // column passes stage up to 2 x 96 x 32 floats (24 KiB) of dynamic LDS
   const int kMax = 2 * (kColRows + 2 * kNcMaxR) * kColW * static_cast<int>(sizeof(float));
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&nc_cols_kernel<true>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, kMax);
