@@ -87,6 +87,7 @@ struct FftPlane {
   float gain;            // scale of delta: 1, or 1 - m for detail gain m on the last iteration
   int rb;                // rows per row-pass workgroup
   int cb;                // spectrum columns per column-pass workgroup
+  int colw;              // L when H = 64 L is done one column per wave (L = 8, 16), else 0
   int row_begin, row_count;   // workgroups of the row passes
   int col_begin, col_count;   // workgroups of the column pass
   const FftSize* szM;    // W/2 complex transform

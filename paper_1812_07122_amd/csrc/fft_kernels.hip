@@ -454,6 +454,149 @@ __device__ __forceinline__ void rows_fwd_item(const FftPlane* __restrict__ plane
 }
 
 // ---------------------------------------------------------------------------
+// Pass 2 for H = 64 L (L = 8, 16): one wave per spectrum column, the column in
+// registers.  With n = l + 64 m (lane l, register m) and k = k1 + L k2:
+//   X[k1 + L k2] = sum_l W_64^(l k2) W_H^(l k1) sum_m x[l + 64 m] W_L^(m k1),
+// so each lane takes an L-point DFT of its registers and a twiddle, and the
+// 64-point DFTs over the lanes (one per k1) run as 8 x 8 (l = l1 + 8 l2,
+// k2 = k2a + 8 k2b) through a wave-private LDS block: 8-point DFTs over l2,
+// the twiddle W_64^(l1 k2a), 8-point DFTs over l1.  The divide applies to the
+// registers that hold X[k], and the inverse retraces the same steps with
+// conjugate twiddles.  No workgroup barrier: a wave orders its own LDS
+// accesses, so a wave-scope fence between the exchanges suffices.
+// ---------------------------------------------------------------------------
+constexpr int kWaveCols = kFftThreads / 64;   // columns per workgroup
+
+// Slot of entry (row, col) of the 8 x 8 block k1 in a wave's LDS: a bijection
+// on the block whose rows are rotated by k1 and whose columns are XOR-ed with
+// the row, so the column reads, the row reads and the lane-order transposes
+// each touch 16 distinct 8-byte bank pairs per 16 lanes.
+__device__ __forceinline__ int wslot(int k1, int row, int col) {
+  return k1 * 64 + (((row + k1) & 7) << 3) + (col ^ row);
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Powers w^t for t < N (N a multiple of 4, at most 16) as w^(t & 3) w^(4 (t >> 2)):
+// six or fewer products, at most four deep, and eight registers at N = 16.
+template <int N>
+struct Powers {
+  float2 lo[4], hi[N / 4];   // w^0..w^3 and w^0, w^4, w^8, w^12
+  __device__ __forceinline__ explicit Powers(float2 w) {
+    lo[0] = make_float2(1.0f, 0.0f);
+    lo[1] = w;
+    lo[2] = cmul(w, w);
+    lo[3] = cmul(lo[2], w);
+    hi[0] = lo[0];
+    if (N > 4) hi[1] = cmul(lo[2], lo[2]);
+#pragma unroll
+    for (int j = 2; j < N / 4; ++j) hi[j] = cmul(hi[j - 1], hi[1]);
+  }
+  // v w^t (t known at compile time after unrolling)
+  __device__ __forceinline__ float2 mul(float2 v, int t) const {
+    if (t & 3) v = cmul(v, lo[t & 3]);
+    if (t >> 2) v = cmul(v, hi[t >> 2]);
+    return v;
+  }
+  __device__ __forceinline__ float2 mul_conj(float2 v, int t) const {
+    if (t & 3) v = cmul(v, cconj(lo[t & 3]));
+    if (t >> 2) v = cmul(v, cconj(hi[t >> 2]));
+    return v;
+  }
+};
+
+template <int L>
+__device__ __forceinline__ void cols_wave_item(const FftPlane& P, int blk, float2* smem) {
+  const int H = P.H, W = P.W, M = W >> 1;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int c = blk * kWaveCols + wave;
+  if (c > M) return;   // no workgroup barrier follows
+  float2* T = smem + wave * (L * 64);
+  const uint32_t base = 8u * static_cast<uint32_t>(imul(c, H));
+  const float2* tw = P.twH;   // two-level table of W_H; entries below 64 are W_H^j
+
+  float2 a[L];
+#pragma unroll
+  for (int m = 0; m < L; ++m) a[m] = gload<float2>(P.spec, base + 8u * (l + 64 * m));
+  butterfly<L>(a, -1.0f);
+  {
+    const Powers<L> pw(tw[l]);   // W_H^(l k1)
+#pragma unroll
+    for (int k1 = 1; k1 < L; ++k1) a[k1] = pw.mul(a[k1], k1);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < L; ++k1) T[wslot(k1, l >> 3, l & 7)] = a[k1];
+  wave_lds_sync();
+
+  // 8-point DFTs over l2 for each (k1, l1), then W_64^(l1 k2a)
+#pragma unroll
+  for (int q = 0; q < L / 8; ++q) {
+    const int p = l + 64 * q, k1 = p >> 3, l1 = p & 7;
+    float2 b[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) b[r] = T[wslot(k1, r, l1)];
+    butterfly<8>(b, -1.0f);
+    const Powers<8> pv(twiddle(tw, l1 * L));   // W_64^l1 = W_H^(l1 L)
+#pragma unroll
+    for (int r = 1; r < 8; ++r) b[r] = pv.mul(b[r], r);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) T[wslot(k1, r, l1)] = b[r];
+  }
+  wave_lds_sync();
+
+  // 8-point DFTs over l1 for each (k1, k2a): X[k1 + L (k2a + 8 k2b)]; the
+  // Eq. (8) divide; the inverse 8-point DFTs over k2b
+  const float sxc = P.sx[c];
+  const float inv_hw = P.gain * (1.0f / (static_cast<float>(H) * static_cast<float>(W)));
+#pragma unroll
+  for (int q = 0; q < L / 8; ++q) {
+    const int p = l + 64 * q, k1 = p >> 3, k2a = p & 7;
+    float2 d[8];
+#pragma unroll
+    for (int col = 0; col < 8; ++col) d[col] = T[wslot(k1, k2a, col)];
+    butterfly<8>(d, -1.0f);
+#pragma unroll
+    for (int k2b = 0; k2b < 8; ++k2b) {
+      const float den = fmaf(P.lambda, sxc + P.sy[k1 + L * (k2a + 8 * k2b)], 1.0f);
+      d[k2b] = cscale(d[k2b], inv_hw * __builtin_amdgcn_rcpf(den));
+    }
+    butterfly<8>(d, 1.0f);
+#pragma unroll
+    for (int col = 0; col < 8; ++col) T[wslot(k1, k2a, col)] = d[col];
+  }
+  wave_lds_sync();
+
+  // conjugate twiddles W_64^(-l1 k2a), inverse 8-point DFTs over k2a
+#pragma unroll
+  for (int q = 0; q < L / 8; ++q) {
+    const int p = l + 64 * q, k1 = p >> 3, l1 = p & 7;
+    float2 e[8];
+    const Powers<8> pv(twiddle(tw, l1 * L));
+#pragma unroll
+    for (int r = 0; r < 8; ++r) e[r] = pv.mul_conj(T[wslot(k1, r, l1)], r);
+    butterfly<8>(e, 1.0f);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) T[wslot(k1, r, l1)] = e[r];
+  }
+  wave_lds_sync();
+
+#pragma unroll
+  for (int k1 = 0; k1 < L; ++k1) a[k1] = T[wslot(k1, l >> 3, l & 7)];
+  {
+    const Powers<L> pw(tw[l]);
+#pragma unroll
+    for (int k1 = 1; k1 < L; ++k1) a[k1] = pw.mul_conj(a[k1], k1);
+  }
+  butterfly<L>(a, 1.0f);
+#pragma unroll
+  for (int m = 0; m < L; ++m) gstore(P.spec, base + 8u * (l + 64 * m), a[m]);
+}
+
+// ---------------------------------------------------------------------------
 // Pass 2: per spectrum column, forward FFT over H, divide, inverse FFT over H.
 // The forward transform reads the columns from HBM in its first stage and
 // applies the divide in its last; the inverse writes HBM in its last stage.
@@ -465,6 +608,14 @@ __device__ __forceinline__ void cols_item(const FftPlane* __restrict__ planes, i
   const FftPlane& P = planes[find_fft_plane<true>(planes, nplanes, item)];
   const int blk = item - P.col_begin;
   if (blk >= P.col_count) return;
+  if (P.colw == 16) {
+    cols_wave_item<16>(P, blk, smem);
+    return;
+  }
+  if (P.colw == 8) {
+    cols_wave_item<8>(P, blk, smem);
+    return;
+  }
   const int H = P.H, W = P.W, M = W >> 1;
   const int k0 = blk * P.cb;
   const int ncols = min(P.cb, M + 1 - k0);
@@ -615,6 +766,8 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader
 static size_t padded(int n) { return static_cast<size_t>(n) + static_cast<size_t>(n) / 16 + 1; }
 size_t fft_rows_lds_bytes(int M, int rb) { return (2 * kTwMax + padded(rb * (M + 1))) * sizeof(float2); }
 size_t fft_cols_lds_bytes(int H, int cb) { return (kTwMax + padded(cb * H)) * sizeof(float2); }
+int fft_cols_wave_per_block() { return kWaveCols; }
+size_t fft_cols_wave_lds_bytes(int L) { return static_cast<size_t>(kWaveCols) * L * 64 * sizeof(float2); }
 
 hipError_t fft_init_kernels() {
   const int kMax = 128 * 1024;  // largest need is about 73 KiB; static LDS comes on top
