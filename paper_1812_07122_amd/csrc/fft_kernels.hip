@@ -602,17 +602,21 @@ __device__ __forceinline__ void cols_wave_item(const FftPlane& P, int blk, float
 // applies the divide in its last; the inverse writes HBM in its last stage.
 // LDS: [table of W_H: kTwMax][columns: cb x H, padded]
 // ---------------------------------------------------------------------------
+// WAVE: planes with colw take the one-column-per-wave transform (direct
+// launches; the persistent kernel omits that path, which keeps it within its
+// register budget, and the server launches such steps directly).
+template <bool WAVE>
 __device__ __forceinline__ void cols_item(const FftPlane* __restrict__ planes, int nplanes, int item,
                                           float2* smem) {
   constexpr int T = kFftThreads;
   const FftPlane& P = planes[find_fft_plane<true>(planes, nplanes, item)];
   const int blk = item - P.col_begin;
   if (blk >= P.col_count) return;
-  if (P.colw == 16) {
+  if (WAVE && P.colw == 16) {
     cols_wave_item<16>(P, blk, smem);
     return;
   }
-  if (P.colw == 8) {
+  if (WAVE && P.colw == 8) {
     cols_wave_item<8>(P, blk, smem);
     return;
   }
@@ -729,7 +733,7 @@ __global__ void __launch_bounds__(kFftThreads, 4)
 fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
   extern __shared__ float2 smem[];
   if (!PERSIST) {
-    cols_item(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
+    cols_item<true>(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
     return;
   }
   const int total = work->items2, np = work->nplanes;
@@ -737,7 +741,7 @@ fft_cols_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __
   for (;;) {
     const int item = grab_item(work->next[1], total, true);
     if (item >= total) break;
-    cols_item(pl, np, item, smem);
+    cols_item<false>(pl, np, item, smem);
     __syncthreads();
   }
 }
