@@ -294,15 +294,19 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   rb = std::min(rb, floor_pow2(H));
   int cb = std::min(16, std::max(1, kFftLdsComplex / H));
   while (cb > 1 && static_cast<long>(C) * ((M + 1 + cb - 1) / cb) < 256) cb = (cb + 1) / 2;
-  // H = 512 or 1024: one spectrum column per wave, held in registers
+  // H = 512 or 1024: one spectrum column per wave, held in registers; likewise
+  // one row per wave for W/2 = 512 or 1024
   const int colw = (H == 512 || H == 1024) ? H / 64 : 0;
   if (colw) cb = fft_cols_wave_per_block();
+  const int roww = (M == 512 || M == 1024) ? M / 64 : 0;
+  if (roww) rb = fft_cols_wave_per_block();
   p->rb = rb;
   p->cb = cb;
   p->colw = colw;
+  p->roww = roww;
   p->row_blocks = (H + rb - 1) / rb;
   p->col_blocks = (M + 1 + cb - 1) / cb;
-  p->lds_rows = fft_rows_lds_bytes(M, rb);
+  p->lds_rows = roww ? fft_rows_wave_lds_bytes(roww) : fft_rows_lds_bytes(M, rb);
   p->lds_cols = colw ? fft_cols_wave_lds_bytes(colw) : fft_cols_lds_bytes(H, cb);
   p->tiles_x = (W + blf_tile_w() - 1) / blf_tile_w();
   p->tiles_y = (H + blf_tile_h() - 1) / blf_tile_h();
@@ -501,7 +505,7 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
     F.spec = reinterpret_cast<float2*>(wsb + plan->off_spec) + static_cast<size_t>(ch) * (M + 1) * H;
     F.f = fc; F.u = uc; F.pitch = pitch;
     F.H = H; F.W = W; F.lambda = prm.lambda;
-    F.rb = plan->rb; F.cb = plan->cb; F.colw = plan->colw;
+    F.rb = plan->rb; F.cb = plan->cb; F.colw = plan->colw; F.roww = plan->roww;
     F.row_begin = ch * plan->row_blocks; F.row_count = plan->row_blocks;
     F.col_begin = ch * plan->col_blocks; F.col_count = plan->col_blocks;
     F.szM = plan->szM; F.szH = plan->szH;

@@ -88,6 +88,7 @@ struct FftPlane {
   int rb;                // rows per row-pass workgroup
   int cb;                // spectrum columns per column-pass workgroup
   int colw;              // L when H = 64 L is done one column per wave (L = 8, 16), else 0
+  int roww;              // L when W/2 = 64 L is done one row per wave (L = 8, 16), else 0
   int row_begin, row_count;   // workgroups of the row passes
   int col_begin, col_count;   // workgroups of the column pass
   const FftSize* szM;    // W/2 complex transform

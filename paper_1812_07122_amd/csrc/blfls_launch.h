@@ -32,6 +32,8 @@ size_t fft_cols_lds_bytes(int H, int cb);
 // Column pass with one column per wave (H = 64 L): columns per workgroup, LDS bytes.
 int fft_cols_wave_per_block();
 size_t fft_cols_wave_lds_bytes(int L);
+// Row passes with one row per wave (W/2 = 64 L): LDS bytes (rows per workgroup as above).
+size_t fft_rows_wave_lds_bytes(int L);
 hipError_t fft_init_kernels();
 hipError_t launch_fft_rows_fwd(const FftPlane* planes, int nplanes, int blocks, size_t lds_bytes,
                                int field_type, hipStream_t s, WorkHeader* work = nullptr);

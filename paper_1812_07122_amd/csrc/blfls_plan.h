@@ -26,6 +26,7 @@ struct blfls_plan_s {
   // FFT pass geometry
   int rb = 1, cb = 1;
   int colw = 0;                         // column pass one column per wave for H = 64 colw
+  int roww = 0;                         // row passes one row per wave for W/2 = 64 roww
   int row_blocks = 0, col_blocks = 0;   // per channel
   size_t lds_rows = 0, lds_cols = 0;
   // BLF geometry

@@ -409,63 +409,17 @@ struct OutDst {
 };
 
 // ---------------------------------------------------------------------------
-// Pass 1: c = lam (D_x^T r_x + D_y^T r_y), real FFT of each row, transposed store
-// LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1), padded]
-// ---------------------------------------------------------------------------
-template <int FT>
-__device__ __forceinline__ void rows_fwd_item(const FftPlane* __restrict__ planes, int nplanes, int item,
-                                              float2* smem) {
-  constexpr int T = kFftThreads;
-  const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
-  const int blk = item - P.row_begin;
-  if (blk >= P.row_count) return;
-  const int H = P.H, W = P.W, M = W >> 1;
-  const int i0 = blk * P.rb;
-  const int nrows = min(P.rb, H - i0);
-  const int tid = threadIdx.x;
-  float2* twS = smem;
-  float2* twR = smem + kTwMax;
-  float2* buf = smem + 2 * kTwMax;
-  stage_twiddles<T>(twS, P.twM, P.ntwM);
-  stage_twiddles<T>(twR, P.twW, P.ntwW);
-  __syncthreads();
-  // the first stage forms the right-hand side straight from the residual fields
-  const LdsIO lds{buf, M};
-  fft_run<T, kFftLdsComplex>(*P.szM, twS, -1.0f, nrows, RhsSrc<FT>{P.rx, P.ry, i0, H, W, P.lambda}, lds, lds);
-
-  // split step: X[k] = E[k] + exp(-2 pi i k/W) O[k], k = 0..M, Z[M] = Z[0]
-  float2* spec = P.spec;
-  for (int idx = tid; idx < (M + 1) * nrows; idx += T) {
-    int k, row;
-    if (nrows == P.rb) {
-      k = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.rb_div));
-      row = idx - k * nrows;
-    } else {
-      k = idx / nrows;
-      row = idx - k * nrows;
-    }
-    const float2 zk = buf[pad(imul(row, M) + (k == M ? 0 : k))];
-    const float2 zm = buf[pad(imul(row, M) + (k == 0 ? 0 : M - k))];
-    const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-    // o = (zk - conj(zm)) / (2i)
-    const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-    gstore(spec, 8u * (imul(k, H) + i0 + row), cadd(e, cmul(twiddle(twR, k), o)));
-  }
-}
-
-// ---------------------------------------------------------------------------
-// Pass 2 for H = 64 L (L = 8, 16): one wave per spectrum column, the column in
-// registers.  With n = l + 64 m (lane l, register m) and k = k1 + L k2:
-//   X[k1 + L k2] = sum_l W_64^(l k2) W_H^(l k1) sum_m x[l + 64 m] W_L^(m k1),
+// Wave-resident transforms of length N = 64 L (L = 8, 16): one wave holds one
+// transform, lane l the elements l + 64 m in registers m.  With k = k1 + L k2,
+//   X[k1 + L k2] = sum_l W_64^(l k2) W_N^(l k1) sum_m x[l + 64 m] W_L^(m k1),
 // so each lane takes an L-point DFT of its registers and a twiddle, and the
 // 64-point DFTs over the lanes (one per k1) run as 8 x 8 (l = l1 + 8 l2,
 // k2 = k2a + 8 k2b) through a wave-private LDS block: 8-point DFTs over l2,
-// the twiddle W_64^(l1 k2a), 8-point DFTs over l1.  The divide applies to the
-// registers that hold X[k], and the inverse retraces the same steps with
-// conjugate twiddles.  No workgroup barrier: a wave orders its own LDS
-// accesses, so a wave-scope fence between the exchanges suffices.
+// the twiddle W_64^(l1 k2a), 8-point DFTs over l1.  The inverse retraces the
+// steps with conjugate twiddles.  A wave orders its own LDS accesses, so the
+// exchanges need a wave-scope fence, not a workgroup barrier.
 // ---------------------------------------------------------------------------
-constexpr int kWaveCols = kFftThreads / 64;   // columns per workgroup
+constexpr int kWaveCols = kFftThreads / 64;   // transforms (waves) per workgroup
 
 // Slot of entry (row, col) of the 8 x 8 block k1 in a wave's LDS: a bijection
 // on the block whose rows are rotated by k1 and whose columns are XOR-ed with
@@ -509,29 +463,21 @@ struct Powers {
   }
 };
 
+// Forward transform of the wave's registers a (a[m] = x[l + 64 m]) with the
+// two-level table tw of W_N.  On return d[q][k2b] = X[k1 + L (k2a + 8 k2b)]
+// with p = l + 64 q, k1 = p / 8, k2a = p mod 8.
 template <int L>
-__device__ __forceinline__ void cols_wave_item(const FftPlane& P, int blk, float2* smem) {
-  const int H = P.H, W = P.W, M = W >> 1;
-  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int c = blk * kWaveCols + wave;
-  if (c > M) return;   // no workgroup barrier follows
-  float2* T = smem + wave * (L * 64);
-  const uint32_t base = 8u * static_cast<uint32_t>(imul(c, H));
-  const float2* tw = P.twH;   // two-level table of W_H; entries below 64 are W_H^j
-
-  float2 a[L];
-#pragma unroll
-  for (int m = 0; m < L; ++m) a[m] = gload<float2>(P.spec, base + 8u * (l + 64 * m));
+__device__ __forceinline__ void wave_fft_fwd(float2 (&a)[L], float2 (&d)[L / 8][8], float2* T, int l,
+                                             const float2* tw) {
   butterfly<L>(a, -1.0f);
   {
-    const Powers<L> pw(tw[l]);   // W_H^(l k1)
+    const Powers<L> pw(tw[l]);   // W_N^(l k1); entries below 64 of the table are W_N^j
 #pragma unroll
     for (int k1 = 1; k1 < L; ++k1) a[k1] = pw.mul(a[k1], k1);
   }
 #pragma unroll
   for (int k1 = 0; k1 < L; ++k1) T[wslot(k1, l >> 3, l & 7)] = a[k1];
   wave_lds_sync();
-
   // 8-point DFTs over l2 for each (k1, l1), then W_64^(l1 k2a)
 #pragma unroll
   for (int q = 0; q < L / 8; ++q) {
@@ -540,37 +486,36 @@ __device__ __forceinline__ void cols_wave_item(const FftPlane& P, int blk, float
 #pragma unroll
     for (int r = 0; r < 8; ++r) b[r] = T[wslot(k1, r, l1)];
     butterfly<8>(b, -1.0f);
-    const Powers<8> pv(twiddle(tw, l1 * L));   // W_64^l1 = W_H^(l1 L)
+    const Powers<8> pv(twiddle(tw, l1 * L));   // W_64^l1 = W_N^(l1 L)
 #pragma unroll
     for (int r = 1; r < 8; ++r) b[r] = pv.mul(b[r], r);
 #pragma unroll
     for (int r = 0; r < 8; ++r) T[wslot(k1, r, l1)] = b[r];
   }
   wave_lds_sync();
-
-  // 8-point DFTs over l1 for each (k1, k2a): X[k1 + L (k2a + 8 k2b)]; the
-  // Eq. (8) divide; the inverse 8-point DFTs over k2b
-  const float sxc = P.sx[c];
-  const float inv_hw = P.gain * (1.0f / (static_cast<float>(H) * static_cast<float>(W)));
+  // 8-point DFTs over l1 for each (k1, k2a)
 #pragma unroll
   for (int q = 0; q < L / 8; ++q) {
     const int p = l + 64 * q, k1 = p >> 3, k2a = p & 7;
-    float2 d[8];
 #pragma unroll
-    for (int col = 0; col < 8; ++col) d[col] = T[wslot(k1, k2a, col)];
-    butterfly<8>(d, -1.0f);
+    for (int col = 0; col < 8; ++col) d[q][col] = T[wslot(k1, k2a, col)];
+    butterfly<8>(d[q], -1.0f);
+  }
+}
+
+// Inverse (unscaled) of wave_fft_fwd: from d in its layout to a[m] = y[l + 64 m].
+// The first writes go to the slots this lane's last forward reads came from.
+template <int L>
+__device__ __forceinline__ void wave_fft_inv(float2 (&d)[L / 8][8], float2 (&a)[L], float2* T, int l,
+                                             const float2* tw) {
 #pragma unroll
-    for (int k2b = 0; k2b < 8; ++k2b) {
-      const float den = fmaf(P.lambda, sxc + P.sy[k1 + L * (k2a + 8 * k2b)], 1.0f);
-      d[k2b] = cscale(d[k2b], inv_hw * __builtin_amdgcn_rcpf(den));
-    }
-    butterfly<8>(d, 1.0f);
+  for (int q = 0; q < L / 8; ++q) {
+    const int p = l + 64 * q, k1 = p >> 3, k2a = p & 7;
+    butterfly<8>(d[q], 1.0f);
 #pragma unroll
-    for (int col = 0; col < 8; ++col) T[wslot(k1, k2a, col)] = d[col];
+    for (int col = 0; col < 8; ++col) T[wslot(k1, k2a, col)] = d[q][col];
   }
   wave_lds_sync();
-
-  // conjugate twiddles W_64^(-l1 k2a), inverse 8-point DFTs over k2a
 #pragma unroll
   for (int q = 0; q < L / 8; ++q) {
     const int p = l + 64 * q, k1 = p >> 3, l1 = p & 7;
@@ -583,7 +528,6 @@ __device__ __forceinline__ void cols_wave_item(const FftPlane& P, int blk, float
     for (int r = 0; r < 8; ++r) T[wslot(k1, r, l1)] = e[r];
   }
   wave_lds_sync();
-
 #pragma unroll
   for (int k1 = 0; k1 < L; ++k1) a[k1] = T[wslot(k1, l >> 3, l & 7)];
   {
@@ -592,6 +536,149 @@ __device__ __forceinline__ void cols_wave_item(const FftPlane& P, int blk, float
     for (int k1 = 1; k1 < L; ++k1) a[k1] = pw.mul_conj(a[k1], k1);
   }
   butterfly<L>(a, 1.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Pass 1: c = lam (D_x^T r_x + D_y^T r_y), real FFT of each row, transposed store
+// LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1), padded]
+// ---------------------------------------------------------------------------
+// Pass 1 for W/2 = 64 L: one wave per row (right-hand side, forward transform
+// in registers, split step), then the workgroup's kWaveCols rows go out
+// through LDS so each spectrum column receives kWaveCols consecutive values.
+// LDS: kWaveCols exchange blocks of W/2 values, then [W/2 + 1][kWaveCols + 1].
+template <int L, int FT>
+__device__ __forceinline__ void rows_fwd_wave_item(const FftPlane& P, int blk, float2* smem) {
+  constexpr int kS = kWaveCols + 1;   // staging row stride (one spare slot against bank conflicts)
+  const int H = P.H, W = P.W, M = W >> 1;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int i0 = blk * kWaveCols;
+  const int nrows = min(kWaveCols, H - i0);
+  const bool live = wave < nrows;
+  float2 x[L], xm = make_float2(0.0f, 0.0f);
+  if (live) {
+    float2* T = smem + wave * M;
+    const RhsSrc<FT> src{P.rx, P.ry, i0, H, W, P.lambda};
+    float2 a[L], d[L / 8][8];
+#pragma unroll
+    for (int m = 0; m < L; ++m) a[m] = src.load(wave, l + 64 * m);
+    wave_fft_fwd<L>(a, d, T, l, P.twM);
+    wave_lds_sync();
+    // Z in natural order, then X[k] = E[k] + exp(-2 pi i k / W) O[k], k = 0..M
+#pragma unroll
+    for (int q = 0; q < L / 8; ++q) {
+      const int p = l + 64 * q, k1 = p >> 3, k2a = p & 7;
+#pragma unroll
+      for (int k2b = 0; k2b < 8; ++k2b) T[k1 + L * (k2a + 8 * k2b)] = d[q][k2b];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < L; ++q) {
+      const int k = l + 64 * q;
+      const float2 zk = T[k];
+      const float2 zm = T[(M - k) & (M - 1)];
+      const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+      const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));   // (zk - conj zm) / (2i)
+      x[q] = cadd(e, cmul(twiddle(P.twW, k), o));
+    }
+    if (l == 0) {   // k = M: Z[M] = Z[0]
+      const float2 z0 = T[0];
+      const float2 e = make_float2(z0.x, 0.0f);
+      const float2 o = make_float2(z0.y, 0.0f);
+      xm = cadd(e, cmul(twiddle(P.twW, M), o));
+    }
+  }
+  __syncthreads();   // every wave is done with its block: the staging overlays them
+  float2* S = smem;
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < L; ++q) S[(l + 64 * q) * kS + wave] = x[q];
+    if (l == 0) S[M * kS + wave] = xm;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < (M + 1) * kWaveCols; idx += kFftThreads) {
+    const int k = idx / kWaveCols, w = idx - k * kWaveCols;
+    if (w < nrows) gstore(P.spec, 8u * (imul(k, H) + i0 + w), S[k * kS + w]);
+  }
+}
+
+// WAVE: planes with roww take the one-row-per-wave transform (direct launches
+// only, as for the column pass).
+template <int FT, bool WAVE>
+__device__ __forceinline__ void rows_fwd_item(const FftPlane* __restrict__ planes, int nplanes, int item,
+                                              float2* smem) {
+  constexpr int T = kFftThreads;
+  const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
+  const int blk = item - P.row_begin;
+  if (blk >= P.row_count) return;
+  if (WAVE && P.roww == 8) {
+    rows_fwd_wave_item<8, FT>(P, blk, smem);
+    return;
+  }
+  if (WAVE && P.roww == 16) {
+    rows_fwd_wave_item<16, FT>(P, blk, smem);
+    return;
+  }
+  const int H = P.H, W = P.W, M = W >> 1;
+  const int i0 = blk * P.rb;
+  const int nrows = min(P.rb, H - i0);
+  const int tid = threadIdx.x;
+  float2* twS = smem;
+  float2* twR = smem + kTwMax;
+  float2* buf = smem + 2 * kTwMax;
+  stage_twiddles<T>(twS, P.twM, P.ntwM);
+  stage_twiddles<T>(twR, P.twW, P.ntwW);
+  __syncthreads();
+  // the first stage forms the right-hand side straight from the residual fields
+  const LdsIO lds{buf, M};
+  fft_run<T, kFftLdsComplex>(*P.szM, twS, -1.0f, nrows, RhsSrc<FT>{P.rx, P.ry, i0, H, W, P.lambda}, lds, lds);
+
+  // split step: X[k] = E[k] + exp(-2 pi i k/W) O[k], k = 0..M, Z[M] = Z[0]
+  float2* spec = P.spec;
+  for (int idx = tid; idx < (M + 1) * nrows; idx += T) {
+    int k, row;
+    if (nrows == P.rb) {
+      k = static_cast<int>(fdiv(static_cast<uint32_t>(idx), P.rb_div));
+      row = idx - k * nrows;
+    } else {
+      k = idx / nrows;
+      row = idx - k * nrows;
+    }
+    const float2 zk = buf[pad(imul(row, M) + (k == M ? 0 : k))];
+    const float2 zm = buf[pad(imul(row, M) + (k == 0 ? 0 : M - k))];
+    const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    // o = (zk - conj(zm)) / (2i)
+    const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+    gstore(spec, 8u * (imul(k, H) + i0 + row), cadd(e, cmul(twiddle(twR, k), o)));
+  }
+}
+
+// Pass 2 for H = 64 L: one wave per spectrum column (forward, divide, inverse
+// in registers); a workgroup takes kWaveCols consecutive columns.
+template <int L>
+__device__ __forceinline__ void cols_wave_item(const FftPlane& P, int blk, float2* smem) {
+  const int H = P.H, W = P.W, M = W >> 1;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int c = blk * kWaveCols + wave;
+  if (c > M) return;   // no workgroup barrier follows
+  float2* T = smem + wave * (L * 64);
+  const uint32_t base = 8u * static_cast<uint32_t>(imul(c, H));
+  float2 a[L], d[L / 8][8];
+#pragma unroll
+  for (int m = 0; m < L; ++m) a[m] = gload<float2>(P.spec, base + 8u * (l + 64 * m));
+  wave_fft_fwd<L>(a, d, T, l, P.twH);
+  // the Eq. (8) divide on X[k1 + L (k2a + 8 k2b)]
+  const float sxc = P.sx[c];
+  const float inv_hw = P.gain * (1.0f / (static_cast<float>(H) * static_cast<float>(W)));
+#pragma unroll
+  for (int q = 0; q < L / 8; ++q) {
+    const int p = l + 64 * q, k1 = p >> 3, k2a = p & 7;
+#pragma unroll
+    for (int k2b = 0; k2b < 8; ++k2b) {
+      const float den = fmaf(P.lambda, sxc + P.sy[k1 + L * (k2a + 8 * k2b)], 1.0f);
+      d[q][k2b] = cscale(d[q][k2b], inv_hw * __builtin_amdgcn_rcpf(den));
+    }
+  }
+  wave_fft_inv<L>(d, a, T, l, P.twH);
 #pragma unroll
   for (int m = 0; m < L; ++m) gstore(P.spec, base + 8u * (l + 64 * m), a[m]);
 }
@@ -640,12 +727,82 @@ __device__ __forceinline__ void cols_item(const FftPlane* __restrict__ planes, i
 // last stage of the inverse transform)
 // LDS: [table of W_{W/2}: kTwMax][table of W_W: kTwMax][rows: rb x (M+1), padded]
 // ---------------------------------------------------------------------------
+// Pass 3 for W/2 = 64 L: the workgroup gathers kWaveCols rows of the half
+// spectrum through LDS, then one wave per row forms Z (the inverse split step)
+// in the forward transform's output layout, transforms back in registers and
+// writes u = f + delta.
+template <int L>
+__device__ __forceinline__ void rows_inv_wave_item(const FftPlane& P, int blk, float2* smem) {
+  constexpr int kS = kWaveCols + 1;
+  const int H = P.H, W = P.W, M = W >> 1;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int i0 = blk * kWaveCols;
+  const int nrows = min(kWaveCols, H - i0);
+  const bool live = wave < nrows;
+  float2* S = smem;
+  const int ntot = (M + 1) * kWaveCols;
+  for (int base = threadIdx.x; base < ntot; base += kFftThreads * kLoadBatch) {
+    float2 v[kLoadBatch];
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int idx = base + u * kFftThreads;
+      const int k = idx / kWaveCols, w = idx - k * kWaveCols;
+      v[u] = make_float2(0.0f, 0.0f);
+      if (idx < ntot && w < nrows) v[u] = gload<float2>(P.spec, 8u * (imul(k, H) + i0 + w));
+    }
+#pragma unroll
+    for (int u = 0; u < kLoadBatch; ++u) {
+      const int idx = base + u * kFftThreads;
+      const int k = idx / kWaveCols, w = idx - k * kWaveCols;
+      if (idx < ntot) S[k * kS + w] = v[u];
+    }
+  }
+  __syncthreads();
+  // Z[k] = (X[k] + conj X[M-k]) + i exp(2 pi i k / W) (X[k] - conj X[M-k])
+  float2 d[L / 8][8];
+  if (live) {
+#pragma unroll
+    for (int q = 0; q < L / 8; ++q) {
+      const int p = l + 64 * q, k1 = p >> 3, k2a = p & 7;
+#pragma unroll
+      for (int k2b = 0; k2b < 8; ++k2b) {
+        const int k = k1 + L * (k2a + 8 * k2b);
+        const float2 xa = S[k * kS + wave], xb = S[(M - k) * kS + wave];
+        const float2 sa = cadd(xa, cconj(xb)), da = csub(xa, cconj(xb));
+        d[q][k2b] = cadd(sa, cmul_isg(cmul(cconj(twiddle(P.twW, k)), da), 1.0f));
+      }
+    }
+  }
+  __syncthreads();   // the staging is read: the exchange blocks overlay it
+  if (live) {
+    float2* T = smem + wave * M;
+    float2 a[L];
+    wave_fft_inv<L>(d, a, T, l, P.twM);
+    const int64_t row = static_cast<int64_t>(i0 + wave) * P.pitch;
+#pragma unroll
+    for (int m = 0; m < L; ++m) {
+      const int64_t o = row + 2 * (l + 64 * m);
+      P.u[o] = P.f[o] + a[m].x;
+      P.u[o + 1] = P.f[o + 1] + a[m].y;
+    }
+  }
+}
+
+template <bool WAVE>
 __device__ __forceinline__ void rows_inv_item(const FftPlane* __restrict__ planes, int nplanes, int item,
                                               float2* smem) {
   constexpr int T = kFftThreads;
   const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
   const int blk = item - P.row_begin;
   if (blk >= P.row_count) return;
+  if (WAVE && P.roww == 8) {
+    rows_inv_wave_item<8>(P, blk, smem);
+    return;
+  }
+  if (WAVE && P.roww == 16) {
+    rows_inv_wave_item<16>(P, blk, smem);
+    return;
+  }
   const int H = P.H, W = P.W, M = W >> 1;
   const int S = M + 1;  // LDS row stride
   const int i0 = blk * P.rb;
@@ -715,7 +872,7 @@ __global__ void __launch_bounds__(kFftThreads, 4)
 fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
   extern __shared__ float2 smem[];
   if (!PERSIST) {
-    rows_fwd_item<FT>(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
+    rows_fwd_item<FT, true>(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
     return;
   }
   const int total = work->items, np = work->nplanes;
@@ -723,7 +880,7 @@ fft_rows_fwd_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader
   for (;;) {
     const int item = grab_item(work->next[0], total, true);
     if (item >= total) break;
-    rows_fwd_item<FT>(pl, np, item, smem);
+    rows_fwd_item<FT, false>(pl, np, item, smem);
     __syncthreads();
   }
 }
@@ -751,7 +908,7 @@ __global__ void __launch_bounds__(kFftThreads, 4)
 fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader* __restrict__ work) {
   extern __shared__ float2 smem[];
   if (!PERSIST) {
-    rows_inv_item(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
+    rows_inv_item<true>(planes, nplanes, xcd_remap(blockIdx.x, gridDim.x), smem);
     return;
   }
   const int total = work->items, np = work->nplanes;
@@ -759,7 +916,7 @@ fft_rows_inv_kernel(const FftPlane* __restrict__ planes, int nplanes, WorkHeader
   for (;;) {
     const int item = grab_item(work->next[2], total, true);
     if (item >= total) break;
-    rows_inv_item(pl, np, item, smem);
+    rows_inv_item<false>(pl, np, item, smem);
     __syncthreads();
   }
 }
@@ -772,6 +929,11 @@ size_t fft_rows_lds_bytes(int M, int rb) { return (2 * kTwMax + padded(rb * (M +
 size_t fft_cols_lds_bytes(int H, int cb) { return (kTwMax + padded(cb * H)) * sizeof(float2); }
 int fft_cols_wave_per_block() { return kWaveCols; }
 size_t fft_cols_wave_lds_bytes(int L) { return static_cast<size_t>(kWaveCols) * L * 64 * sizeof(float2); }
+size_t fft_rows_wave_lds_bytes(int L) {
+  const size_t exchange = static_cast<size_t>(kWaveCols) * L * 64;
+  const size_t staging = static_cast<size_t>(L * 64 + 1) * (kWaveCols + 1);
+  return (exchange > staging ? exchange : staging) * sizeof(float2);
+}
 
 hipError_t fft_init_kernels() {
   const int kMax = 128 * 1024;  // largest need is about 73 KiB; static LDS comes on top

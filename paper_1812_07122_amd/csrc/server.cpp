@@ -119,7 +119,7 @@ struct Group {
   int items = 0, items2 = 0;    // work items (fft: rows, cols)
   size_t lds_rows = 0, lds_cols = 0;
   int64_t max_pix = 0;
-  bool wave_cols = false;       // fft: a plane's column pass holds one column per wave
+  bool wave_cols = false;       // fft: a plane's passes hold one column or row per wave
 };
 
 struct Step {
@@ -249,7 +249,7 @@ static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
         fp.col_begin = fft.items2;
         fft.items += fp.row_count;
         fft.items2 += fp.col_count;
-        fft.wave_cols = fft.wave_cols || fp.colw != 0;
+        fft.wave_cols = fft.wave_cols || fp.colw != 0 || fp.roww != 0;
         push_desc(fft, fp);
       }
       fft.lds_rows = std::max(fft.lds_rows, jb->plan->lds_rows);
@@ -398,8 +398,8 @@ hipError_t blfls_server_s::launch_step(Step& st, int slot) {
   size_t used = tables_base + st.jobs.size() * sizeof(RequestTables);
   std::vector<Group> groups = build_groups(st.jobs);
   bool direct = static_cast<int>(groups.size()) > kMaxGroups;
-  // per-request filters launch directly, and so do column passes that hold one
-  // column per wave (the captured persistent column kernel has no such path)
+  // per-request filters launch directly, and so do Fourier passes that hold one
+  // column or row per wave (the captured persistent kernels have no such path)
   for (const Group& g : groups) direct = direct || g.kind == 4 || g.wave_cols;
   if (direct) {
     stats_direct_steps++;

@@ -1,11 +1,13 @@
-"""GPU parity of the column pass for H = 512 and 1024, where one wave holds one
-spectrum column in registers (the Eq. (8) divide between a forward and an
-inverse transform over H, as a four-step 64 x L transform), against the FP64
-oracle through the C ABI.
+"""GPU parity of the Fourier passes that hold one transform per wave in
+registers (a four-step 64 x L transform): the column pass for H = 512 and 1024
+(forward transform, Eq. (8) divide, inverse), and the row passes for W = 1024
+and 2048 (right-hand side, real forward transform with its split step and the
+transposed store; gather, inverse split step, inverse transform, u = f + delta),
+against the FP64 oracle through the C ABI.
 
-Widths cover one workgroup of eight columns with idle waves (W/2 + 1 below 8),
-several workgroups with a ragged last one, one and three channels, the 16-bit
-field storages, the detail gain folded into the divide, rolling iterations, and
+Shapes cover one workgroup of eight columns or rows with idle waves, several
+workgroups with a ragged last one, one and three channels, the 16-bit field
+storages, the detail gain folded into the divide, rolling iterations, and
 requests served in a mix, whose results must equal the synchronous ones bitwise.
 """
 import time
@@ -45,6 +47,10 @@ def _run(f64, **kw):
     (512, 6, 1),      # 4 columns: one workgroup, half its waves idle
     (1024, 2, 1),     # 2 columns (k = 0 and the Nyquist column)
     (512, 50, 3),     # W/2 = 25: the row passes take radix 5
+    (45, 1024, 1),    # rows: W/2 = 512, six workgroups of eight rows, the last with five
+    (6, 2048, 3),     # rows: W/2 = 1024, one workgroup with two idle waves, three planes
+    (512, 1024, 1),   # rows and columns both one transform per wave
+    (100, 2048, 1),
 ])
 def test_wave_columns_match_oracle(H, W, C):
     f = voronoi_rgb(H, W, 40 + W)[:C] if C > 1 else voronoi_image(H, W, 40 + W)
@@ -57,10 +63,11 @@ def test_wave_columns_match_oracle(H, W, C):
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
 def test_wave_columns_mixed_fields(precision):
-    f = voronoi_image(1024, 40, 41)
-    u, fin = _run(f, lam=50.0, sigma_s=2.0, sigma_r=0.05, precision=precision)
-    ref = oracle.smooth(fin, 50.0, 2.0, 0.05)
-    assert float(np.max(np.abs(u - ref))) <= TOL_MIXED
+    for H, W in ((1024, 40), (24, 1024)):
+        f = voronoi_image(H, W, 41)
+        u, fin = _run(f, lam=50.0, sigma_s=2.0, sigma_r=0.05, precision=precision)
+        ref = oracle.smooth(fin, 50.0, 2.0, 0.05)
+        assert float(np.max(np.abs(u - ref))) <= TOL_MIXED, (H, W)
 
 
 def test_wave_columns_detail_gain_and_iterations():
@@ -76,7 +83,7 @@ def test_wave_columns_detail_gain_and_iterations():
 
 def test_wave_columns_served_equal_alone():
     b = blfls()
-    shapes = [(512, 64, 1), (1024, 32, 3), (96, 80, 1), (512, 6, 3), (1024, 96, 1)]
+    shapes = [(512, 64, 1), (1024, 32, 3), (96, 80, 1), (512, 6, 3), (45, 1024, 1), (20, 2048, 3), (1024, 96, 1)]
     reqs = []
     for k, (H, W, C) in enumerate(shapes * 2):
         f = np.stack([voronoi_image(H, W, 800 + 10 * k + c) for c in range(C)])
