@@ -557,10 +557,24 @@ __device__ __forceinline__ void rows_fwd_wave_item(const FftPlane& P, int blk, f
   float2 x[L], xm = make_float2(0.0f, 0.0f);
   if (live) {
     float2* T = smem + wave * M;
-    const RhsSrc<FT> src{P.rx, P.ry, i0, H, W, P.lambda};
+    // c(i, j) = lam ((r_x(i, j-1) - r_x(i, j)) + (r_y(i-1, j) - r_y(i, j))) for the
+    // pair j = 2n, 2n + 1, n = l + 64 m: r_x(i, 2n - 1) is the odd value of the lane
+    // to the left (of lane 63 one register back for lane 0; column W - 1 at n = 0)
+    const int i = i0 + wave;
+    const uint32_t ri = imul(i, W), rp = imul(i == 0 ? H - 1 : i - 1, W);
     float2 a[L], d[L / 8][8];
+    float carry = load_one<FT>(P.rx, ri + W - 1);
 #pragma unroll
-    for (int m = 0; m < L; ++m) a[m] = src.load(wave, l + 64 * m);
+    for (int m = 0; m < L; ++m) {
+      const uint32_t j0 = 2u * (l + 64 * m);
+      const float2 x = load_pair<FT>(P.rx, ri + j0);
+      const float2 y = load_pair<FT>(P.ry, ri + j0);
+      const float2 yp = load_pair<FT>(P.ry, rp + j0);
+      const float left = __shfl_up(x.y, 1);
+      const float xm = l == 0 ? carry : left;
+      carry = __shfl(x.y, 63);
+      a[m] = make_float2(P.lambda * ((xm - x.x) + (yp.x - y.x)), P.lambda * ((x.x - x.y) + (yp.y - y.y)));
+    }
     wave_fft_fwd<L>(a, d, T, l, P.twM);
     wave_lds_sync();
     // Z in natural order, then X[k] = E[k] + exp(-2 pi i k / W) O[k], k = 0..M
