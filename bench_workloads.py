@@ -580,11 +580,13 @@ def run_serve(args, torch, blfls, state):
                                   "(WxH), lambda~U[5,100], sigma_s in {2,4,8}, sigma_r~U[0.03,0.2], Poisson arrivals "
                                   "at 0.7 x saturation", "requests": n},
            "saturation": {"req_per_s": round(r_sat, 2), "MPix/s": round(mpix / t_sat, 2),
-                          "steps": sat_stats["steps"], "p50_ms": round(sat_stats["latency_p50_ms"], 3),
+                          "steps": sat_stats["steps"], "graph_steps": sat_stats["graph_steps"],
+                          "direct_steps": sat_stats["direct_steps"], "p50_ms": round(sat_stats["latency_p50_ms"], 3),
                           "p99_ms": round(sat_stats["latency_p99_ms"], 3)},
            "open_loop": {"req_per_s_offered": round(rate, 2), "p50_ms": round(st["latency_p50_ms"], 3),
                          "p99_ms": round(st["latency_p99_ms"], 3), "max_ms": round(st["latency_max_ms"], 3),
-                         "steps": st["steps"], "mean_batch": round(n / max(st["steps"], 1), 2),
+                         "steps": st["steps"], "graph_steps": st["graph_steps"], "direct_steps": st["direct_steps"],
+                         "mean_batch": round(n / max(st["steps"], 1), 2),
                          "arena_peak_GB": round(st["arena_peak"] / 1e9, 3)},
            "sequential_sync_MPix/s": round(mpix / t_seq, 2),
            "alone_vs_mix_bitwise_mismatches": mismatches}
@@ -634,7 +636,7 @@ def run_joint(args, torch, blfls, state):
            "config": {"workload": f"joint: {n} pairs 2048x2048x1, target = guide + N(0,0.05^2), lambda=30, "
                                   "sigma_s=4 (r=12), sigma_r=0.08, FP16 field storage, served", "pairs": n},
            "served": {"p50_ms": round(st["latency_p50_ms"], 3), "p99_ms": round(st["latency_p99_ms"], 3),
-                      "steps": st["steps"]},
+                      "steps": st["steps"], "graph_steps": st["graph_steps"], "direct_steps": st["direct_steps"]},
            "sequential_sync_MPix/s": round(mpix / t_seq, 2),
            "alone_vs_mix_bitwise_mismatches": mism}
     ref, t = _collect(state)

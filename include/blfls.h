@@ -238,6 +238,9 @@ typedef struct {
   double latency_p50_ms;        /* submit -> DONE, host steady clock, over all completed requests */
   double latency_p99_ms;
   double latency_max_ms;
+  uint64_t graph_steps;         /* steps replayed from a captured graph of persistent launches */
+  uint64_t direct_steps;        /* steps launched kernel by kernel (per-request filters, Fourier
+                                   passes holding one transform per wave, or too many groups) */
 } blfls_stats;
 
 /* Create a server that runs requests on `stream` (void* hipStream_t).  `arena`

@@ -79,6 +79,8 @@ class Stats(ctypes.Structure):
         ("latency_p50_ms", ctypes.c_double),
         ("latency_p99_ms", ctypes.c_double),
         ("latency_max_ms", ctypes.c_double),
+        ("graph_steps", ctypes.c_uint64),
+        ("direct_steps", ctypes.c_uint64),
     ]
 
 

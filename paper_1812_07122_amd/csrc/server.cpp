@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -171,7 +172,8 @@ struct blfls_server_s {
   size_t kFftLdsMax = 0;
   hipStream_t capture_stream = nullptr;
   std::map<std::pair<std::vector<int>, int>, hipGraphExec_t> graphs;
-  uint64_t stats_graph_steps = 0, stats_direct_steps = 0;
+  // written by the scheduler thread outside the lock, read by blfls_server_stats
+  std::atomic<uint64_t> stats_graph_steps{0}, stats_direct_steps{0};
 
   void run();
   void retire(Step& st);
@@ -663,6 +665,8 @@ blfls_status blfls_server_stats(blfls_server_t s, blfls_stats* out) {
     out->latency_p99_ms = pct(0.99);
     out->latency_max_ms = lat.back();
   }
+  out->graph_steps = s->stats_graph_steps.load(std::memory_order_relaxed);
+  out->direct_steps = s->stats_direct_steps.load(std::memory_order_relaxed);
   return BLFLS_OK;
 }
 

@@ -100,6 +100,9 @@ def test_wave_columns_served_equal_alone():
             time.sleep(0.001)
         assert state == b.DONE and status == 0
     server.stream.synchronize()
+    st = server.stats()
+    # steps holding a plane whose Fourier passes keep one transform per wave launch directly
+    assert st["direct_steps"] >= 1 and st["graph_steps"] + st["direct_steps"] == st["steps"]
     server.close()
     for (f, prm), (_, u) in zip(reqs, pending):
         alone = b.smooth(_gpu(f), **prm)

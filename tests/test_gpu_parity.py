@@ -348,6 +348,8 @@ def test_server_results_equal_alone():
     server.stream.synchronize()
     stats = server.stats()
     assert stats["completed"] == len(reqs) and stats["failed"] == 0
+    # BLF-LS steps of these sizes replay captured graphs of persistent launches
+    assert stats["graph_steps"] >= 1 and stats["graph_steps"] + stats["direct_steps"] == stats["steps"]
     server.close()
     for (f, guide, prm), u in zip(reqs, outs):
         g = None if guide is None else _to_gpu(guide)
