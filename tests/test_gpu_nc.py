@@ -49,8 +49,10 @@ def _psnr(a, b):
 
 @pytest.mark.parametrize("H,W,ss,sr,lam", [
     (256, 256, 4.0, 0.05, 20.0),
-    (96, 100, 2.0, 0.1, 50.0),      # ragged segments and tiles
-    (72, 90, 8.0, 0.02, 20.0),      # boxes much wider than a tile's halo of 64
+    (96, 100, 2.0, 0.1, 50.0),      # ragged tiles
+    (40, 300, 3.0, 0.05, 20.0),     # two 256-pixel row segments (the second of 44), ten 32-column tiles
+    (36, 540, 2.0, 0.08, 30.0),     # three row segments; two 32-row tiles, the second of 4 rows
+    (72, 90, 8.0, 0.02, 20.0),      # first box radius 12.1: halos of 12 rows around 32-row tiles
     (8, 12, 3.0, 0.05, 10.0),       # image smaller than one segment and one tile
     (2, 4, 1.0, 0.1, 5.0),
     (160, 30, 1.5, 0.08, 100.0),
