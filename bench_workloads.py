@@ -297,7 +297,7 @@ def run_grid(args, torch, blfls, state):
                                   "(cells of 8 pixels by one range cell) against the exact windowed filter (r=24)",
                       "H": H, "W": W, "C": C},
            "filters": res}
-    ops = grid_ops(H, W, C, max(1, int(math.floor(GRID_CONFIG["sigma_s"] + 0.5))))
+    ops = grid_ops(H, W, C, max(1, int(math.floor(GRID_CONFIG["sigma_s"] + 0.5))), grid_z_slots(state["f"], GRID_CONFIG["sigma_r"]))
     gfrac = ops / (res["grid"]["filter_ms"] * 1e-3) / 1e12
     out["roofline"] = {"kernel": "grid_filter_kernel", "bound": "alu", "achieved": round(gfrac, 3),
                        "peak": VALU_PEAK_T, "unit": "T lane-ops/s", "frac": round(gfrac / VALU_PEAK_T, 4),
@@ -315,17 +315,30 @@ def run_grid(args, torch, blfls, state):
 VALU_PEAK_T = 78.6432
 
 
-def grid_ops(H, W, C, s, zbins=36):
-    """VALU lane-operations of the bilateral-grid kernel by a count of its code, per launch
-    (both fields of every channel).  Per workgroup (8 x 8 output cells of one field): the
-    splat of the 14 x 14 reachable cells' s x s pixels (two gradients, the bin, two LDS
-    read-add-writes: about 25 ops each), the blur (3 axes x 196 lines of the range axis x
-    2 grids x 5 taps over zbins bins), and the slice of the 64 s^2 output pixels (two
-    gradients, the cell coordinates, 8 cells x 2 grids trilinear, the division: about 60
-    ops each)."""
-    tiles = (((W - 1 + s // 2) // s + 1 + 7) // 8) * (((H - 1 + s // 2) // s + 1 + 7) // 8)
-    per_wg = 196 * s * s * 25 + 3 * 196 * zbins * 2 * 5 + 64 * s * s * 60
-    return 2 * C * tiles * per_wg
+def grid_ops(H, W, C, s, zslots):
+    """Algorithmic VALU lane-operations of the bilateral-grid filter, per launch (both
+    fields of every channel), each pixel and grid cell counted once: the splat of every
+    pixel (two gradients, the bin, two read-add-writes: about 25 ops), the blur (3 axes x
+    2 grids x 5 taps over the zslots range slots of every cell of the (W/s + 1) x (H/s + 1)
+    grid), and the slice of every pixel (two gradients, the cell coordinates, 8 cells x 2
+    grids trilinear, the division: about 60 ops).  The kernel's own halo work (each
+    workgroup rebuilds the cells within 3 of its tile) is not counted."""
+    cells = ((W - 1 + s // 2) // s + 1) * ((H - 1 + s // 2) // s + 1)
+    per_field = H * W * 25 + cells * zslots * 2 * 5 * 3 + H * W * 60
+    return int(2 * C * per_field)
+
+
+def grid_z_slots(f, sigma_r, normalize=False):
+    """Mean range slots per cell the grid blurs over the gradient fields of image f
+    [C][H][W]: round(span / sigma_r) + 1 bins (round(1 / sigma_r) + 1 when the range
+    axis is normalised), at most 32, plus two empty bins at each end."""
+    slots = []
+    for ch in np.asarray(f, dtype=np.float64):
+        for ax in (1, 0):
+            q = np.roll(ch, -1, axis=ax) - ch
+            span = 1.0 if normalize else float(q.max() - q.min())
+            slots.append(min(32, int(math.floor(span / sigma_r + 0.5)) + 1) + 4)
+    return float(np.mean(slots))
 
 
 def nc_bytes(H, W, C, field_bytes, rounds):

@@ -161,7 +161,7 @@ struct AmfGeom {
 };
 
 // One channel plane for the bilateral-grid approximation of Eq. (1): both
-// gradient fields of one channel, tiles of 8 x 8 grid cells per field.
+// gradient fields of one channel, tiles of 10 x 10 grid cells per field.
 constexpr int kGridZMax = 32;           // range bins at most
 constexpr int kGridMaxCell = 32;        // spatial cell size at most (pixels)
 struct GridPlane {
@@ -174,7 +174,7 @@ struct GridPlane {
   const float* minmax;   // range-source gradient extrema partials (always)
   int H, W;
   int s;                 // spatial cell size in pixels
-  int tiles_x;           // tiles across W (8 cells each)
+  int tiles_x;           // tiles across W (10 cells each)
   int tile_begin;        // first tile index of this plane in the launch
   int tile_count;        // tiles per field
   float inv_r;           // 1 / sigma_r rounded to FP32 (0: range term off)

@@ -54,7 +54,9 @@ hipError_t launch_nc_pass(const NcPlane* planes, int nplanes, int items, int pas
 int grid_cell_size(float sigma_s);
 int grid_tiles_x(int W, int s);
 int grid_tiles_y(int H, int s);
-hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int field_type, hipStream_t s);
+int grid_z_stride(const GridPlane& host_plane);
+hipError_t grid_init_kernels();
+hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int zs, int field_type, hipStream_t s);
 
 // Adaptive-manifold filter: manifold slots of a tree of the given height,
 // column-scan segments of an image of H rows, the kernels' LDS limits, and

@@ -8,10 +8,11 @@
 // own (x / s, y / s, range position) by trilinear interpolation.  The image is
 // periodic like the exact filter's window.
 //
-// No global grid is stored: a workgroup owns 8 x 8 output cells of one field
-// and builds, in LDS, the 14 x 14 cells (+-3) that can reach them through the
-// blur and the interpolation, with the whole range axis (at most 32 bins plus
-// 2 empty bins of padding at each end):
+// No global grid is stored: a workgroup owns 10 x 10 output cells of one field
+// and builds, in LDS, the 16 x 16 cells (+-3) that can reach them through the
+// blur and the interpolation, with the range axis (the bins the plane can use,
+// at most 32, plus 2 empty bins of padding at each end; dynamic LDS sized to
+// them, so narrow range axes leave room for more workgroups per CU):
 //   * splat: thread c owns local cell c and adds its s x s pixels (wrapped into
 //     the image) to its own bins, so no atomics are needed and the sums are
 //     deterministic;
@@ -20,7 +21,7 @@
 //   * slice: each output pixel interpolates num and den from the 8 cells
 //     around it, and the residual g - p is written in the field type.
 // The range bin floor((q - qmin) inv + 1/2) is an integer decision: it is
-// computed in FP32 one rounding per operation, as the checker computes it.
+// computed in FP32 one rounding per operation, as the oracle computes it.
 // qmin and the span come from the gradient-extrema partials of the range
 // source.
 #include "blfls_field.h"
@@ -34,17 +35,20 @@ namespace blfls {
 
 namespace {
 
-constexpr int kTileCells = 8;                   // output cells per tile side
+constexpr int kTileCells = 10;                  // output cells per tile side
 constexpr int kLocal = kTileCells + 6;          // local grid cells per side (+-3)
-constexpr int kCells = kLocal * kLocal;         // 196
+constexpr int kCells = kLocal * kLocal;         // 256: one splatting thread per cell
 constexpr int kZPad = 2;
-constexpr int kZS = kGridZMax + 2 * kZPad + 1;  // 37: odd stride per cell (LDS banks)
 constexpr int kGridThreads = 256;
+static_assert(kCells <= kGridThreads, "one thread per local cell");
 
 __device__ __forceinline__ int wrapi(int v, int n) {
   const int m = v % n;
   return m < 0 ? m + n : m;
 }
+
+// i wrapped into [0, n) for any i (the cheap test first: only tiles at the border wrap).
+__device__ __forceinline__ int wrapc(int v, int n) { return v >= 0 && v < n ? v : wrapi(v, n); }
 
 // Circular forward difference of image x along the field's axis at (i, j).
 __device__ __forceinline__ float grad_px(const float* __restrict__ x, int64_t pitch, int H, int W, int i, int j,
@@ -85,11 +89,14 @@ __device__ __forceinline__ void blur_line(float* base, int stride, int n, const 
 
 }  // namespace
 
-// One workgroup: (plane, field, tile of 8 x 8 output cells).
+// One workgroup: (plane, field, tile of kTileCells x kTileCells output cells).  The two
+// local grids (sums of values and of counts) take kCells x zs floats each of dynamic
+// LDS; zs, odd for the LDS banks, covers every range bin the launch's planes can use.
 __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPlane* __restrict__ planes,
-                                                                   int nplanes, int field_type) {
-  __shared__ float snum[kCells * kZS];
-  __shared__ float sden[kCells * kZS];
+                                                                   int nplanes, int field_type, int zs) {
+  extern __shared__ float grids[];
+  float* const snum = grids;
+  float* const sden = grids + kCells * zs;
   __shared__ float taps[2][5];
   const int item = blockIdx.x;
   const GridPlane& P = planes[find_grid_plane(planes, nplanes, item)];
@@ -113,7 +120,8 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
     inv = __fmul_rn(inv, inv_span);
   }
   if (__fmul_rn(span, inv) > static_cast<float>(kGridZMax - 1)) inv = __fdiv_rn(static_cast<float>(kGridZMax - 1), span);
-  const int nz = static_cast<int>(floorf(__fadd_rn(__fmul_rn(span, inv), 0.5f))) + 1;
+  // (the host's stride bound makes the min a no-op; it keeps every access in the grids)
+  const int nz = min(static_cast<int>(floorf(__fadd_rn(__fmul_rn(span, inv), 0.5f))) + 1, zs - 2 * kZPad);
   const int zt = nz + 2 * kZPad;
   if (tid < 5) {
     const float k = static_cast<float>(tid - 2);
@@ -121,7 +129,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
     taps[0][tid] = expf(-(k * k) / (2.0f * P.sig_xy * P.sig_xy));
     taps[1][tid] = sz > 0.0f ? expf(-(k * k) / (2.0f * sz * sz)) : (tid == 2 ? 1.0f : 0.0f);
   }
-  for (int i = tid; i < kCells * kZS; i += kGridThreads) {
+  for (int i = tid; i < kCells * zs; i += kGridThreads) {
     snum[i] = 0.0f;
     sden[i] = 0.0f;
   }
@@ -137,14 +145,22 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
     const int cy = tid / kLocal, cx = tid - (tid / kLocal) * kLocal;
     const int py0 = (Y0 - 3 + cy) * s - half;
     const int px0 = (X0 - 3 + cx) * s - half;
-    float* cn = snum + tid * kZS + kZPad;
-    float* cd = sden + tid * kZS + kZPad;
+    float* cn = snum + tid * zs + kZPad;
+    float* cd = sden + tid * zs + kZPad;
     for (int a = 0; a < s; ++a) {
-      const int i = wrapi(py0 + a, H);
+      // the forward difference reads (i, j) and its neighbour: row i1 at column j for
+      // the y field, row i at column j + 1 (wrapped) for the x field
+      const int i = wrapc(py0 + a, H);
+      const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
+      const float* __restrict__ f0 = f + static_cast<int64_t>(i) * P.pitch;
+      const float* __restrict__ f1 = f + static_cast<int64_t>(i1) * P.pitch;
+      const float* __restrict__ g0 = g + static_cast<int64_t>(i) * gp;
+      const float* __restrict__ g1 = g + static_cast<int64_t>(i1) * gp;
       for (int b = 0; b < s; ++b) {
-        const int j = wrapi(px0 + b, W);
-        const float pv = grad_px(f, P.pitch, H, W, i, j, field);
-        const float qv = grad_px(g, gp, H, W, i, j, field);
+        const int j = wrapc(px0 + b, W);
+        const int j1 = field ? j : (j + 1 == W ? 0 : j + 1);
+        const float pv = f1[j1] - f0[j];
+        const float qv = g1[j1] - g0[j];
         const float t = __fmul_rn(__fsub_rn(qv, qmin), inv);
         const int z = static_cast<int>(floorf(__fadd_rn(t, 0.5f)));
         cn[z] += pv;
@@ -156,24 +172,24 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
 
   // blur along the range axis (per cell), then x, then y (per grid line)
   if (tid < kCells) {
-    blur_line<kGridZMax + 2 * kZPad>(snum + tid * kZS, 1, zt, taps[1]);
-    blur_line<kGridZMax + 2 * kZPad>(sden + tid * kZS, 1, zt, taps[1]);
+    blur_line<kGridZMax + 2 * kZPad>(snum + tid * zs, 1, zt, taps[1]);
+    blur_line<kGridZMax + 2 * kZPad>(sden + tid * zs, 1, zt, taps[1]);
   }
   __syncthreads();
   for (int l = tid; l < kLocal * zt; l += kGridThreads) {   // line (cy, z) along x
     const int cy = l / zt, z = l - (l / zt) * zt;
-    blur_line<kLocal>(snum + cy * kLocal * kZS + z, kZS, kLocal, taps[0]);
-    blur_line<kLocal>(sden + cy * kLocal * kZS + z, kZS, kLocal, taps[0]);
+    blur_line<kLocal>(snum + cy * kLocal * zs + z, zs, kLocal, taps[0]);
+    blur_line<kLocal>(sden + cy * kLocal * zs + z, zs, kLocal, taps[0]);
   }
   __syncthreads();
   for (int l = tid; l < kLocal * zt; l += kGridThreads) {   // line (cx, z) along y
     const int cx = l / zt, z = l - (l / zt) * zt;
-    blur_line<kLocal>(snum + cx * kZS + z, kLocal * kZS, kLocal, taps[0]);
-    blur_line<kLocal>(sden + cx * kZS + z, kLocal * kZS, kLocal, taps[0]);
+    blur_line<kLocal>(snum + cx * zs + z, kLocal * zs, kLocal, taps[0]);
+    blur_line<kLocal>(sden + cx * zs + z, kLocal * zs, kLocal, taps[0]);
   }
   __syncthreads();
 
-  // slice the output pixels of the tile: pixels whose cell lies in [Y0, Y0+8) x [X0, X0+8)
+  // slice the output pixels of the tile: pixels whose cell lies in [Y0, Y0+T) x [X0, X0+T)
   const int y_lo = max(Y0 * s - half, 0), y_hi = min((Y0 + kTileCells) * s - half, H);
   const int x_lo = max(X0 * s - half, 0), x_hi = min((X0 + kTileCells) * s - half, W);
   const int tw = x_hi - x_lo, npx = (y_hi - y_lo) * max(tw, 0);
@@ -195,7 +211,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
 #pragma unroll
       for (int dx = 0; dx < 2; ++dx) {
         const float wxy = (dy ? ay : 1.0f - ay) * (dx ? ax : 1.0f - ax);
-        const int c = ((y0 + dy) * kLocal + (x0 + dx)) * kZS + z0;
+        const int c = ((y0 + dy) * kLocal + (x0 + dx)) * zs + z0;
         vn += wxy * ((1.0f - az) * snum[c] + az * snum[c + 1]);
         vd += wxy * ((1.0f - az) * sden[c] + az * sden[c + 1]);
       }
@@ -208,9 +224,34 @@ int grid_cell_size(float sigma_s) { return std::max(1, static_cast<int>(std::flo
 int grid_tiles_x(int W, int s) { return ((W - 1 + s / 2) / s + 1 + kTileCells - 1) / kTileCells; }
 int grid_tiles_y(int H, int s) { return ((H - 1 + s / 2) / s + 1 + kTileCells - 1) / kTileCells; }
 
-hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int field_type, hipStream_t s) {
+// Range slots per cell for a plane's parameters.  The kernel uses nz = round(span * inv)
+// + 1 bins plus kZPad on each side.  With normalisation inv = inv_r / span up to three
+// roundings, so nz <= round(inv_r) + 1; one bin of slack covers the roundings and the
+// cap at kGridZMax bins holds in every case.  The stride is made odd for the LDS banks.
+int grid_z_stride(const GridPlane& p) {
+  int nz = kGridZMax;
+  if (p.inv_r == 0.0f) {
+    nz = 1;
+  } else if (p.normalize) {
+    const double b = std::floor(static_cast<double>(p.inv_r) * (1.0 + 1e-5) + 0.5) + 2.0;
+    nz = static_cast<int>(std::min(b, static_cast<double>(kGridZMax)));
+  }
+  return (nz + 2 * kZPad) | 1;
+}
+
+size_t grid_lds_bytes(int zs) { return 2 * sizeof(float) * static_cast<size_t>(kCells) * zs; }
+
+hipError_t grid_init_kernels() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&grid_filter_kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(grid_lds_bytes(kGridZMax + 2 * kZPad + 1)));
+}
+
+hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int zs, int field_type, hipStream_t s) {
   if (items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(grid_filter_kernel, dim3(items), dim3(kGridThreads), 0, s, planes, nplanes, field_type);
+  if (zs < 1 + 2 * kZPad || zs > kGridZMax + 2 * kZPad + 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(grid_filter_kernel, dim3(items), dim3(kGridThreads), grid_lds_bytes(zs), s, planes, nplanes,
+                     field_type, zs);
   return hipGetLastError();
 }
 

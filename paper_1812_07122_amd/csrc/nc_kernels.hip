@@ -22,7 +22,7 @@
 //   * each output walks outward from its pixel, accumulating the increments in
 //     FP32 (one rounding per addition, no contraction) until the distance
 //     exceeds r_k, and averages the values it passed.  Window membership is an
-//     integer decision, so it is computed exactly as the checker computes it.
+//     integer decision, so it is computed exactly as the oracle computes it.
 // The first pass forms the gradient field from f; passes ping-pong between
 // two FP32 buffers per field; the last pass writes the residual
 // r = NC(p) - p in the field type, which the Fourier solve consumes as it does

@@ -342,7 +342,8 @@ hipError_t blfls_server_s::launch_other_filter(const Job& jb, const uint8_t* pla
     return hipSuccess;
   }
   if (rd.filter == BLFLS_FILTER_GRID)
-    return launch_grid(reinterpret_cast<const GridPlane*>(planes), C, 2 * C * rd.grid_first[0].tile_count, ft, stream);
+    return launch_grid(reinterpret_cast<const GridPlane*>(planes), C, 2 * C * rd.grid_first[0].tile_count,
+                       grid_z_stride(rd.grid_first[0]), ft, stream);
   AmfGeom G = rd.amf_geom;
   G.planes = reinterpret_cast<const AmfPlane*>(planes);
   return launch_amf(G, rd.amf_slots, rd.amf_height, stream);

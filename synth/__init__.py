@@ -6,7 +6,7 @@ stand in for them: piecewise-constant regions (strong edges the smoothing must
 keep), a low-amplitude periodic texture and fine noise (detail it must remove).
 
 This module draws random numbers and lays out arrays only.  It holds none of
-the method's arithmetic, so both the FP64 checker and the GPU path can take
+the method's arithmetic, so both the FP64 oracle and the GPU path can take
 their inputs from it without sharing any part of the computation.
 """
 from __future__ import annotations
