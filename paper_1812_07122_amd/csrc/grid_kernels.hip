@@ -13,13 +13,16 @@
 // blur and the interpolation, with the range axis (the bins the plane can use,
 // at most 32, plus 2 empty bins of padding at each end; dynamic LDS sized to
 // them, so narrow range axes leave room for more workgroups per CU):
-//   * splat: thread c owns local cell c and adds its s x s pixels (wrapped into
-//     the image) to its own bins, so no atomics are needed and the sums are
-//     deterministic;
+//   * splat: the threads walk the local region's pixels (wrapped into the image)
+//     a row at a time, coalesced, and add each pixel to its cell's bin with integer
+//     LDS atomics, the value in fixed point with a power-of-two scale: integer sums
+//     do not depend on the order of the adds, so they are deterministic and the
+//     result does not change between runs, graph replays or served batches;
 //   * blur: along the range axis per cell, then along x and y per grid line,
 //     each line held in registers (in place);
 //   * slice: each output pixel interpolates num and den from the 8 cells
-//     around it, and the residual g - p is written in the field type.
+//     around it, and the residual g - p is written in the field type (threads
+//     on consecutive pixels of a row, each keeping its columns).
 // The range bin floor((q - qmin) inv + 1/2) is an integer decision: it is
 // computed in FP32 one rounding per operation, as the oracle computes it.
 // qmin and the span come from the gradient-extrema partials of the range
@@ -49,14 +52,6 @@ __device__ __forceinline__ int wrapi(int v, int n) {
 
 // i wrapped into [0, n) for any i (the cheap test first: only tiles at the border wrap).
 __device__ __forceinline__ int wrapc(int v, int n) { return v >= 0 && v < n ? v : wrapi(v, n); }
-
-// Circular forward difference of image x along the field's axis at (i, j).
-__device__ __forceinline__ float grad_px(const float* __restrict__ x, int64_t pitch, int H, int W, int i, int j,
-                                         int field) {
-  const float v = x[static_cast<int64_t>(i) * pitch + j];
-  if (field == 0) return x[static_cast<int64_t>(i) * pitch + (j + 1 == W ? 0 : j + 1)] - v;
-  return x[static_cast<int64_t>(i + 1 == H ? 0 : i + 1) * pitch + j] - v;
-}
 
 __device__ __forceinline__ int find_grid_plane(const GridPlane* planes, int nplanes, int item) {
   int lo = 0, hi = nplanes - 1;
@@ -129,44 +124,90 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
     taps[0][tid] = expf(-(k * k) / (2.0f * P.sig_xy * P.sig_xy));
     taps[1][tid] = sz > 0.0f ? expf(-(k * k) / (2.0f * sz * sz)) : (tid == 2 ? 1.0f : 0.0f);
   }
-  for (int i = tid; i < kCells * zs; i += kGridThreads) {
-    snum[i] = 0.0f;
-    sden[i] = 0.0f;
-  }
-  __syncthreads();
-
   const float* __restrict__ f = P.f;
-  const float* __restrict__ g = P.g ? P.g : P.f;
-  const int64_t gp = P.g ? P.gpitch : P.pitch;
+  const bool self = P.g == nullptr;
+  const float* __restrict__ g = self ? P.f : P.g;
+  const int64_t gp = self ? P.pitch : P.gpitch;
 
-  // splat: local cell c = (cy, cx) is grid cell (Y0 - 3 + cy, X0 - 3 + cx), whose
-  // pixels (extended coordinates) start at cell * s - s/2
-  if (tid < kCells) {
-    const int cy = tid / kLocal, cx = tid - (tid / kLocal) * kLocal;
-    const int py0 = (Y0 - 3 + cy) * s - half;
-    const int px0 = (X0 - 3 + cx) * s - half;
-    float* cn = snum + tid * zs + kZPad;
-    float* cd = sden + tid * zs + kZPad;
-    for (int a = 0; a < s; ++a) {
-      // the forward difference reads (i, j) and its neighbour: row i1 at column j for
-      // the y field, row i at column j + 1 (wrapped) for the x field
-      const int i = wrapc(py0 + a, H);
-      const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
-      const float* __restrict__ f0 = f + static_cast<int64_t>(i) * P.pitch;
-      const float* __restrict__ f1 = f + static_cast<int64_t>(i1) * P.pitch;
-      const float* __restrict__ g0 = g + static_cast<int64_t>(i) * gp;
-      const float* __restrict__ g1 = g + static_cast<int64_t>(i1) * gp;
-      for (int b = 0; b < s; ++b) {
-        const int j = wrapc(px0 + b, W);
-        const int j1 = field ? j : (j + 1 == W ? 0 : j + 1);
-        const float pv = f1[j1] - f0[j];
-        const float qv = g1[j1] - g0[j];
-        const float t = __fmul_rn(__fsub_rn(qv, qmin), inv);
-        const int z = static_cast<int>(floorf(__fadd_rn(t, 0.5f)));
-        cn[z] += pv;
-        cd[z] += 1.0f;
+  // Splat, one pixel per thread and step: the local cells (cy, cx) are grid cells
+  // (Y0 - 3 + cy, X0 - 3 + cx), covering the kLocal s x kLocal s pixels (extended
+  // coordinates) from ((Y0 - 3) s - s/2, (X0 - 3) s - s/2).  Consecutive threads take
+  // consecutive pixels of a row, so the loads are coalesced, and add to their bins
+  // with integer LDS atomics: the gradient in fixed point (scale 2^e, |sum| < 2^31)
+  // and the count.  Integer sums do not depend on the order of the adds, so the
+  // grids, and the result, are deterministic.
+  const int side = kLocal * s;                       // local region side in pixels
+  const int wc = min(side, kGridThreads);            // threads across a row
+  const int rows_per_step = kGridThreads / wc;
+  const int tr = tid / wc, tc = tid - (tid / wc) * wc;
+  const bool active = tr < rows_per_step;
+  const int ybase = (Y0 - 3) * s - half, xbase = (X0 - 3) * s - half;
+  // (v * inv_s16) >> 16 == v / s for 0 <= v < 512 and s <= 32
+  const unsigned inv_s16 = (65536u + static_cast<unsigned>(s) - 1u) / static_cast<unsigned>(s);
+
+  // fixed-point exponent: 2^e max|p| s^2 < 2^30.  For a self-guided plane max|p| is
+  // the field's extremum; with a separate range source it is this tile's own maximum
+  // (a reduction in a fixed order, so still deterministic).
+  __shared__ float red[kGridThreads / 64];
+  float amax = 0.0f;
+  if (self) {
+    amax = fmaxf(fabsf(qmin), fabsf(qmax));
+  } else {
+    float m = 0.0f;
+    for (int c = tc; active && c < side; c += wc) {
+      const int j = wrapc(xbase + c, W);
+      const int j1 = field ? j : (j + 1 == W ? 0 : j + 1);
+      for (int r = tr; r < side; r += rows_per_step) {
+        const int i = wrapc(ybase + r, H);
+        const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
+        m = fmaxf(m, fabsf(f[static_cast<int64_t>(i1) * P.pitch + j1] - f[static_cast<int64_t>(i) * P.pitch + j]));
       }
     }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((tid & 63) == 0) red[tid >> 6] = m;
+  }
+  int* const ni = reinterpret_cast<int*>(snum);
+  int* const di = reinterpret_cast<int*>(sden);
+  for (int i = tid; i < kCells * zs; i += kGridThreads) {
+    ni[i] = 0;
+    di[i] = 0;
+  }
+  __syncthreads();
+  if (!self) {
+#pragma unroll
+    for (int w = 0; w < kGridThreads / 64; ++w) amax = fmaxf(amax, red[w]);
+  }
+  int ex = 0;
+  (void)frexpf(__fmul_rn(amax, static_cast<float>(s * s)), &ex);
+  const int e = amax > 0.0f && amax < INFINITY ? min(max(30 - ex, -120), 120) : 0;
+  const float scale = ldexpf(1.0f, e), unscale = ldexpf(1.0f, -e);
+
+  for (int c = tc; active && c < side; c += wc) {
+    // the forward difference reads (i, j) and its neighbour: row i1 at column j for
+    // the y field, row i at column j + 1 (wrapped) for the x field
+    const int j = wrapc(xbase + c, W);
+    const int j1 = field ? j : (j + 1 == W ? 0 : j + 1);
+    const int cx = static_cast<int>((static_cast<unsigned>(c) * inv_s16) >> 16);
+#pragma unroll 4
+    for (int r = tr; r < side; r += rows_per_step) {
+      const int i = wrapc(ybase + r, H);
+      const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
+      const float pv = f[static_cast<int64_t>(i1) * P.pitch + j1] - f[static_cast<int64_t>(i) * P.pitch + j];
+      const float qv = self ? pv : g[static_cast<int64_t>(i1) * gp + j1] - g[static_cast<int64_t>(i) * gp + j];
+      const float t = __fmul_rn(__fsub_rn(qv, qmin), inv);
+      const int z = static_cast<int>(floorf(__fadd_rn(t, 0.5f)));
+      const int cy = static_cast<int>((static_cast<unsigned>(r) * inv_s16) >> 16);
+      const int slot = (cy * kLocal + cx) * zs + kZPad + z;
+      atomicAdd(ni + slot, __float2int_rn(__fmul_rn(pv, scale)));
+      atomicAdd(di + slot, 1);
+    }
+  }
+  __syncthreads();
+  // back to FP32: one rounding of the integer, then an exact scaling by 2^-e
+  for (int i = tid; i < kCells * zs; i += kGridThreads) {
+    ni[i] = __float_as_int(__fmul_rn(static_cast<float>(ni[i]), unscale));
+    di[i] = __float_as_int(static_cast<float>(di[i]));
   }
   __syncthreads();
 
@@ -192,30 +233,41 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
   // slice the output pixels of the tile: pixels whose cell lies in [Y0, Y0+T) x [X0, X0+T)
   const int y_lo = max(Y0 * s - half, 0), y_hi = min((Y0 + kTileCells) * s - half, H);
   const int x_lo = max(X0 * s - half, 0), x_hi = min((X0 + kTileCells) * s - half, W);
-  const int tw = x_hi - x_lo, npx = (y_hi - y_lo) * max(tw, 0);
+  const int tw = x_hi - x_lo, th = y_hi - y_lo;
   const float inv_s = 1.0f / static_cast<float>(s);
   void* out = field ? P.ry : P.rx;
-  for (int e = tid; e < npx; e += kGridThreads) {
-    const int i = y_lo + e / tw, j = x_lo + (e - (e / tw) * tw);
-    const float pv = grad_px(f, P.pitch, H, W, i, j, field);
-    const float qv = grad_px(g, gp, H, W, i, j, field);
-    const float fz = __fmul_rn(__fsub_rn(qv, qmin), inv) + static_cast<float>(kZPad);
-    const float fy = static_cast<float>(i) * inv_s - static_cast<float>(Y0 - 3);
+  // consecutive threads take consecutive pixels of a row; a thread keeps its columns
+  const int swc = min(max(tw, 1), kGridThreads);
+  const int srows = kGridThreads / swc;
+  const int sr0 = tid / swc, sc0 = tid - (tid / swc) * swc;
+  for (int jj = sc0; th > 0 && sr0 < srows && jj < tw; jj += swc) {
+    const int j = x_lo + jj;
+    const int j1 = field ? j : (j + 1 == W ? 0 : j + 1);
     const float fx = static_cast<float>(j) * inv_s - static_cast<float>(X0 - 3);
-    const int z0 = min(max(static_cast<int>(floorf(fz)), 0), zt - 2);
-    const int y0 = static_cast<int>(floorf(fy)), x0 = static_cast<int>(floorf(fx));
-    const float az = fz - static_cast<float>(z0), ay = fy - static_cast<float>(y0), ax = fx - static_cast<float>(x0);
-    float vn = 0.0f, vd = 0.0f;
+    const int x0 = static_cast<int>(floorf(fx));
+    const float ax = fx - static_cast<float>(x0);
+    for (int ii = sr0; ii < th; ii += srows) {
+      const int i = y_lo + ii;
+      const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
+      const float pv = f[static_cast<int64_t>(i1) * P.pitch + j1] - f[static_cast<int64_t>(i) * P.pitch + j];
+      const float qv = self ? pv : g[static_cast<int64_t>(i1) * gp + j1] - g[static_cast<int64_t>(i) * gp + j];
+      const float fz = __fmul_rn(__fsub_rn(qv, qmin), inv) + static_cast<float>(kZPad);
+      const float fy = static_cast<float>(i) * inv_s - static_cast<float>(Y0 - 3);
+      const int z0 = min(max(static_cast<int>(floorf(fz)), 0), zt - 2);
+      const int y0 = static_cast<int>(floorf(fy));
+      const float az = fz - static_cast<float>(z0), ay = fy - static_cast<float>(y0);
+      float vn = 0.0f, vd = 0.0f;
 #pragma unroll
-    for (int dy = 0; dy < 2; ++dy)
+      for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-      for (int dx = 0; dx < 2; ++dx) {
-        const float wxy = (dy ? ay : 1.0f - ay) * (dx ? ax : 1.0f - ax);
-        const int c = ((y0 + dy) * kLocal + (x0 + dx)) * zs + z0;
-        vn += wxy * ((1.0f - az) * snum[c] + az * snum[c + 1]);
-        vd += wxy * ((1.0f - az) * sden[c] + az * sden[c + 1]);
-      }
-    store_field(out, static_cast<int64_t>(i) * W + j, vn / vd - pv, field_type);
+        for (int dx = 0; dx < 2; ++dx) {
+          const float wxy = (dy ? ay : 1.0f - ay) * (dx ? ax : 1.0f - ax);
+          const int c = ((y0 + dy) * kLocal + (x0 + dx)) * zs + z0;
+          vn += wxy * ((1.0f - az) * snum[c] + az * snum[c + 1]);
+          vd += wxy * ((1.0f - az) * sden[c] + az * sden[c + 1]);
+        }
+      store_field(out, static_cast<int64_t>(i) * W + j, vn / vd - pv, field_type);
+    }
   }
 }
 
