@@ -43,6 +43,8 @@ constexpr int kLocal = kTileCells + 6;          // local grid cells per side (+-
 constexpr int kCells = kLocal * kLocal;         // 256: one splatting thread per cell
 constexpr int kZPad = 2;
 constexpr int kGridThreads = 256;
+constexpr int kSplatBatch = 8;                  // splat rows whose loads go out together
+constexpr int kSliceBatch = 4;                  // slice rows whose loads go out together
 static_assert(kCells <= kGridThreads, "one thread per local cell");
 
 __device__ __forceinline__ int wrapi(int v, int n) {
@@ -52,6 +54,13 @@ __device__ __forceinline__ int wrapi(int v, int n) {
 
 // i wrapped into [0, n) for any i (the cheap test first: only tiles at the border wrap).
 __device__ __forceinline__ int wrapc(int v, int n) { return v >= 0 && v < n ? v : wrapi(v, n); }
+
+// A load from global memory in its own address space: a load through a generic
+// pointer is a flat access, which also counts against the LDS wait counter, so each
+// wait for it would wait for the splat's LDS atomics as well.
+__device__ __forceinline__ float ldg(const float* base, int64_t idx) {
+  return ((const __attribute__((address_space(1))) float*)base)[idx];
+}
 
 __device__ __forceinline__ int find_grid_plane(const GridPlane* planes, int nplanes, int item) {
   int lo = 0, hi = nplanes - 1;
@@ -160,7 +169,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
       for (int r = tr; r < side; r += rows_per_step) {
         const int i = wrapc(ybase + r, H);
         const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
-        m = fmaxf(m, fabsf(f[static_cast<int64_t>(i1) * P.pitch + j1] - f[static_cast<int64_t>(i) * P.pitch + j]));
+        m = fmaxf(m, fabsf(ldg(f, static_cast<int64_t>(i1) * P.pitch + j1) - ldg(f, static_cast<int64_t>(i) * P.pitch + j)));
       }
     }
 #pragma unroll
@@ -189,18 +198,40 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
     const int j = wrapc(xbase + c, W);
     const int j1 = field ? j : (j + 1 == W ? 0 : j + 1);
     const int cx = static_cast<int>((static_cast<unsigned>(c) * inv_s16) >> 16);
-#pragma unroll 4
-    for (int r = tr; r < side; r += rows_per_step) {
-      const int i = wrapc(ybase + r, H);
-      const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
-      const float pv = f[static_cast<int64_t>(i1) * P.pitch + j1] - f[static_cast<int64_t>(i) * P.pitch + j];
-      const float qv = self ? pv : g[static_cast<int64_t>(i1) * gp + j1] - g[static_cast<int64_t>(i) * gp + j];
-      const float t = __fmul_rn(__fsub_rn(qv, qmin), inv);
-      const int z = static_cast<int>(floorf(__fadd_rn(t, 0.5f)));
-      const int cy = static_cast<int>((static_cast<unsigned>(r) * inv_s16) >> 16);
-      const int slot = (cy * kLocal + cx) * zs + kZPad + z;
-      atomicAdd(ni + slot, __float2int_rn(__fmul_rn(pv, scale)));
-      atomicAdd(di + slot, 1);
+    // rows in batches of kSplatBatch: every load of the batch is issued before the
+    // first atomic, so one memory round trip covers the batch
+    for (int r0 = tr; r0 < side; r0 += kSplatBatch * rows_per_step) {
+      // raw loads first, unconditional (rows past the region reload its last row and
+      // are skipped below), so no wait falls between them
+      float a0[kSplatBatch], a1[kSplatBatch], b0[kSplatBatch], b1[kSplatBatch];
+#pragma unroll
+      for (int u = 0; u < kSplatBatch; ++u) {
+        const int r = min(r0 + u * rows_per_step, side - 1);
+        const int i = wrapc(ybase + r, H);
+        const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
+        a0[u] = ldg(f, static_cast<int64_t>(i) * P.pitch + j);
+        a1[u] = ldg(f, static_cast<int64_t>(i1) * P.pitch + j1);
+        b0[u] = 0.0f;
+        b1[u] = 0.0f;
+        if (!self) {
+          b0[u] = ldg(g, static_cast<int64_t>(i) * gp + j);
+          b1[u] = ldg(g, static_cast<int64_t>(i1) * gp + j1);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kSplatBatch; ++u) {
+        const int r = r0 + u * rows_per_step;
+        if (r < side) {
+          const float pvu = a1[u] - a0[u];
+          const float q = self ? pvu : b1[u] - b0[u];
+          const float t = __fmul_rn(__fsub_rn(q, qmin), inv);
+          const int z = static_cast<int>(floorf(__fadd_rn(t, 0.5f)));
+          const int cy = static_cast<int>((static_cast<unsigned>(r) * inv_s16) >> 16);
+          const int slot = (cy * kLocal + cx) * zs + kZPad + z;
+          atomicAdd(ni + slot, __float2int_rn(__fmul_rn(pvu, scale)));
+          atomicAdd(di + slot, 1);
+        }
+      }
     }
   }
   __syncthreads();
@@ -246,27 +277,46 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
     const float fx = static_cast<float>(j) * inv_s - static_cast<float>(X0 - 3);
     const int x0 = static_cast<int>(floorf(fx));
     const float ax = fx - static_cast<float>(x0);
-    for (int ii = sr0; ii < th; ii += srows) {
-      const int i = y_lo + ii;
-      const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
-      const float pv = f[static_cast<int64_t>(i1) * P.pitch + j1] - f[static_cast<int64_t>(i) * P.pitch + j];
-      const float qv = self ? pv : g[static_cast<int64_t>(i1) * gp + j1] - g[static_cast<int64_t>(i) * gp + j];
-      const float fz = __fmul_rn(__fsub_rn(qv, qmin), inv) + static_cast<float>(kZPad);
-      const float fy = static_cast<float>(i) * inv_s - static_cast<float>(Y0 - 3);
-      const int z0 = min(max(static_cast<int>(floorf(fz)), 0), zt - 2);
-      const int y0 = static_cast<int>(floorf(fy));
-      const float az = fz - static_cast<float>(z0), ay = fy - static_cast<float>(y0);
-      float vn = 0.0f, vd = 0.0f;
+    for (int ii0 = sr0; ii0 < th; ii0 += kSliceBatch * srows) {
+      float a0[kSliceBatch], a1[kSliceBatch], b0[kSliceBatch], b1[kSliceBatch];
 #pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          const float wxy = (dy ? ay : 1.0f - ay) * (dx ? ax : 1.0f - ax);
-          const int c = ((y0 + dy) * kLocal + (x0 + dx)) * zs + z0;
-          vn += wxy * ((1.0f - az) * snum[c] + az * snum[c + 1]);
-          vd += wxy * ((1.0f - az) * sden[c] + az * sden[c + 1]);
+      for (int u = 0; u < kSliceBatch; ++u) {   // the batch's loads first, as in the splat
+        const int i = y_lo + min(ii0 + u * srows, th - 1);
+        const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
+        a0[u] = ldg(f, static_cast<int64_t>(i) * P.pitch + j);
+        a1[u] = ldg(f, static_cast<int64_t>(i1) * P.pitch + j1);
+        b0[u] = 0.0f;
+        b1[u] = 0.0f;
+        if (!self) {
+          b0[u] = ldg(g, static_cast<int64_t>(i) * gp + j);
+          b1[u] = ldg(g, static_cast<int64_t>(i1) * gp + j1);
         }
-      store_field(out, static_cast<int64_t>(i) * W + j, vn / vd - pv, field_type);
+      }
+#pragma unroll
+      for (int u = 0; u < kSliceBatch; ++u) {
+        const int ii = ii0 + u * srows;
+        if (ii < th) {
+          const int i = y_lo + ii;
+          const float pvu = a1[u] - a0[u];
+          const float q = self ? pvu : b1[u] - b0[u];
+          const float fz = __fmul_rn(__fsub_rn(q, qmin), inv) + static_cast<float>(kZPad);
+          const float fy = static_cast<float>(i) * inv_s - static_cast<float>(Y0 - 3);
+          const int z0 = min(max(static_cast<int>(floorf(fz)), 0), zt - 2);
+          const int y0 = static_cast<int>(floorf(fy));
+          const float az = fz - static_cast<float>(z0), ay = fy - static_cast<float>(y0);
+          float vn = 0.0f, vd = 0.0f;
+#pragma unroll
+          for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+              const float wxy = (dy ? ay : 1.0f - ay) * (dx ? ax : 1.0f - ax);
+              const int c = ((y0 + dy) * kLocal + (x0 + dx)) * zs + z0;
+              vn += wxy * ((1.0f - az) * snum[c] + az * snum[c + 1]);
+              vd += wxy * ((1.0f - az) * sden[c] + az * sden[c + 1]);
+            }
+          store_field(out, static_cast<int64_t>(i) * W + j, vn / vd - pvu, field_type);
+        }
+      }
     }
   }
 }
