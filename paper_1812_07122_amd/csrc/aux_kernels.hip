@@ -33,21 +33,42 @@ hipError_t launch_desc_copy(const void* host_src, size_t bytes, void* dev_dst, h
   return hipSuccess;
 }
 
+// A load from global memory in its own address space (a flat load would also count
+// against the LDS wait counter).
+__device__ __forceinline__ float ldg_src(const float* base, int64_t idx) {
+  return ((const __attribute__((address_space(1))) float*)base)[idx];
+}
+
+constexpr int kMinmaxBatch = 4;   // columns per thread whose loads go out together
+
 // partial[b] = (min D_x, max D_x, min D_y, max D_y) over the elements of block b
 // (kMinmaxBlocks blocks per plane, rows strided over the blocks).
 __device__ __forceinline__ void minmax_item(const AuxPlane& P, int blk) {
   const int H = P.H, W = P.W;
   float lx = INFINITY, hx = -INFINITY, ly = INFINITY, hy = -INFINITY;
-  // block blk takes rows blk, blk + kMinmaxBlocks, ...; threads stride the columns
+  // block blk takes rows blk, blk + kMinmaxBlocks, ...; threads stride the columns,
+  // kMinmaxBatch at a time with every load issued before the first use.  Columns
+  // past the row are clamped to its last one: a repeated value leaves a min or max
+  // unchanged, so they need no guard.
   for (int i = blk; i < H; i += kMinmaxBlocks) {
-    const float* row = P.src + static_cast<int64_t>(i) * P.pitch;
-    const float* rown = P.src + static_cast<int64_t>(i + 1 == H ? 0 : i + 1) * P.pitch;
-    for (int j = threadIdx.x; j < W; j += 256) {
-      const float v = row[j];
-      const float gx = row[j + 1 == W ? 0 : j + 1] - v;
-      const float gy = rown[j] - v;
-      lx = fminf(lx, gx); hx = fmaxf(hx, gx);
-      ly = fminf(ly, gy); hy = fmaxf(hy, gy);
+    const int64_t o = static_cast<int64_t>(i) * P.pitch;
+    const int64_t on = static_cast<int64_t>(i + 1 == H ? 0 : i + 1) * P.pitch;
+    for (int j0 = threadIdx.x; j0 < W; j0 += 256 * kMinmaxBatch) {
+      float v[kMinmaxBatch], vr[kMinmaxBatch], vd[kMinmaxBatch];
+#pragma unroll
+      for (int u = 0; u < kMinmaxBatch; ++u) {
+        const int j = min(j0 + 256 * u, W - 1);
+        v[u] = ldg_src(P.src, o + j);
+        vr[u] = ldg_src(P.src, o + (j + 1 == W ? 0 : j + 1));
+        vd[u] = ldg_src(P.src, on + j);
+      }
+#pragma unroll
+      for (int u = 0; u < kMinmaxBatch; ++u) {
+        const float gx = vr[u] - v[u];
+        const float gy = vd[u] - v[u];
+        lx = fminf(lx, gx); hx = fmaxf(hx, gx);
+        ly = fminf(ly, gy); hy = fmaxf(hy, gy);
+      }
     }
   }
 #pragma unroll
