@@ -6,6 +6,7 @@
 //    the field's span), reduced per workgroup with wavefront shuffles;
 //  * the circular Gaussian that smooths the initial guidance of the rolling
 //    guidance extension (Section III-D), as two separable passes.
+#include "blfls_field.h"
 #include "blfls_internal.h"
 #include "blfls_launch.h"
 #include "blfls_work.h"
@@ -33,12 +34,6 @@ hipError_t launch_desc_copy(const void* host_src, size_t bytes, void* dev_dst, h
   return hipSuccess;
 }
 
-// A load from global memory in its own address space (a flat load would also count
-// against the LDS wait counter).
-__device__ __forceinline__ float ldg_src(const float* base, int64_t idx) {
-  return ((const __attribute__((address_space(1))) float*)base)[idx];
-}
-
 constexpr int kMinmaxBatch = 4;   // columns per thread whose loads go out together
 
 // partial[b] = (min D_x, max D_x, min D_y, max D_y) over the elements of block b
@@ -58,9 +53,9 @@ __device__ __forceinline__ void minmax_item(const AuxPlane& P, int blk) {
 #pragma unroll
       for (int u = 0; u < kMinmaxBatch; ++u) {
         const int j = min(j0 + 256 * u, W - 1);
-        v[u] = ldg_src(P.src, o + j);
-        vr[u] = ldg_src(P.src, o + (j + 1 == W ? 0 : j + 1));
-        vd[u] = ldg_src(P.src, on + j);
+        v[u] = load_global(P.src, o + j);
+        vr[u] = load_global(P.src, o + (j + 1 == W ? 0 : j + 1));
+        vd[u] = load_global(P.src, on + j);
       }
 #pragma unroll
       for (int u = 0; u < kMinmaxBatch; ++u) {

@@ -567,7 +567,7 @@ hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, cons
       StageTimer t(BLFLS_STAGE_BLF, s);
       const GridPlane* gp = first ? dev.grid_first : dev.grid_next;
       const GridPlane& g0 = first ? rd.grid_first[0] : rd.grid_next[0];
-      e = launch_grid(gp, C, 2 * C * g0.tile_count, grid_z_stride(g0), ft, s);
+      e = launch_grid(gp, C, 2 * C * g0.tile_count, grid_z_stride(g0), g0.g == nullptr, ft, s);
       if (e != hipSuccess) return e;
     } else if (rd.filter == BLFLS_FILTER_AMF) {
       StageTimer t(BLFLS_STAGE_BLF, s);

@@ -8,17 +8,29 @@
 
 namespace blfls {
 
+// Global memory accessed in its own address space.  An access through a generic
+// pointer is a flat access, which also counts against the LDS wait counter, so a
+// kernel that stages through LDS would wait for its LDS work at every use of a load.
+__device__ __forceinline__ float load_global(const float* base, int64_t idx) {
+  return ((const __attribute__((address_space(1))) float*)base)[idx];
+}
+
+template <typename T>
+__device__ __forceinline__ void store_global(T* base, int64_t idx, T v) {
+  ((__attribute__((address_space(1))) T*)base)[idx] = v;
+}
+
 // Store v as element idx of a packed field of type ft (FP32, BF16 or FP16,
 // rounded to nearest even).
 __device__ __forceinline__ void store_field(void* base, int64_t idx, float v, int ft) {
   if (ft == kF32) {
-    static_cast<float*>(base)[idx] = v;
+    store_global(static_cast<float*>(base), idx, v);
   } else if (ft == kBF16) {
     uint32_t b = __float_as_uint(v);
     b += 0x7FFFu + ((b >> 16) & 1u);  // round to nearest even (values are finite)
-    static_cast<uint16_t*>(base)[idx] = static_cast<uint16_t>(b >> 16);
+    store_global(static_cast<uint16_t*>(base), idx, static_cast<uint16_t>(b >> 16));
   } else {
-    static_cast<_Float16*>(base)[idx] = static_cast<_Float16>(v);  // round to nearest even
+    store_global(static_cast<_Float16*>(base), idx, static_cast<_Float16>(v));  // round to nearest even
   }
 }
 

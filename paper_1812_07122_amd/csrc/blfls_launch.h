@@ -56,7 +56,9 @@ int grid_tiles_x(int W, int s);
 int grid_tiles_y(int H, int s);
 int grid_z_stride(const GridPlane& host_plane);
 hipError_t grid_init_kernels();
-hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int zs, int field_type, hipStream_t s);
+// self: every plane's range source is its image (GridPlane::g == nullptr)
+hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int zs, bool self, int field_type,
+                       hipStream_t s);
 
 // Adaptive-manifold filter: manifold slots of a tree of the given height,
 // column-scan segments of an image of H rows, the kernels' LDS limits, and

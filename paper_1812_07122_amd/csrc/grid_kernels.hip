@@ -55,13 +55,6 @@ __device__ __forceinline__ int wrapi(int v, int n) {
 // i wrapped into [0, n) for any i (the cheap test first: only tiles at the border wrap).
 __device__ __forceinline__ int wrapc(int v, int n) { return v >= 0 && v < n ? v : wrapi(v, n); }
 
-// A load from global memory in its own address space: a load through a generic
-// pointer is a flat access, which also counts against the LDS wait counter, so each
-// wait for it would wait for the splat's LDS atomics as well.
-__device__ __forceinline__ float ldg(const float* base, int64_t idx) {
-  return ((const __attribute__((address_space(1))) float*)base)[idx];
-}
-
 __device__ __forceinline__ int find_grid_plane(const GridPlane* planes, int nplanes, int item) {
   int lo = 0, hi = nplanes - 1;
   while (lo < hi) {
@@ -96,6 +89,9 @@ __device__ __forceinline__ void blur_line(float* base, int stride, int n, const 
 // One workgroup: (plane, field, tile of kTileCells x kTileCells output cells).  The two
 // local grids (sums of values and of counts) take kCells x zs floats each of dynamic
 // LDS; zs, odd for the LDS banks, covers every range bin the launch's planes can use.
+// SELF: the range source is the image itself (every plane of the launch has g ==
+// nullptr), so the range-source loads and the tile maximum are not needed.
+template <bool SELF>
 __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPlane* __restrict__ planes,
                                                                    int nplanes, int field_type, int zs) {
   extern __shared__ float grids[];
@@ -134,9 +130,10 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
     taps[1][tid] = sz > 0.0f ? expf(-(k * k) / (2.0f * sz * sz)) : (tid == 2 ? 1.0f : 0.0f);
   }
   const float* __restrict__ f = P.f;
-  const bool self = P.g == nullptr;
-  const float* __restrict__ g = self ? P.f : P.g;
-  const int64_t gp = self ? P.pitch : P.gpitch;
+  constexpr bool self = SELF;
+  // (a plane without a range source read by the general kernel uses its image)
+  const float* __restrict__ g = self || P.g == nullptr ? P.f : P.g;
+  const int64_t gp = self || P.g == nullptr ? P.pitch : P.gpitch;
 
   // Splat, one pixel per thread and step: the local cells (cy, cx) are grid cells
   // (Y0 - 3 + cy, X0 - 3 + cx), covering the kLocal s x kLocal s pixels (extended
@@ -169,7 +166,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
       for (int r = tr; r < side; r += rows_per_step) {
         const int i = wrapc(ybase + r, H);
         const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
-        m = fmaxf(m, fabsf(ldg(f, static_cast<int64_t>(i1) * P.pitch + j1) - ldg(f, static_cast<int64_t>(i) * P.pitch + j)));
+        m = fmaxf(m, fabsf(load_global(f, static_cast<int64_t>(i1) * P.pitch + j1) - load_global(f, static_cast<int64_t>(i) * P.pitch + j)));
       }
     }
 #pragma unroll
@@ -209,13 +206,13 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
         const int r = min(r0 + u * rows_per_step, side - 1);
         const int i = wrapc(ybase + r, H);
         const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
-        a0[u] = ldg(f, static_cast<int64_t>(i) * P.pitch + j);
-        a1[u] = ldg(f, static_cast<int64_t>(i1) * P.pitch + j1);
+        a0[u] = load_global(f, static_cast<int64_t>(i) * P.pitch + j);
+        a1[u] = load_global(f, static_cast<int64_t>(i1) * P.pitch + j1);
         b0[u] = 0.0f;
         b1[u] = 0.0f;
         if (!self) {
-          b0[u] = ldg(g, static_cast<int64_t>(i) * gp + j);
-          b1[u] = ldg(g, static_cast<int64_t>(i1) * gp + j1);
+          b0[u] = load_global(g, static_cast<int64_t>(i) * gp + j);
+          b1[u] = load_global(g, static_cast<int64_t>(i1) * gp + j1);
         }
       }
 #pragma unroll
@@ -283,13 +280,13 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
       for (int u = 0; u < kSliceBatch; ++u) {   // the batch's loads first, as in the splat
         const int i = y_lo + min(ii0 + u * srows, th - 1);
         const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
-        a0[u] = ldg(f, static_cast<int64_t>(i) * P.pitch + j);
-        a1[u] = ldg(f, static_cast<int64_t>(i1) * P.pitch + j1);
+        a0[u] = load_global(f, static_cast<int64_t>(i) * P.pitch + j);
+        a1[u] = load_global(f, static_cast<int64_t>(i1) * P.pitch + j1);
         b0[u] = 0.0f;
         b1[u] = 0.0f;
         if (!self) {
-          b0[u] = ldg(g, static_cast<int64_t>(i) * gp + j);
-          b1[u] = ldg(g, static_cast<int64_t>(i1) * gp + j1);
+          b0[u] = load_global(g, static_cast<int64_t>(i) * gp + j);
+          b1[u] = load_global(g, static_cast<int64_t>(i1) * gp + j1);
         }
       }
 #pragma unroll
@@ -344,16 +341,25 @@ int grid_z_stride(const GridPlane& p) {
 size_t grid_lds_bytes(int zs) { return 2 * sizeof(float) * static_cast<size_t>(kCells) * zs; }
 
 hipError_t grid_init_kernels() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&grid_filter_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             static_cast<int>(grid_lds_bytes(kGridZMax + 2 * kZPad + 1)));
+  const int max_lds = static_cast<int>(grid_lds_bytes(kGridZMax + 2 * kZPad + 1));
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&grid_filter_kernel<true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&grid_filter_kernel<false>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, max_lds);
+  return e;
 }
 
-hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int zs, int field_type, hipStream_t s) {
+hipError_t launch_grid(const GridPlane* planes, int nplanes, int items, int zs, bool self, int field_type,
+                       hipStream_t s) {
   if (items <= 0) return hipSuccess;
   if (zs < 1 + 2 * kZPad || zs > kGridZMax + 2 * kZPad + 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(grid_filter_kernel, dim3(items), dim3(kGridThreads), grid_lds_bytes(zs), s, planes, nplanes,
-                     field_type, zs);
+  if (self)
+    hipLaunchKernelGGL(grid_filter_kernel<true>, dim3(items), dim3(kGridThreads), grid_lds_bytes(zs), s, planes,
+                       nplanes, field_type, zs);
+  else
+    hipLaunchKernelGGL(grid_filter_kernel<false>, dim3(items), dim3(kGridThreads), grid_lds_bytes(zs), s, planes,
+                       nplanes, field_type, zs);
   return hipGetLastError();
 }
 

@@ -47,9 +47,9 @@ __device__ __forceinline__ int next_wrap(int i, int n) { return i + 1 == n ? 0 :
 // Circular forward difference of image x along the field's axis at (i, j).
 __device__ __forceinline__ float grad_at(const float* __restrict__ x, int64_t pitch, int H, int W, int i, int j,
                                          int field) {
-  const float v = x[static_cast<int64_t>(i) * pitch + j];
-  if (field == 0) return x[static_cast<int64_t>(i) * pitch + next_wrap(j, W)] - v;
-  return x[static_cast<int64_t>(next_wrap(i, H)) * pitch + j] - v;
+  const float v = load_global(x, static_cast<int64_t>(i) * pitch + j);
+  if (field == 0) return load_global(x, static_cast<int64_t>(i) * pitch + next_wrap(j, W)) - v;
+  return load_global(x, static_cast<int64_t>(next_wrap(i, H)) * pitch + j) - v;
 }
 
 // Domain-transform increment between neighbouring guide values q0 -> q1,
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) nc_rows_kernel(const NcPlane* __restrict_
       vv[u] = 0.0f;
       dd[u] = 0.0f;
       if (t < kRowSeg + 2 * R && m >= 0 && m < W) {
-        vv[u] = FIRST ? grad_at(f, P.pitch, H, W, i, m, field) : in[static_cast<int64_t>(i) * W + m];
+        vv[u] = FIRST ? grad_at(f, P.pitch, H, W, i, m, field) : load_global(in, static_cast<int64_t>(i) * W + m);
         if (m >= 1)
           dd[u] = dt_increment(grad_at(g, gp, H, W, i, m, field), grad_at(g, gp, H, W, i, m - 1, field), P.a, inv,
                                scaled);
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(256) nc_rows_kernel(const NcPlane* __restrict_
       const int j = j0 + lane + 64 * q;
       if (j < W) {
         const float out = nc_window_mean(sv[wave], sd[wave], 1, lane + 64 * q + R, min(R, W - 1 - j), min(R, j), r);
-        P.buf[src ^ 1][field][static_cast<int64_t>(i) * W + j] = out;
+        store_global(P.buf[src ^ 1][field], static_cast<int64_t>(i) * W + j, out);
       }
     }
   }
@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(256) nc_cols_kernel(const NcPlane* __restrict_
         fv[u] = 0.0f;
         dv[u] = 0.0f;
         if (t < rows && m >= 0 && m < H) {
-          fv[u] = in[static_cast<int64_t>(m) * W + j];
+          fv[u] = load_global(in, static_cast<int64_t>(m) * W + j);
           if (m >= 1)
             dv[u] = dt_increment(grad_at(g, gp, H, W, m, j, field), grad_at(g, gp, H, W, m - 1, j, field), P.a, inv,
                                  scaled);
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(256) nc_cols_kernel(const NcPlane* __restrict_
         const float res = out - grad_at(P.f, P.pitch, H, W, i, j, field);
         store_field(field ? P.ry : P.rx, o, res, field_type);
       } else {
-        P.buf[src ^ 1][field][o] = out;
+        store_global(P.buf[src ^ 1][field], o, out);
       }
     }
   }

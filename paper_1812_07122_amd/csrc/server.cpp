@@ -180,7 +180,7 @@ struct blfls_server_s {
   void admit(std::vector<Job*>* admitted);
   hipError_t launch_step(Step& st, int slot);
   hipError_t launch_direct(std::vector<Group>& groups, int slot, int ft, size_t tables_used);
-  hipError_t launch_other_filter(const Job& jb, const uint8_t* planes, int ft);
+  hipError_t launch_other_filter(const Job& jb, const uint8_t* planes, bool joint, int ft);
   hipError_t build_graph(const std::vector<Group>& groups, int slot, int ft, hipGraphExec_t* out);
 };
 
@@ -222,6 +222,7 @@ static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
       if (rd.filter != BLFLS_FILTER_BLF) {
         Group g{4};
         g.job = jb;
+        g.joint = first ? rd.joint_first : true;   // the range source differs from the image
         if (rd.filter == BLFLS_FILTER_NC)
           for (const auto& d : (first ? rd.nc_first : rd.nc_next)) push_desc(g, d);
         else if (rd.filter == BLFLS_FILTER_GRID)
@@ -311,7 +312,7 @@ hipError_t blfls_server_s::launch_direct(std::vector<Group>& groups, int slot, i
       case 0: e = launch_gauss(reinterpret_cast<const AuxPlane*>(d), g.n, g.max_pix, stream); break;
       case 1: e = launch_minmax(reinterpret_cast<const AuxPlane*>(d), g.n, stream); break;
       case 2: e = launch_blf(g.R, reinterpret_cast<const BlfPlane*>(d), g.n, g.items, g.joint, ft, stream); break;
-      case 4: e = launch_other_filter(*g.job, d, ft); break;
+      case 4: e = launch_other_filter(*g.job, d, g.joint, ft); break;
       default: {
         const FftPlane* fp = reinterpret_cast<const FftPlane*>(d);
         e = launch_fft_rows_fwd(fp, g.n, g.items, g.lds_rows, ft, stream);
@@ -326,7 +327,7 @@ hipError_t blfls_server_s::launch_direct(std::vector<Group>& groups, int slot, i
 
 // One request's NC, grid or AMF stage, as blfls_smooth queues it, reading the
 // descriptors staged at `planes`.
-hipError_t blfls_server_s::launch_other_filter(const Job& jb, const uint8_t* planes, int ft) {
+hipError_t blfls_server_s::launch_other_filter(const Job& jb, const uint8_t* planes, bool joint, int ft) {
   const RequestDesc& rd = jb.rd;
   const blfls_plan_s* plan = jb.plan;
   const int C = plan->C;
@@ -343,7 +344,7 @@ hipError_t blfls_server_s::launch_other_filter(const Job& jb, const uint8_t* pla
   }
   if (rd.filter == BLFLS_FILTER_GRID)
     return launch_grid(reinterpret_cast<const GridPlane*>(planes), C, 2 * C * rd.grid_first[0].tile_count,
-                       grid_z_stride(rd.grid_first[0]), ft, stream);
+                       grid_z_stride(rd.grid_first[0]), !joint, ft, stream);
   AmfGeom G = rd.amf_geom;
   G.planes = reinterpret_cast<const AmfPlane*>(planes);
   return launch_amf(G, rd.amf_slots, rd.amf_height, stream);
