@@ -119,6 +119,62 @@ def test_grid_rgb_1024_channel_full_size_and_distance_to_exact():
     assert _psnr(u, exact) > 30.0
 
 
+@pytest.mark.parametrize("k", [1000.0, 1e-3])
+def test_grid_fixed_point_scale_follows_the_data(k):
+    """The splat sums gradients in fixed point with a power-of-two scale taken from
+    the largest gradient (the field's when self-guided, the tile's with a separate
+    range source): scaling the image, the guide and sigma_r by k scales the result by
+    k, so the oracle is matched within k times the FP32 tolerance at any magnitude."""
+    f = voronoi_image(72, 90, 97) * k
+    u, fin = _grid(f, lam=20.0, sigma_s=4.0, sigma_r=0.05 * k)
+    ref = oracle.smooth(fin, 20.0, 4.0, 0.05 * k, filter="grid")
+    err = float(np.max(np.abs(u - ref)))
+    print(f"self-guided, scale {k:g}: max-abs {err:.3e}")
+    assert err <= TOL_FP32 * k
+    t, g = joint_pair(64, 80, 7)
+    u, tin = _grid(t * k, g * k, lam=30.0, sigma_s=3.0, sigma_r=0.08 * k)
+    gin = np.asarray(g * k, np.float32).astype(np.float64)
+    ref = oracle.smooth(tin, 30.0, 3.0, 0.08 * k, guide=gin, filter="grid")
+    err = float(np.max(np.abs(u - ref)))
+    print(f"joint, scale {k:g}: max-abs {err:.3e}")
+    assert err <= TOL_FP32 * k
+
+
+def test_grid_repeats_and_graph_replays_are_bitwise_equal():
+    """The splat's integer sums do not depend on the order of its atomics, so the
+    same inputs give the same bits: repeated calls, and replays of a captured graph
+    (new inputs copied in before each) against the eager call, joint guidance."""
+    b = blfls()
+    H, W, C = 96, 128, 3
+    plan = b.Plan(H, W, C)
+    prm = dict(lam=30.0, sigma_s=4.0, sigma_r=0.05, filter="grid")
+    static_f = torch.zeros((C, H, W), device="cuda")
+    static_g = torch.zeros_like(static_f)
+    static_u = torch.zeros_like(static_f)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.smooth(static_f, guide=static_g, out=static_u, **prm)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.smooth(static_f, guide=static_g, out=static_u, **prm)
+    for k in range(3):
+        img = _gpu(voronoi_rgb(H, W, 60 + k))
+        gd = _gpu(voronoi_rgb(H, W, 70 + k))
+        static_f.copy_(img)
+        static_g.copy_(gd)
+        graph.replay()
+        torch.cuda.synchronize()
+        first = plan.smooth(img, guide=gd, **prm)
+        second = plan.smooth(img, guide=gd, **prm)
+        torch.cuda.synchronize()
+        assert torch.equal(first, second), f"repeat {k} differs"
+        assert torch.equal(static_u, first), f"replay {k} differs from eager"
+    plan.close()
+
+
 def test_grid_abi_errors():
     b = blfls()
     f = _gpu(voronoi_image(16, 16, 1))
