@@ -166,7 +166,9 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
       for (int r = tr; r < side; r += rows_per_step) {
         const int i = wrapc(ybase + r, H);
         const int i1 = field ? (i + 1 == H ? 0 : i + 1) : i;
-        m = fmaxf(m, fabsf(load_global(f, static_cast<int64_t>(i1) * P.pitch + j1) - load_global(f, static_cast<int64_t>(i) * P.pitch + j)));
+        const float pv = load_global(f, static_cast<int64_t>(i1) * P.pitch + j1) -
+                         load_global(f, static_cast<int64_t>(i) * P.pitch + j);
+        m = fmaxf(m, fabsf(pv));
       }
     }
 #pragma unroll
