@@ -33,8 +33,7 @@ Readings taken where the paper is silent (each one is listed in the design notes
     per field, literally, when ``normalize=True``;
   * NC-LS (Section III-D) replaces the BLF by the normalized-convolution filter
     of the domain transform on the same fields and guides; its borders do not
-    wrap, it runs three iterations, and its window-membership decisions are
-    taken in FP32 (see the NC section below);
+    wrap and it runs three iterations (see the NC section below);
   * AMF-LS (Section III-D) replaces it by the adaptive-manifold filter, whose
     recursive passes start at the borders (see the AMF section below);
   * iterations > 1 follow the rolling-guidance extension: iteration k filters
@@ -56,7 +55,9 @@ __all__ = [
     "dense_difference_matrices", "dense_blfls_solve",
     "gaussian_blur", "smooth", "smooth_channel",
     "nc_schedule", "nc_increments", "nc_box_pass", "nc_filter", "nc_filter_bruteforce",
-    "grid_cell", "grid_range", "grid_filter", "grid_filter_bruteforce",
+    "nc_decision_margin",
+    "GRID_PAD", "GRID_ZMAX", "grid_cell", "grid_range", "grid_bin_margin", "grid_filter",
+    "grid_filter_bruteforce",
     "AMF_MAX_HEIGHT", "AMF_TAU", "amf_tree_height", "amf_rf_line_rows", "amf_blur",
     "amf_filter", "amf_filter_dense",
     "TM_FLOOR", "tonemap",
@@ -184,9 +185,13 @@ def bilateral_filter_at(p, q, sigma_s, sigma_r, radius, rows, cols):
 # field and the guide is the field itself or the guide image's field of the
 # same axis (as for the BLF); windows stop at the image borders (the filter
 # is defined on a finite signal; only the solve is circular); three
-# iterations.  Window membership is an integer decision taken from floating
-# point, so it is computed in FP32 with the increments accumulated outward
-# from the centre pixel, as the GPU kernel does; the averages are FP64.
+# iterations.  Everything here is FP64, window membership included: the
+# transformed distance between j and m is the sum of the increments between
+# them, and m is in j's window when that sum is at most r.  Membership is a
+# discontinuous function of the guide, so ``nc_decision_margin`` reports how
+# far the closest decision lies from its threshold; a lower-precision
+# implementation reproduces these windows exactly when its own rounding of the
+# distances stays below that margin.
 
 def nc_schedule(sigma_s: float, n_iter: int = 3):
     """Box radii of the n_iter passes: sigma_k = sigma_s sqrt(3) 2^(n-k) / sqrt(4^n - 1)
@@ -200,64 +205,66 @@ def nc_schedule(sigma_s: float, n_iter: int = 3):
     return out
 
 
-def nc_increments(q: np.ndarray, a: np.float32, inv_span=None):
-    """FP32 domain-transform increments of the guide field q: dh[i, j] = 1 + a |q[i, j] - q[i, j-1]|
-    (column 0 unused) and dv[i, j] = 1 + a |q[i, j] - q[i-1, j]| (row 0 unused); with inv_span the
-    term is (a |dq|) * inv_span (normalised fields).  Products and sums are rounded to FP32 one
-    operation at a time."""
-    q32 = np.asarray(q, dtype=np.float64).astype(np.float32)
-    a = np.float32(a)
-    def inc(diff):
-        t = np.abs(diff).astype(np.float32)
-        t = (a * t).astype(np.float32)
-        if inv_span is not None:
-            t = (t * np.float32(inv_span)).astype(np.float32)
-        return (np.float32(1.0) + t).astype(np.float32)
-    dh = np.ones_like(q32)
-    dv = np.ones_like(q32)
-    dh[:, 1:] = inc(q32[:, 1:] - q32[:, :-1])
-    dv[1:, :] = inc(q32[1:, :] - q32[:-1, :])
+def nc_increments(q: np.ndarray, a: float, inv_span=None):
+    """Domain-transform increments of the guide field q: dh[i, j] = 1 + a |q[i, j] - q[i, j-1]|
+    (column 0 unused) and dv[i, j] = 1 + a |q[i, j] - q[i-1, j]| (row 0 unused); with inv_span
+    (normalised fields) the term is a |dq| inv_span."""
+    q = np.asarray(q, dtype=np.float64)
+    scale = float(a) * (1.0 if inv_span is None else float(inv_span))
+    dh = np.ones_like(q)
+    dv = np.ones_like(q)
+    dh[:, 1:] = 1.0 + scale * np.abs(q[:, 1:] - q[:, :-1])
+    dv[1:, :] = 1.0 + scale * np.abs(q[1:, :] - q[:-1, :])
     return dh, dv
+
+
+def _nc_walks(d: np.ndarray, r: float):
+    """Outward walks along the rows of d: for k = 1, 2, ... yields (k, sign, dist, live),
+    dist the sum of the increments between j and j + sign k (inf past the border) and live
+    whether every distance up to that step is within r."""
+    Hn, Wn = d.shape
+    R = int(math.floor(r)) + 1          # increments are >= 1: no window reaches past R
+    for sgn in (1, -1):
+        dist = np.zeros((Hn, Wn))
+        live = np.ones((Hn, Wn), dtype=bool)
+        for k in range(1, min(R, Wn - 1) + 1):
+            inc = np.full((Hn, Wn), np.inf)
+            if sgn > 0:
+                inc[:, :Wn - k] = d[:, k:]            # to the right: d[j+1], ..., d[j+k]
+            else:
+                inc[:, k:] = d[:, 1:Wn - k + 1]       # to the left: d[j], ..., d[j-k+1]
+            dist = dist + inc
+            live &= dist <= r
+            yield k, sgn, dist, live
 
 
 def nc_box_pass(F: np.ndarray, d: np.ndarray, r: float, axis: int) -> np.ndarray:
     """One transformed-domain box pass along `axis` (1: rows, 0: columns).  The output at j
     is the mean of F over the m on the same line with transformed distance
-    dist(j, m) <= r, dist being the FP32 sum of the increments d between j and m taken
-    outward from j; no wrap at the borders."""
+    dist(j, m) <= r, dist being the sum of the increments d between j and m; no wrap at
+    the borders."""
     F = np.asarray(F, dtype=np.float64)
     if axis == 0:
         return nc_box_pass(F.T, d.T, r, 1).T
-    r32 = np.float32(r)
-    Hn, Wn = F.shape
+    Wn = F.shape[1]
     num = F.copy()
     cnt = np.ones_like(F)
-    R = int(math.floor(float(r32))) + 1
-    # to the right: m = j + k, distance accumulates d[j+1], ..., d[j+k]
-    dist = np.zeros((Hn, Wn), dtype=np.float32)
-    live = np.ones((Hn, Wn), dtype=bool)
-    for k in range(1, min(R, Wn - 1) + 1):
-        inc = np.full((Hn, Wn), np.float32(np.inf), dtype=np.float32)
-        inc[:, :Wn - k] = d[:, k:]
-        dist = (dist + inc).astype(np.float32)
-        live &= dist <= r32
+    for k, sgn, _dist, live in _nc_walks(d, float(r)):
         vals = np.zeros_like(F)
-        vals[:, :Wn - k] = F[:, k:]
-        num += np.where(live, vals, 0.0)
-        cnt += live
-    # to the left: m = j - k, distance accumulates d[j], d[j-1], ..., d[j-k+1]
-    dist = np.zeros((Hn, Wn), dtype=np.float32)
-    live = np.ones((Hn, Wn), dtype=bool)
-    for k in range(1, min(R, Wn - 1) + 1):
-        inc = np.full((Hn, Wn), np.float32(np.inf), dtype=np.float32)
-        inc[:, k:] = d[:, 1:Wn - k + 1]
-        dist = (dist + inc).astype(np.float32)
-        live &= dist <= r32
-        vals = np.zeros_like(F)
-        vals[:, k:] = F[:, :Wn - k]
+        if sgn > 0:
+            vals[:, :Wn - k] = F[:, k:]
+        else:
+            vals[:, k:] = F[:, :Wn - k]
         num += np.where(live, vals, 0.0)
         cnt += live
     return num / cnt
+
+
+def _nc_params(sigma_s, sigma_r):
+    # the sigmas arrive as the library's FP32 parameters; a and the radii follow in FP64
+    s = float(np.float32(sigma_s))
+    a = 0.0 if math.isinf(sigma_r) else s / float(np.float32(sigma_r))
+    return s, a
 
 
 def nc_filter(p: np.ndarray, q, sigma_s: float, sigma_r: float, n_iter: int = 3, inv_span=None) -> np.ndarray:
@@ -267,47 +274,65 @@ def nc_filter(p: np.ndarray, q, sigma_s: float, sigma_r: float, n_iter: int = 3,
     switches the range term off (increments 1: plain iterated box filters)."""
     p = np.asarray(p, dtype=np.float64)
     qq = p if q is None else np.asarray(q, dtype=np.float64)
-    # the sigmas arrive as FP32 (the library's parameters); a and the radii are
-    # formed from them in FP64 and rounded once to FP32
-    s32 = float(np.float32(sigma_s))
-    a = np.float32(0.0) if math.isinf(sigma_r) else np.float32(s32 / float(np.float32(sigma_r)))
+    s, a = _nc_params(sigma_s, sigma_r)
     dh, dv = nc_increments(qq, a, inv_span)
     F = p
-    for r in nc_schedule(s32, n_iter):
+    for r in nc_schedule(s, n_iter):
         F = nc_box_pass(F, dh, r, 1)
         F = nc_box_pass(F, dv, r, 0)
     return F
 
 
+def nc_decision_margin(q, sigma_s: float, sigma_r: float, n_iter: int = 3, inv_span=None) -> float:
+    """Smallest |dist - r_k| over the window-membership decisions nc_filter takes for the
+    guide field q (every step of every walk up to and including its first step past r_k,
+    both axes, every pass): how far the closest decision lies from its threshold."""
+    qq = np.asarray(q, dtype=np.float64)
+    s, a = _nc_params(sigma_s, sigma_r)
+    dh, dv = nc_increments(qq, a, inv_span)
+    best = math.inf
+    for r in nc_schedule(s, n_iter):
+        for d in (dh, dv.T):
+            alive = np.ones(d.shape, dtype=bool)
+            prev_sgn = None
+            for _k, sgn, dist, live in _nc_walks(d, float(r)):
+                if sgn != prev_sgn:
+                    alive = np.ones(d.shape, dtype=bool)
+                    prev_sgn = sgn
+                decided = alive & np.isfinite(dist)     # steps still walked (inside the image)
+                if decided.any():
+                    best = min(best, float(np.min(np.abs(dist[decided] - r))))
+                alive = live.copy()
+    return best
+
+
 def nc_filter_bruteforce(p, q, sigma_s, sigma_r, n_iter=3):
     """Pixel-by-pixel loops over the same definition (tiny inputs only): for each pixel walk
-    outward along the line, adding FP32 increments, and average the values reached within r."""
+    outward along the line, adding the increments, and average the values reached within r."""
     p = np.asarray(p, dtype=np.float64)
     qq = p if q is None else np.asarray(q, dtype=np.float64)
     Hn, Wn = p.shape
-    q32 = qq.astype(np.float32)
-    s32 = float(np.float32(sigma_s))
-    a = np.float32(0.0) if math.isinf(sigma_r) else np.float32(s32 / float(np.float32(sigma_r)))
+    s, a = _nc_params(sigma_s, sigma_r)
 
     def incr(x1, x0):
-        return np.float32(np.float32(1.0) + np.float32(a * np.float32(abs(np.float32(x1 - x0)))))
+        return 1.0 + a * abs(x1 - x0)
 
-    def line_pass(vals, guide, r32):
+    def line_pass(vals, guide, r):
         n = len(vals)
         out = [0.0] * n
         for j in range(n):
             tot, cnt = vals[j], 1
-            dist = np.float32(0.0)
+            dist = 0.0
             for m in range(j + 1, n):
-                dist = np.float32(dist + incr(guide[m], guide[m - 1]))
-                if not dist <= r32:
+                dist += incr(guide[m], guide[m - 1])
+                if not dist <= r:
                     break
                 tot += vals[m]
                 cnt += 1
-            dist = np.float32(0.0)
+            dist = 0.0
             for m in range(j - 1, -1, -1):
-                dist = np.float32(dist + incr(guide[m + 1], guide[m]))
-                if not dist <= r32:
+                dist += incr(guide[m + 1], guide[m])
+                if not dist <= r:
                     break
                 tot += vals[m]
                 cnt += 1
@@ -315,10 +340,9 @@ def nc_filter_bruteforce(p, q, sigma_s, sigma_r, n_iter=3):
         return out
 
     F = [list(row) for row in p]
-    for r in nc_schedule(s32, n_iter):
-        r32 = np.float32(r)
-        F = [line_pass(F[i], list(q32[i]), r32) for i in range(Hn)]
-        cols = [line_pass([F[i][j] for i in range(Hn)], [q32[i][j] for i in range(Hn)], r32) for j in range(Wn)]
+    for r in nc_schedule(s, n_iter):
+        F = [line_pass(F[i], list(qq[i]), r) for i in range(Hn)]
+        cols = [line_pass([F[i][j] for i in range(Hn)], [qq[i][j] for i in range(Hn)], r) for j in range(Wn)]
         F = [[cols[j][i] for j in range(Wn)] for i in range(Hn)]
     return np.array(F, dtype=np.float64)
 
@@ -337,10 +361,11 @@ def nc_filter_bruteforce(p, q, sigma_s, sigma_r, n_iter=3):
 #   * spatial cell s = max(1, floor(sigma_s + 1/2)) pixels: pixel x lies in cell
 #     floor((x + floor(s/2)) / s) and is read back at x / s;
 #   * range cell 1 / inv from min(q): inv = 1 / sigma_r, lowered if needed so
-#     that at most GRID_ZMAX bins span [min q, max q]; a pixel's bin is the
-#     integer decision floor((q - min q) inv + 1/2), taken in FP32 one
-#     rounding per operation as the GPU kernel takes it; with the normalise
-#     flag inv is divided by the field's span first;
+#     that at most GRID_ZMAX bins span [min q, max q]; a pixel's bin is
+#     floor((q - min q) inv + 1/2), in FP64 like everything here (the bin is a
+#     discontinuous function of q: ``grid_bin_margin`` reports how close the
+#     closest pixel lies to a bin boundary); with the normalise flag inv is
+#     divided by the field's span first;
 #   * blur: Gaussian taps exp(-k^2 / (2 sigma^2)) for k in [-2, 2], sigma =
 #     sigma_s / s cells along x and y and sigma_r inv cells along the range;
 #     the range axis has two empty bins of padding at each end;
@@ -353,23 +378,48 @@ GRID_ZMAX = 32
 
 
 def grid_cell(sigma_s: float) -> int:
-    """Spatial cell size s = max(1, floor(sigma_s + 1/2)) from the FP32 sigma_s."""
+    """Spatial cell size: sigma_s (the sampling rate of the Paris-Durand grid) rounded to a
+    whole number of pixels, halves up, at least 1: max(1, floor(sigma_s + 1/2)), from the
+    library's FP32 sigma_s."""
     return max(1, int(math.floor(float(np.float32(sigma_s)) + 0.5)))
 
 
-def grid_range(q: np.ndarray, sigma_r: float, inv_span=None):
-    """FP32 range origin and scale of the guide field q: (qmin, inv, bins per pixel, bins in use)."""
-    q32 = np.asarray(q, dtype=np.float64).astype(np.float32)
-    qmin = np.float32(q32.min())
-    span = np.float32(np.float32(q32.max()) - qmin)
-    inv = np.float32(0.0) if math.isinf(sigma_r) else np.float32(1.0 / float(np.float32(sigma_r)))
+def _grid_scale(q: np.ndarray, sigma_r: float, inv_span=None):
+    """Range origin, span and bins per unit of the guide field q (FP64): inv = 1 / sigma_r
+    (times inv_span when normalised), lowered to (GRID_ZMAX - 1) / span when more bins than
+    GRID_ZMAX would be needed."""
+    q = np.asarray(q, dtype=np.float64)
+    qmin = float(q.min())
+    span = float(q.max()) - qmin
+    inv = 0.0 if math.isinf(sigma_r) else 1.0 / float(np.float32(sigma_r))
     if inv_span is not None:
-        inv = np.float32(inv * np.float32(inv_span))
-    if np.float32(span * inv) > np.float32(GRID_ZMAX - 1):
-        inv = np.float32(np.float32(GRID_ZMAX - 1) / span)
-    t = ((q32 - qmin).astype(np.float32) * inv).astype(np.float32)
-    z = np.floor((t + np.float32(0.5)).astype(np.float32)).astype(np.int64)
-    return float(qmin), inv, z, int(z.max()) + 1
+        inv *= float(inv_span)
+    capped = span * inv > GRID_ZMAX - 1
+    if capped:
+        inv = (GRID_ZMAX - 1) / span
+    return qmin, span, inv, capped
+
+
+def grid_range(q: np.ndarray, sigma_r: float, inv_span=None):
+    """Range origin and scale of the guide field q: (qmin, inv, bin of every pixel, bins in
+    use); the bin is floor((q - qmin) inv + 1/2)."""
+    q = np.asarray(q, dtype=np.float64)
+    qmin, _span, inv, _capped = _grid_scale(q, sigma_r, inv_span)
+    z = np.floor((q - qmin) * inv + 0.5).astype(np.int64)
+    return qmin, inv, z, int(z.max()) + 1
+
+
+def grid_bin_margin(q: np.ndarray, sigma_r: float, inv_span=None) -> float:
+    """How close the grid's integer decisions come to their thresholds for the guide field
+    q: the smallest distance of (q - qmin) inv + 1/2 from an integer over the pixels, and of
+    span inv from GRID_ZMAX - 1 (the cap decision), in bins."""
+    q = np.asarray(q, dtype=np.float64)
+    qmin, span, inv, _capped = _grid_scale(q, sigma_r, inv_span)
+    raw = 0.0 if math.isinf(sigma_r) else 1.0 / float(np.float32(sigma_r))
+    if inv_span is not None:
+        raw *= float(inv_span)
+    t = (q - qmin) * inv + 0.5
+    return min(float(np.min(np.abs(t - np.round(t)))), abs(span * raw - (GRID_ZMAX - 1)))
 
 
 def _grid_taps(sigma_cells: float):
@@ -417,8 +467,7 @@ def grid_filter(p: np.ndarray, q, sigma_s: float, sigma_r: float, inv_span=None)
                 out[tuple(dst)] += w * arr[tuple(src)]
             arr[...] = out
     yy, xx = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
-    q32 = qq.astype(np.float32).astype(np.float64)
-    fz = (q32 - qmin) * float(inv) + GRID_PAD
+    fz = (qq - qmin) * float(inv) + GRID_PAD
     fy = yy / s - oy
     fx = xx / s - ox
     z0, y0, x0 = np.floor(fz).astype(np.int64), np.floor(fy).astype(np.int64), np.floor(fx).astype(np.int64)
@@ -445,7 +494,6 @@ def grid_filter_bruteforce(p, q, sigma_s, sigma_r):
     qmin, inv, zb, nz = grid_range(qq, sigma_r)
     ts = _grid_taps(float(np.float32(sigma_s)) / s)
     tz = _grid_taps(0.0 if math.isinf(sigma_r) else float(np.float32(sigma_r)) * float(inv))
-    q32 = qq.astype(np.float32).astype(np.float64)
     m = 4 * s + s // 2 + 1
 
     def tap(taps, d):
@@ -454,7 +502,7 @@ def grid_filter_bruteforce(p, q, sigma_s, sigma_r):
     out = np.zeros_like(p)
     for i in range(H):
         for j in range(W):
-            fz, fy, fx = (q32[i, j] - qmin) * float(inv), i / s, j / s
+            fz, fy, fx = (qq[i, j] - qmin) * float(inv), i / s, j / s
             z0, y0, x0 = math.floor(fz), math.floor(fy), math.floor(fx)
             num = den = 0.0
             for a in range(-m, H + m):
@@ -807,14 +855,14 @@ def _normalise_unit(v: np.ndarray):
 
 
 def _field_inv_span(p, q, sigma_r, normalize):
-    # the normalisation of the experiments section maps the guide field g to
-    # [0, 1], scaling its differences by 1/span(g): taken in FP32 from the raw
-    # field (min, max and the reciprocal of max - min each rounded once)
+    """The normalisation of the experiments section maps the guide field to [0, 1], which
+    scales its differences by 1 / span (None: no normalisation, range kernel off, or a
+    constant field, which keeps sigma_r)."""
     if not (normalize and math.isfinite(sigma_r)):
         return None
-    g32 = np.asarray(p if q is None else q, dtype=np.float64).astype(np.float32)
-    span32 = np.float32(np.float32(g32.max()) - np.float32(g32.min()))
-    return np.float32(np.float32(1.0) / span32) if span32 > 0 else None
+    g = np.asarray(p if q is None else q, dtype=np.float64)
+    span = float(g.max()) - float(g.min())
+    return 1.0 / span if span > 0 else None
 
 
 def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iterations=3, amf_height=0):
@@ -827,17 +875,11 @@ def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iter
         return amf_filter(p, q, sigma_s, sigma_r, amf_height, _field_inv_span(p, q, sigma_r, normalize))
     if filt == "nc":
         # NC-LS (Section III-D): the NC filter in place of the BLF.  With the
-        # normalisation of the experiments section the guide field g is mapped
-        # to [0, 1], which scales its differences by 1/span(g): the increments
-        # take that factor, computed in FP32 from the raw field (min, max and
-        # the reciprocal of max - min each rounded once); the filtered field's
-        # own affine map commutes with the averaging.
-        inv = None
-        if normalize and math.isfinite(sigma_r):
-            g32 = np.asarray(p if q is None else q, dtype=np.float64).astype(np.float32)
-            span32 = np.float32(np.float32(g32.max()) - np.float32(g32.min()))
-            if span32 > 0:
-                inv = np.float32(np.float32(1.0) / span32)
+        # normalisation of the experiments section the guide field is mapped to
+        # [0, 1], which scales its differences (and so the increments' range
+        # term) by 1/span; the filtered field's own affine map commutes with
+        # the averaging.
+        inv = _field_inv_span(p, q, sigma_r, normalize)
         return nc_filter(p, q, sigma_s, sigma_r, nc_iterations, inv)
     if not normalize:
         return bilateral_filter(p, q, sigma_s, sigma_r, radius)

@@ -18,6 +18,7 @@ __all__ = [
     "voronoi_rgb",
     "joint_pair",
     "config_seed",
+    "quantized",
 ]
 
 N_SITES = 32
@@ -82,3 +83,10 @@ def joint_pair(height: int, width: int, index: int, noise_sigma: float = 0.05):
     rng = np.random.default_rng(4500 + int(index))
     target = guide + rng.normal(0.0, noise_sigma, size=(height, width))
     return target, guide
+
+
+def quantized(img: np.ndarray, levels: int = 64) -> np.ndarray:
+    """img rounded to the nearest multiple of 1/levels (an image stored with a few bits per
+    sample).  With levels a power of two every sample, every difference of samples and
+    every small multiple of those is exact in binary floating point, FP32 included."""
+    return np.round(np.asarray(img, dtype=np.float64) * levels) / levels

@@ -1,14 +1,27 @@
 """GPU parity of NC-LS (Section III-D: the domain transform's normalized
 convolution in place of the BLF) against the FP64 oracle, through the C ABI.
 
-Window membership is decided in FP32 on both sides from the same guide values,
-so with identical range sources the GPU and the oracle pick the same windows
-and differ only by FP32 averaging and transforms: max-abs 1e-5 for FP32
-fields, 2e-3 and PSNR >= 50 dB for 16-bit fields.  Rolling guidance makes
-iteration k's range source the previous output, which differs in its last
-bits between the two sides; iteration 2 is therefore checked against the
-oracle's joint filtering guided by the GPU's own first iteration (the
-definition of the rolling step).
+Window membership is a discontinuous function of the guide: the oracle decides
+it in FP64, the kernel in FP32.  The two pick the same windows whenever the
+kernel's rounding of a transformed distance stays below the distance between
+that distance and the box radius.  The kernel sums at most 33 increments (box
+radii up to 32), each and each partial sum rounded once, so its distances are
+within 33 * 2^-23 * 33 < 1.3e-4 of the exact ones.  The inputs here are images
+with 6-bit samples (multiples of 1/64, ``synth.quantized``), whose increments
+fall on a coarse grid; every test asserts that the oracle's smallest decision
+margin (``oracle.nc_decision_margin``) is at least MARGIN = 1e-3, so both
+sides take every decision alike and then differ only by FP32 averaging and
+transforms: max-abs 1e-5 for FP32 fields, 2e-3 and PSNR >= 50 dB for 16-bit
+fields.
+
+Rolling guidance takes iteration k's range source from the previous output,
+which is not on such a grid and differs in its last bits between the two
+sides; a decision close to its threshold can then go either way, moving one
+sample in or out of a window.  The end-to-end rolling test therefore states a
+distributional bar (most pixels at the FP32 tolerance, the rest within the
+effect of a few such moves), and a separate test checks the rolling step's
+definition exactly: iteration 2 equals, bit for bit, the GPU's own joint
+filtering guided by its first iteration.
 """
 import math
 
@@ -16,13 +29,27 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import voronoi_image, voronoi_rgb, joint_pair
+from synth import voronoi_image, voronoi_rgb, joint_pair, quantized
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL_FP32 = 1e-5
 TOL_MIXED = 2e-3
+MARGIN = 1e-3
+
+
+def _assert_margin(src, ss, sr, normalize=False, n_iter=3):
+    """The oracle's decisions on the range source `src` (an image, one channel or a stack)
+    all lie at least MARGIN from their thresholds."""
+    src = np.asarray(src, dtype=np.float32).astype(np.float64)
+    for ch in (src if src.ndim == 3 else [src]):
+        for q in (oracle.grad_x(ch), oracle.grad_y(ch)):
+            inv = None
+            if normalize and math.isfinite(sr) and q.max() > q.min():
+                inv = 1.0 / (q.max() - q.min())
+            m = oracle.nc_decision_margin(q, ss, sr, n_iter, inv)
+            assert m >= MARGIN, f"input too close to a window decision: margin {m:.2e}"
 
 
 def blfls():
@@ -59,7 +86,8 @@ def _psnr(a, b):
     (80, 100, 21.0, 0.3, 20.0),     # first box radius 31.75: the largest halo
 ])
 def test_nc_ls_parity(H, W, ss, sr, lam):
-    f = voronoi_image(H, W, 500 + H + W)
+    f = quantized(voronoi_image(H, W, 500 + H + W))
+    _assert_margin(f, ss, sr)
     u, fin = _nc(f, lam=lam, sigma_s=ss, sigma_r=sr)
     ref = oracle.smooth(fin, lam, ss, sr, filter="nc")
     err = float(np.max(np.abs(u - ref)))
@@ -69,25 +97,30 @@ def test_nc_ls_parity(H, W, ss, sr, lam):
 
 @pytest.mark.parametrize("rounds", [1, 2, 5])
 def test_nc_rounds(rounds):
-    f = voronoi_image(64, 80, 77 + rounds)
+    f = quantized(voronoi_image(64, 80, 77 + rounds))
+    _assert_margin(f, 3.0, 0.05, n_iter=rounds)
     u, fin = _nc(f, lam=20.0, sigma_s=3.0, sigma_r=0.05, filter_iterations=rounds)
     ref = oracle.smooth(fin, 20.0, 3.0, 0.05, filter="nc", nc_iterations=rounds)
     assert np.max(np.abs(u - ref)) <= TOL_FP32
 
 
 def test_nc_rgb_and_joint():
-    f = voronoi_rgb(64, 96, 3)
+    f = quantized(voronoi_rgb(64, 96, 3))
+    _assert_margin(f, 4.0, 0.05)
     u, fin = _nc(f, lam=30.0, sigma_s=4.0, sigma_r=0.05)
     ref = oracle.smooth(fin, 30.0, 4.0, 0.05, filter="nc")
     assert np.max(np.abs(u - ref)) <= TOL_FP32
     t, g = joint_pair(96, 128, 3)
+    g = quantized(g)
+    _assert_margin(g, 4.0, 0.08)
     u, tin = _nc(t, g, lam=30.0, sigma_s=4.0, sigma_r=0.08)
     ref = oracle.smooth(tin, 30.0, 4.0, 0.08, guide=np.asarray(g, np.float32).astype(np.float64), filter="nc")
     assert np.max(np.abs(u - ref)) <= TOL_FP32
 
 
 def test_nc_normalize_and_range_off():
-    f = voronoi_image(72, 90, 91)
+    f = quantized(voronoi_image(72, 90, 91))
+    _assert_margin(f, 3.0, 0.3, normalize=True)
     u, fin = _nc(f, lam=20.0, sigma_s=3.0, sigma_r=0.3, normalize=True)
     ref = oracle.smooth(fin, 20.0, 3.0, 0.3, normalize=True, filter="nc")
     assert np.max(np.abs(u - ref)) <= TOL_FP32
@@ -96,15 +129,34 @@ def test_nc_normalize_and_range_off():
     assert np.max(np.abs(u - ref)) <= TOL_FP32
 
 
-def test_nc_rolling_step_is_joint_filtering_guided_by_the_previous_output():
-    f = voronoi_image(96, 128, 93)
+def test_nc_rolling_end_to_end():
+    """Rolling NC-LS with the texture-removal settings (three iterations from a
+    Gaussian-smoothed guide) against oracle.smooth(iterations=3), nothing of the GPU's
+    fed to the oracle.  Iterations 2 and 3 decide windows from the previous output, so
+    a decision within rounding of its threshold may go either way: the bar is the FP32
+    tolerance at 97% of the pixels, 2e-3 (a few samples moved in or out of windows) at
+    every pixel, and a PSNR of 80 dB; measured on the CPU by perturbing the FP64 guide
+    by 1e-7, such moves touch about 1% of the pixels by up to 8e-4."""
+    f = quantized(voronoi_image(128, 160, 93))
+    prm = dict(lam=20.0, sigma_s=8.0, sigma_r=0.02, iterations=3, sigma_guide=2.5)
+    u, fin = _nc(f, **prm)
+    ref = oracle.smooth(fin, filter="nc", **prm)
+    d = np.abs(u - ref)
+    frac = float(np.mean(d <= TOL_FP32))
+    print(f"rolling NC-LS n=3: {frac:.4f} of pixels within 1e-5, max-abs {d.max():.3e}, "
+          f"PSNR {_psnr(u, ref):.1f} dB")
+    assert frac >= 0.97 and d.max() <= 2e-3 and _psnr(u, ref) >= 80.0
+
+
+def test_nc_rolling_step_is_the_gpu_joint_step_guided_by_the_previous_output():
+    """Iteration 2 of rolling guidance is, bit for bit, the GPU's own joint filtering
+    guided by its first iteration (the definition of the rolling step); iteration 1
+    matches the oracle at the FP32 tolerance."""
+    f = quantized(voronoi_image(96, 128, 93))
+    _assert_margin(f, 4.0, 0.02)
     u1, fin = _nc(f, lam=20.0, sigma_s=4.0, sigma_r=0.02, iterations=1)
     u2, _ = _nc(f, lam=20.0, sigma_s=4.0, sigma_r=0.02, iterations=2)
-    # iteration 1 matches the oracle; iteration 2 is the joint step guided by u1
     assert np.max(np.abs(u1 - oracle.smooth(fin, 20.0, 4.0, 0.02, filter="nc"))) <= TOL_FP32
-    ref2 = oracle.smooth(fin, 20.0, 4.0, 0.02, guide=u1, filter="nc")
-    assert np.max(np.abs(u2 - ref2)) <= TOL_FP32
-    # and the GPU's own joint call with that guide gives the same result
     u2j, _ = _nc(f, u1, lam=20.0, sigma_s=4.0, sigma_r=0.02)
     assert np.max(np.abs(u2 - u2j)) == 0.0
 
@@ -121,7 +173,8 @@ def test_nc_exact_special_cases():
 
 @pytest.mark.parametrize("precision", ["bf16", "fp16"])
 def test_nc_mixed_precision_fields(precision):
-    f = voronoi_rgb(128, 160, 4)
+    f = quantized(voronoi_rgb(128, 160, 4))
+    _assert_margin(f, 6.0, 0.05)
     u, fin = _nc(f, lam=30.0, sigma_s=6.0, sigma_r=0.05, precision=precision)
     ref = oracle.smooth(fin, 30.0, 6.0, 0.05, filter="nc")
     err = float(np.max(np.abs(u - ref)))
@@ -131,7 +184,8 @@ def test_nc_mixed_precision_fields(precision):
 
 
 def test_nc_rgb_1024_channel_full_size():
-    f = voronoi_rgb(1024, 1024, 1)
+    f = quantized(voronoi_rgb(1024, 1024, 1))
+    _assert_margin(f[0], 8.0, 0.05)
     u, fin = _nc(f, lam=20.0, sigma_s=8.0, sigma_r=0.05)
     ref0 = oracle.smooth(fin[0], 20.0, 8.0, 0.05, filter="nc")
     err = float(np.max(np.abs(u[0] - ref0)))

@@ -376,3 +376,100 @@ def test_gaussian_blur_normalised_and_symmetric():
     assert abs(b.sum() - 1.0) < 1e-14
     assert np.allclose(b, b.T) and np.allclose(b, b[::-1, ::-1])
     assert b[7, 7] == b.max()
+
+
+@pytest.mark.parametrize("sigma", [0.7, 1.2, 1.7, 2.5])
+def test_gaussian_blur_is_the_library_gaussian_on_a_torus(sigma):
+    """The initial guide's smoothing (Section III-D) against scipy's Gaussian filter with
+    the same radius ceil(3 sigma) and wrap-around borders: an independent implementation
+    of the normalised sampled Gaussian (separable, so its 2-D normalisation is the product
+    of the 1-D ones)."""
+    from scipy import ndimage
+    img = np.random.default_rng(31).random((23, 29))
+    r = int(math.ceil(3.0 * sigma))
+    ref = ndimage.gaussian_filter(img, sigma, mode="wrap", radius=r)
+    assert np.max(np.abs(oracle.gaussian_blur(img, sigma) - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("sigma", [0.9, 1.7, 2.5])
+def test_gaussian_blur_impulse_support_and_variance(sigma):
+    """Impulse response: nonzero exactly on the square of radius ceil(3 sigma), rank one
+    (Euclidean distance makes the 2-D Gaussian separable), and a second moment per axis
+    of sigma^2 up to the truncation at 3 sigma (which removes less than 3% of it)."""
+    n = 41
+    img = np.zeros((n, n))
+    img[n // 2, n // 2] = 1.0
+    b = oracle.gaussian_blur(img, sigma)
+    r = int(math.ceil(3.0 * sigma))
+    k = np.arange(n) - n // 2
+    inside = (np.abs(k)[:, None] <= r) & (np.abs(k)[None, :] <= r)
+    assert np.all(b[inside] > 0) and np.all(b[~inside] == 0)
+    s = np.linalg.svd(b, compute_uv=False)
+    assert s[1] < 1e-12 * s[0]
+    var_y = float(np.sum(b * (k[:, None] ** 2)))
+    assert 0.97 * sigma ** 2 < var_y <= sigma ** 2 * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("sigma_s,s", [(0.3, 1), (1.0, 1), (1.49, 1), (1.5, 2), (2.5, 3), (3.0, 3),
+                                       (7.6, 8), (8.0, 8), (8.5, 9), (20.0, 20)])
+def test_grid_cell_hand_derived(sigma_s, s):
+    """Cell size: sigma_s rounded to whole pixels, halves up, at least one pixel."""
+    assert oracle.grid_cell(sigma_s) == s
+
+
+def test_grid_range_hand_derived_bins():
+    """Bins worked by hand: q = (0, 0.25, 0.26, 0.74, 1) with sigma_r = 0.5 gives inv = 2,
+    t = (0, 0.5, 0.52, 1.48, 2) and bins floor(t + 1/2) = (0, 1, 1, 1, 2) (a half rounds
+    up); a field spanning [-1, 1] with sigma_r = 0.01 would need 200 bins, so inv drops
+    to 31 / 2 = 15.5 and q = (-1, -0.5, 0, 0.5, 1) fall in bins (0, 8, 16, 23, 31): t = (0,
+    7.75, 15.5, 23.25, 31), so 32 bins."""
+    q = np.array([[0.0, 0.25, 0.26, 0.74, 1.0]])
+    qmin, inv, z, nz = oracle.grid_range(q, 0.5)
+    assert qmin == 0.0 and abs(inv - 2.0) < 1e-7 and nz == 3
+    assert z.tolist() == [[0, 1, 1, 1, 2]]
+    q = np.array([[-1.0, -0.5, 0.0, 0.5, 1.0]])
+    qmin, inv, z, nz = oracle.grid_range(q, 0.01)
+    assert qmin == -1.0 and inv == 15.5 and nz == oracle.GRID_ZMAX
+    assert z.tolist() == [[0, 8, 16, 23, 31]]
+    # the same field with normalisation (inv_span = 1/2) and sigma_r = 0.25: 2 bins per unit
+    qmin, inv, z, nz = oracle.grid_range(q, 0.25, 0.5)
+    assert abs(inv - 2.0) < 1e-7 and z.tolist() == [[0, 1, 2, 3, 4]] and nz == 5
+
+
+def test_grid_bin_margin_hand_derived():
+    """t + 1/2 = (0.5, 1.0, 1.02, 1.98, 2.5) for the first field above: the closest
+    decision is the exact half (margin 0); without it, 0.02."""
+    q = np.array([[0.0, 0.25, 0.26, 0.74, 1.0]])
+    assert oracle.grid_bin_margin(q, 0.5) < 1e-7
+    q = np.array([[0.0, 0.26, 0.74, 1.0]])
+    assert abs(oracle.grid_bin_margin(q, 0.5) - 0.02) < 1e-7
+    # the cap decision: span 2 at inv 15.4 is 30.8 bins, 0.2 from the cap at 31
+    q = np.array([[-1.0, 1.0]])
+    assert abs(oracle.grid_bin_margin(q, 1.0 / 15.4) - 0.2) < 1e-6
+
+
+def test_nc_decision_margin_by_loops():
+    """The NC filter's smallest decision margin against explicit walks over every pixel,
+    direction and pass (tiny field)."""
+    rng = np.random.default_rng(5)
+    q = rng.random((5, 7))
+    ss, sr = 2.0, 0.7
+    s32, r32 = float(np.float32(ss)), float(np.float32(sr))
+    a = s32 / r32
+    best = math.inf
+    for rad in oracle.nc_schedule(s32, 3):
+        for line_set in (q, q.T):
+            for line in line_set:
+                n = len(line)
+                for j in range(n):
+                    for step in (1, -1):
+                        dist = 0.0
+                        m = j
+                        while 0 <= m + step < n:
+                            nxt = m + step
+                            dist += 1.0 + a * abs(line[nxt] - line[m])
+                            best = min(best, abs(dist - rad))
+                            m = nxt
+                            if dist > rad:
+                                break
+    assert abs(oracle.nc_decision_margin(q, ss, sr, 3) - best) < 1e-12

@@ -3,7 +3,9 @@
 Each mutation swaps one oracle function for a subtly wrong version: a backward
 difference, a missing conjugate, a wrong range-kernel sign, a dropped term, an
 NC filter with a wrong box schedule, wrapping windows or wrong increments, a
-bilateral grid with a wrong Gaussian or without the periodic extension, an
+bilateral grid with a wrong Gaussian, without the periodic extension, with bins
+rounded down or halves to even, a cap one bin too high or cells rounded halves
+to even, an initial-guide Gaussian with sigma for sigma^2 or a short radius, an
 adaptive-manifold filter with a shifted backward coefficient, the unhalved range
 sigma in its blur, no column pass or no blend for far pixels.
 The pins of ``test_oracle.py`` must reject every one of them.
@@ -91,15 +93,14 @@ def _bad_nc_box_wrap(F, d, r, axis):
     F = np.asarray(F, dtype=np.float64)
     if axis == 0:
         return _bad_nc_box_wrap(F.T, d.T, r, 1).T
-    r32 = np.float32(r)
     num, cnt = F.copy(), np.ones_like(F)
     for sgn in (1, -1):
-        dist = np.zeros(F.shape, dtype=np.float32)
+        dist = np.zeros(F.shape)
         live = np.ones(F.shape, dtype=bool)
-        for k in range(1, int(r32) + 2):
+        for k in range(1, int(r) + 2):
             inc = np.roll(d, -k if sgn > 0 else k - 1, axis=1)
-            dist = (dist + inc).astype(np.float32)
-            live &= dist <= r32
+            dist = dist + inc
+            live &= dist <= r
             num += np.where(live, np.roll(F, -sgn * k, axis=1), 0.0)
             cnt += live
     return num / cnt
@@ -107,9 +108,71 @@ def _bad_nc_box_wrap(F, d, r, axis):
 
 def _bad_nc_increments(q, a, inv_span=None):
     # increments from the guide values instead of their differences
-    q32 = np.asarray(q, dtype=np.float64).astype(np.float32)
-    d = (np.float32(1.0) + (np.float32(a) * np.abs(q32)).astype(np.float32)).astype(np.float32)
+    d = 1.0 + float(a) * np.abs(np.asarray(q, dtype=np.float64))
     return d, d.copy()
+
+
+def _bad_gauss_sigma(img, sigma):
+    # exp(-d^2 / (2 sigma)) instead of exp(-d^2 / (2 sigma^2))
+    img = np.asarray(img, dtype=np.float64)
+    r = int(math.ceil(3.0 * sigma))
+    acc, tot = np.zeros_like(img), 0.0
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            w = math.exp(-(dx * dx + dy * dy) / (2.0 * sigma))
+            acc += w * np.roll(img, (-dy, -dx), axis=(-2, -1))
+            tot += w
+    return acc / tot
+
+
+def _bad_gauss_radius(img, sigma):
+    # radius ceil(2 sigma) instead of ceil(3 sigma)
+    img = np.asarray(img, dtype=np.float64)
+    r = int(math.ceil(2.0 * sigma))
+    acc, tot = np.zeros_like(img), 0.0
+    for dy in range(-r, r + 1):
+        for dx in range(-r, r + 1):
+            w = math.exp(-(dx * dx + dy * dy) / (2.0 * sigma * sigma))
+            acc += w * np.roll(img, (-dy, -dx), axis=(-2, -1))
+            tot += w
+    return acc / tot
+
+
+_orig_grid_scale = ob._grid_scale
+
+
+def _bad_grid_range_floor(q, sigma_r, inv_span=None):
+    # bins floor(t) instead of floor(t + 1/2)
+    q = np.asarray(q, dtype=np.float64)
+    qmin, _span, inv, _c = _orig_grid_scale(q, sigma_r, inv_span)
+    z = np.floor((q - qmin) * inv).astype(np.int64)
+    return qmin, inv, z, int(z.max()) + 1
+
+
+def _bad_grid_range_half_even(q, sigma_r, inv_span=None):
+    # halves rounded to even instead of up
+    q = np.asarray(q, dtype=np.float64)
+    qmin, _span, inv, _c = _orig_grid_scale(q, sigma_r, inv_span)
+    z = np.round((q - qmin) * inv).astype(np.int64)
+    return qmin, inv, z, int(z.max()) + 1
+
+
+def _bad_grid_scale_cap(q, sigma_r, inv_span=None):
+    # the cap lets GRID_ZMAX + 1 bins through
+    q = np.asarray(q, dtype=np.float64)
+    qmin = float(q.min())
+    span = float(q.max()) - qmin
+    inv = 0.0 if math.isinf(sigma_r) else 1.0 / float(np.float32(sigma_r))
+    if inv_span is not None:
+        inv *= float(inv_span)
+    capped = span * inv > ob.GRID_ZMAX
+    if capped:
+        inv = ob.GRID_ZMAX / span
+    return qmin, span, inv, capped
+
+
+def _bad_grid_cell_half_even(sigma_s):
+    return max(1, int(round(float(np.float32(sigma_s)))))
 
 
 def _bad_grid_taps(sigma_cells):
@@ -200,6 +263,12 @@ MUTATIONS = {
     "nc_increments_from_values": ("nc_increments", _bad_nc_increments),
     "grid_sigma_not_squared": ("_grid_taps", _bad_grid_taps),
     "grid_zero_border": ("grid_filter", _bad_grid_zero_border),
+    "grid_bin_floor": ("grid_range", _bad_grid_range_floor),
+    "grid_bin_half_to_even": ("grid_range", _bad_grid_range_half_even),
+    "grid_cap_off_by_one": ("_grid_scale", _bad_grid_scale_cap),
+    "grid_cell_half_to_even": ("grid_cell", _bad_grid_cell_half_even),
+    "gaussian_guide_sigma_not_squared": ("gaussian_blur", _bad_gauss_sigma),
+    "gaussian_guide_radius": ("gaussian_blur", _bad_gauss_radius),
     "amf_backward_coefficient_index": ("amf_rf_line_rows", _bad_amf_rf_backward_index),
     "amf_blur_sigma_not_halved": ("_amf_alpha", _bad_amf_alpha_sigma),
     "amf_blur_rows_only": ("amf_blur", _bad_amf_rows_only),
@@ -222,6 +291,13 @@ PIN_SUITE = [
     nc_pins.test_nc_keeps_constants_and_clean_steps,
     lambda: grid_pins.test_grid_with_unit_cells_and_no_range_is_the_exact_gaussian(0.75),
     grid_pins.test_grid_commutes_with_whole_cell_shifts,
+    pins.test_grid_range_hand_derived_bins,
+    pins.test_grid_bin_margin_hand_derived,
+    lambda: pins.test_grid_cell_hand_derived(2.5, 3),
+    lambda: pins.test_grid_cell_hand_derived(8.5, 9),
+    lambda: pins.test_gaussian_blur_is_the_library_gaussian_on_a_torus(1.7),
+    lambda: pins.test_gaussian_blur_impulse_support_and_variance(1.7),
+    pins.test_nc_decision_margin_by_loops,
     lambda: amf_pins.test_amf_matches_explicit_operators(6, 6, 3.0, 0.05, 3),
     amf_pins.test_rf_step_that_cannot_be_crossed_splits_the_line,
     amf_pins.test_range_off_is_the_separable_exponential_kernel,
