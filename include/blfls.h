@@ -255,7 +255,14 @@ blfls_status blfls_server_create(blfls_server_t *out, void *arena, size_t arena_
 
 /* Queue a request.  Validated at once (same errors as blfls_smooth; a request
  * whose workspace exceeds the whole arena gives BLFLS_E_NOMEM).  A full queue
- * gives BLFLS_E_AGAIN.  On success *ticket identifies the request. */
+ * gives BLFLS_E_AGAIN.  On success *ticket identifies the request.
+ * Ordering: the request's kernels run on the server's stream at some later
+ * step and synchronise with nothing else, so f and guide must be fully
+ * written, and u no longer in use, as seen from the server's stream, before
+ * the call: work still queued on another stream must be made to precede it
+ * (hipStreamWaitEvent on the server's stream; the Python binding does this for
+ * the caller's current stream).  The buffers stay owned by the caller and must
+ * stay valid until blfls_poll reports DONE or FAILED. */
 blfls_status blfls_submit(blfls_server_t server, const blfls_request *request, uint64_t *ticket);
 
 /* State of a ticket: *state is BLFLS_QUEUED, _RUNNING, _DONE or _FAILED;

@@ -188,6 +188,32 @@ def profile_read(reset: bool = True) -> dict:
     return {name: (pr.ms[i], int(pr.launches[i])) for i, name in enumerate(STAGES)}
 
 
+def _checked_image(t, name: str, shape=None, device=None):
+    """t viewed as (C, H, W) after checking that it is a contiguous float32 CUDA tensor of
+    that shape on that device (raises ValueError before anything is queued)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dim() not in (2, 3):
+        raise ValueError(f"{name} must be a 2-D (H, W) or 3-D (C, H, W) torch tensor")
+    t3 = t.reshape(1, *t.shape) if t.dim() == 2 else t
+    if t3.dtype != torch.float32 or not t3.is_cuda or not t3.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+    if shape is not None and tuple(t3.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t3.shape)})")
+    if device is not None and t3.device != torch.device(device):
+        raise ValueError(f"{name} is on {t3.device}, expected {device}")
+    return t3
+
+
+def _new_or_checked_out(out, f3, shape, device):
+    import torch
+    if out is None:
+        return torch.empty_like(f3)
+    u = _checked_image(out, "out", shape, device)
+    if u.data_ptr() == f3.data_ptr():
+        raise ValueError("out must not be f")
+    return u
+
+
 class Plan:
     """A ``blfls_plan`` for (C, H, W) images at one precision, with its workspace."""
 
@@ -223,17 +249,9 @@ class Plan:
                filter: str = "blf", filter_iterations: int = 0, detail_gain: float = 0.0):
         import torch
         shape = (self.C, self.H, self.W)
-        f3 = f.reshape(shape) if f.dim() == 2 else f
-        if tuple(f3.shape) != shape or f3.dtype != torch.float32 or not f3.is_cuda:
-            raise ValueError(f"f must be a float32 CUDA tensor of shape {shape}")
-        if not f3.is_contiguous():
-            raise ValueError("f must be contiguous")
-        g3 = None
-        if guide is not None:
-            g3 = guide.reshape(shape) if guide.dim() == 2 else guide
-            if tuple(g3.shape) != shape or g3.dtype != torch.float32 or not g3.is_contiguous():
-                raise ValueError(f"guide must be a contiguous float32 CUDA tensor of shape {shape}")
-        u = torch.empty_like(f3) if out is None else out
+        f3 = _checked_image(f, "f", shape, self.device)
+        g3 = None if guide is None else _checked_image(guide, "guide", shape, self.device)
+        u = _new_or_checked_out(out, f3, shape, self.device)
         prm = make_params(lam, sigma_s, sigma_r, radius, iterations, normalize, sigma_guide, filter,
                           filter_iterations, detail_gain)
         need = self.workspace_for(prm)
@@ -275,7 +293,7 @@ def smooth(f, lam: float = 1024.0, sigma_s: float = 3.0, sigma_r: float = 0.1, r
     tree of height filter_iterations (0 = the default rule).  detail_gain m != 0 returns
     u + m (f - u) (the experiments' detail enhancement uses m = 5).
     """
-    C, H, W = (1, *f.shape) if f.dim() == 2 else tuple(f.shape)
+    C, H, W = tuple(_checked_image(f, "f").shape)
     key = (C, H, W, _PRECISIONS[precision], f.device.index)
     plan = _plan_cache.get(key)
     if plan is None:
@@ -340,18 +358,25 @@ class Server:
                filter_iterations: int = 0, detail_gain: float = 0.0):
         """Queue one image; returns (ticket, u).  u is valid once poll(ticket) reports DONE.
 
-        Raises BlflsError with status E_AGAIN when the queue is full.
+        The server's stream is made to wait for the caller's current stream first, so inputs
+        still being written there, and the memory of a new ``u`` allocated there, are
+        ordered before the request's kernels.  Raises BlflsError with status E_AGAIN when
+        the queue is full, ValueError for tensors that are not contiguous float32 CUDA
+        images of one shape on the server's device.
         """
         import torch
-        C, H, W = (1, *f.shape) if f.dim() == 2 else tuple(f.shape)
-        u = torch.empty_like(f) if out is None else out
-        req = Request(H, W, C, f.data_ptr(), guide.data_ptr() if guide is not None else 0, u.data_ptr(), W,
+        f3 = _checked_image(f, "f", None, self.device)
+        C, H, W = tuple(f3.shape)
+        g3 = None if guide is None else _checked_image(guide, "guide", (C, H, W), self.device)
+        u = _new_or_checked_out(out, f3, (C, H, W), self.device)
+        self._stream.wait_stream(torch.cuda.current_stream(self.device))
+        req = Request(H, W, C, f3.data_ptr(), g3.data_ptr() if g3 is not None else 0, u.data_ptr(), W,
                       make_params(lam, sigma_s, sigma_r, radius, iterations, normalize, sigma_guide, filter,
                                   filter_iterations, detail_gain))
         ticket = ctypes.c_uint64()
         _check(lib().blfls_submit(self._handle, ctypes.byref(req), ctypes.byref(ticket)))
         self._keep[ticket.value] = (f, guide, u)
-        return ticket.value, u
+        return ticket.value, u.reshape(f.shape)
 
     def poll(self, ticket: int):
         """(state, status) of a ticket; DONE/FAILED retire it."""

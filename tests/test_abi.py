@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_1812_07122_amd as blfls
@@ -111,3 +112,14 @@ def test_struct_layouts_match_the_header(tmp_path):
         names = [n for n, _ in cls._fields_]
         for fld, py in zip(fields, names):
             assert int(out[f"{struct}.{fld}"]) == getattr(cls, py).offset, f"{struct}.{fld}"
+
+
+def test_binding_rejects_tensors_it_cannot_pass_as_planar_float32_images():
+    """The binding checks dtype, device, contiguity and shape before anything is queued
+    (CPU tensors stand in for each mistake; the CUDA checks run in the GPU suite)."""
+    torch = pytest.importorskip("torch")
+    import paper_1812_07122_amd as b
+    for bad in (torch.zeros(2, 3, 4, dtype=torch.float64), torch.zeros(2, 3, 4), np.zeros((3, 4), np.float32),
+                torch.zeros(5)):
+        with pytest.raises(ValueError):
+            b._checked_image(bad, "f")

@@ -466,3 +466,53 @@ def test_server_rejects_and_backpressure():
         server.poll(tickets[0])  # retired by the poll that reported DONE
     assert e.value.status == -6
     server.close()
+
+
+def test_binding_validates_out_guide_and_server_inputs():
+    """Wrong shapes, dtypes, strides or devices of out, guide or a served image raise
+    ValueError before anything is queued."""
+    b = blfls()
+    f = _to_gpu(voronoi_image(64, 80, 6))
+    plan = b.Plan(64, 80, 1)
+    for bad in (torch.empty(32, 80, device="cuda"), torch.empty(64, 80, device="cuda", dtype=torch.float64),
+                torch.empty(80, 64, device="cuda").t(), torch.empty(64, 80)):
+        with pytest.raises(ValueError):
+            plan.smooth(f, 20.0, 2.0, 0.1, out=bad)
+        with pytest.raises(ValueError):
+            plan.smooth(f, 20.0, 2.0, 0.1, guide=bad)
+    with pytest.raises(ValueError):
+        plan.smooth(f, 20.0, 2.0, 0.1, out=f)
+    server = b.Server(arena_bytes=64 << 20, max_slots=2)
+    for bad in (f.double(), torch.empty(80, 64, device="cuda").t(), f.cpu()):
+        with pytest.raises(ValueError):
+            server.submit(bad, lam=20.0, sigma_s=2.0, sigma_r=0.1)
+    with pytest.raises(ValueError):
+        server.submit(f, guide=torch.empty(32, 80, device="cuda"), lam=20.0, sigma_s=2.0, sigma_r=0.1)
+    with pytest.raises(ValueError):
+        server.submit(f, out=torch.empty(64, 81, device="cuda"), lam=20.0, sigma_s=2.0, sigma_r=0.1)
+    server.close()
+    plan.close()
+
+
+def test_server_orders_inputs_still_being_written_on_the_callers_stream():
+    """An image produced by GPU work still queued on the caller's stream when it is
+    submitted: the server's stream waits for that work, so the result equals the same
+    request run alone."""
+    import time
+    b = blfls()
+    img = voronoi_image(512, 512, 8)
+    server = b.Server(arena_bytes=256 << 20, max_slots=2)
+    big = torch.eye(4096, device="cuda")
+    for _ in range(20):                 # milliseconds of queued work (the products stay the identity)
+        big = big @ big
+    f = _to_gpu(img) + big[0, :1] * 0.0   # written only after the products
+    t, u = server.submit(f, lam=20.0, sigma_s=2.0, sigma_r=0.1)
+    deadline = time.time() + 60
+    while server.poll(t)[0] not in (b.DONE, b.FAILED):
+        assert time.time() < deadline
+        time.sleep(0.001)
+    server.stream.synchronize()
+    alone = b.smooth(_to_gpu(img), lam=20.0, sigma_s=2.0, sigma_r=0.1)
+    torch.cuda.synchronize()
+    assert torch.equal(alone, u)
+    server.close()
