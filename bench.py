@@ -1,19 +1,26 @@
 """Benchmark of the BLF-LS hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rgb1024|uhd|serve|joint|nc|grid|amf|copy]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload headline|rgb1024|uhd|serve|joint|nc|grid|amf|copy]
 
 A step is one whole BLF-LS pass (Eq. (1) on both gradient fields of every
 channel, then the Eq. (8) solve) over one image whose input already sits in
-HBM.  The default workload is the paper's timing shape (Table I): one
-1024x1024 RGB image, channels independent, lambda = 20, sigma_s = 3 (r = 9),
-sigma_r = 0.1, one iteration, FP32.  The step is replayed from a HIP graph
-that captured one blfls_smooth call (the eager rate is reported beside it, and
-the replayed output must equal the eager one bitwise).  Rank 0 prints one JSON
-line.
+HBM, replayed from a HIP graph that captured one blfls_smooth call.  Rank 0
+prints one JSON line.
+
+The default (headline) workload is the mixed-precision comparison: one
+3840x2160 RGB image (channels independent), lambda = 50, sigma_s = 8 (r = 24),
+sigma_r = 0.05, one iteration.  ``value`` is the plain FP32 rate; the BF16 and
+FP16 field-storage runs are timed beside it, the three interleaved in rounds so
+that clock drift falls on all of them alike, and each is compared with the
+FP64 oracle on channel 0 (max-abs and PSNR).  The line also carries the
+filter's roofline against the FP32 vector peak, the Fourier passes' HBM
+fractions, the oracle's own time on the host cores (filter and solve apart),
+and the paper's timing shape (1024x1024 RGB, lambda = 20, sigma_s = 3,
+sigma_r = 0.1; Table I) as a nested line.
 
 Other workloads (each prints its own JSON line):
-  uhd    3840x2160 RGB, sigma_s = 8 (r = 24), sigma_r = 0.05, lambda = 50,
-         FP32 against BF16 and FP16 field storage
+  rgb1024 the 1024x1024 RGB image alone, FP32 against BF16 and FP16 storage
+  uhd    3840x2160 RGB with the oracle over all three channels (minutes)
   serve  2000 requests of uneven sizes through the continuous-batching server
          with Poisson arrivals (p50/p99 latency)
   joint  64 guided 2048x2048 pairs (FP16 storage, lambda = 30, sigma_s = 4,
@@ -24,8 +31,7 @@ Other workloads (each prints its own JSON line):
          the exact filter
   amf    AMF-LS (the adaptive-manifold filter in place of the BLF) on the
          1024x1024 RGB image, trees of height 2 and 3
-The single-image lines (default, nc, amf, grid) replay the step from a captured
-graph and report the eager rate beside it.
+  copy   a 1 GiB device copy (scales the HBM byte counters)
 """
 from __future__ import annotations
 
@@ -44,9 +50,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# BLF tap peak (Ttap/s): 256 CUs x 4 SIMDs x 2.4 GHz x 64 lanes / 18 SIMD cycles per
-# wave64 tap (3 two-cycle VOP2 ops + one four-cycle VOP3 FMA + one eight-cycle v_exp_f32)
-BLF_TAP_PEAK_T = 256 * 4 * 2.4e9 * 64 / 18 / 1e12
+# MI355X published dense FP32 vector peak
+FP32_PEAK_TFLOPS = 157.3
+# Algorithmic FP32 work of one tap of Eq. (1) (one weight applied to one output of one
+# field): the range difference (1 flop), the exponent's FMA (2), the weighted value's FMA
+# (2) and the weight sum (1); plus one exponential, counted apart
+BLF_FLOPS_PER_TAP = 6
+# exponential issue rate: one wave64 v_exp_f32 per 8 SIMD cycles (a quarter of the
+# 32-lane FP32 rate), 256 CUs x 4 SIMDs at 2.4 GHz
+EXP_PEAK_T = 256 * 4 * 2.4e9 * 64 / 8 / 1e12
+# the library's kernel spends this many v_exp_f32 per tap (a symmetric pair shares one)
+BLF_KERNEL_EXPS_PER_TAP = 1.0
 
 
 def parse():
@@ -54,7 +68,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="rgb1024", choices=["rgb1024", "uhd", "serve", "joint", "nc", "grid", "amf", "copy"])
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "rgb1024", "uhd", "serve", "joint", "nc", "grid", "amf", "copy"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default=None,
                     help="nc / amf workloads: run this configuration only (e.g. for a counter run)")
@@ -147,7 +162,205 @@ def fft_bytes(H, W, C, field_bytes):
     return rows_fwd, cols, rows_inv
 
 
-def run_rgb1024(args, torch, blfls):
+def blf_roofline(kernel, H, W, C, r, blf_ms, traffic):
+    """The filter's roofline object: algorithmic FP32 flops of Eq. (1) per launch (every tap
+    of both fields of every channel) over the launch duration, against the FP32 vector
+    peak; the exponentials per second beside it."""
+    taps = C * H * W * 2 * (2 * r + 1) ** 2
+    tflops = taps * BLF_FLOPS_PER_TAP / (blf_ms * 1e-3) / 1e12
+    exps = taps * BLF_KERNEL_EXPS_PER_TAP / (blf_ms * 1e-3) / 1e12
+    return {"kernel": kernel, "bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
+            "launch_ms": round(blf_ms, 5), "taps_per_launch": taps, "flops_per_tap": BLF_FLOPS_PER_TAP,
+            "exp_pipe": {"exps_per_tap": BLF_KERNEL_EXPS_PER_TAP, "achieved_T_exp_s": round(exps, 3),
+                         "peak_T_exp_s": round(EXP_PEAK_T, 3), "frac": round(exps / EXP_PEAK_T, 4)}}
+
+
+def fft_passes(stages, H, W, C, field_bytes):
+    rf, cl, ri = fft_bytes(H, W, C, field_bytes)
+    out, tot_ms = {}, 0.0
+    for name, nbytes in (("rows_fwd", rf), ("cols", cl), ("rows_inv", ri)):
+        t = stages[name][0] / max(stages[name][1], 1)
+        tot_ms += t
+        gbs = nbytes / (t * 1e-3) / 1e9
+        out[name] = {"ms": round(t, 5), "bytes": nbytes, "GB/s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    gbs = (rf + cl + ri) / (tot_ms * 1e-3) / 1e9
+    out["all"] = {"ms": round(tot_ms, 5), "bytes": rf + cl + ri, "GB/s": round(gbs, 1),
+                  "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def _psnr(a, b):
+    mse = float(np.mean((a - b) ** 2))
+    return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
+
+
+def oracle_channel_timed(job):
+    """Worker: the FP64 oracle on one channel, Eq. (1) by the oracle's C loops (OpenMP over
+    rows) and the Eq. (8) solve by numpy.fft, each timed; returns (u, blf_s, solve_s, threads)."""
+    import oracle
+    from oracle.c_blf import bilateral_filter_c
+    f, lam, ss, sr = job
+    r = oracle.default_radius(ss)
+    t0 = time.perf_counter()
+    px, py = oracle.grad_x(f), oracle.grad_y(f)
+    gx = bilateral_filter_c(px, None, ss, sr, r)
+    gy = bilateral_filter_c(py, None, ss, sr, r)
+    t1 = time.perf_counter()
+    u = oracle.blfls_solve(f, gx, gy, lam)
+    t2 = time.perf_counter()
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    return u, t1 - t0, t2 - t1, threads
+
+
+def prepare_headline(args):
+    """CPU inputs and the oracle's worker process, before anything touches the GPU."""
+    import multiprocessing as mp
+    import synth
+    state = {"f": synth.voronoi_rgb(2160, 3840, 2).astype(np.float32),
+             "f1": synth.voronoi_rgb(1024, 1024, 1).astype(np.float32)}
+    if not args.no_cpu_baseline:
+        state["pool"] = mp.get_context("spawn").Pool(processes=1)
+    return state
+
+
+def _capture(plan, f, u, prm, torch):
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.smooth(f, out=u, **prm)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.smooth(f, out=u, **prm)
+    torch.cuda.synchronize()
+    return g
+
+
+def time_interleaved(graphs, steps, warmup, torch):
+    """ms per replay of each graph: `steps` replays each, in rounds that rotate the order of
+    the graphs, so clock and thermal drift falls on all of them alike."""
+    names = list(graphs)
+    for n in names:
+        for _ in range(warmup):
+            graphs[n].replay()
+    torch.cuda.synchronize()
+    rounds = min(5, steps)
+    per = [steps // rounds + (1 if i < steps % rounds else 0) for i in range(rounds)]
+    total = {n: 0.0 for n in names}
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    for i, k in enumerate(per):
+        order = names[i % len(names):] + names[:i % len(names)]
+        for n in order:
+            torch.cuda.synchronize()
+            start.record()
+            for _ in range(k):
+                graphs[n].replay()
+            end.record()
+            torch.cuda.synchronize()
+            total[n] += start.elapsed_time(end)
+    return {n: total[n] / steps for n in names}
+
+
+def measure_image(blfls, torch, f_np, prm, r, precisions, steps, warmup, prof_steps):
+    """Graph-replayed ms per step of each precision (interleaved), the eager stage times
+    (library HIP events on the plan's stream) and each precision's output."""
+    H, W = f_np.shape[-2:]
+    C = f_np.shape[0]
+    f = torch.from_numpy(f_np).cuda()
+    plans, graphs, outs, stages = {}, {}, {}, {}
+    for p in precisions:
+        plans[p] = blfls.Plan(H, W, C, p)
+        outs[p] = torch.empty_like(f)
+        graphs[p] = _capture(plans[p], f, outs[p], prm, torch)
+    ms = time_interleaved(graphs, steps, warmup, torch)
+    for p in precisions:
+        _, stages[p] = time_plan(plans[p], f, torch.empty_like(f), prm, prof_steps, 1, torch, blfls)
+    eager = {}
+    for p in precisions:
+        e = plans[p].smooth(f, **prm)
+        torch.cuda.synchronize()
+        eager[p] = bool(torch.equal(e, outs[p]))
+    res = {p: outs[p].cpu().numpy().astype(np.float64) for p in precisions}
+    for p in precisions:
+        plans[p].close()
+    del graphs
+    return ms, stages, res, eager
+
+
+def run_headline(args, torch, blfls, state):
+    H, W, C, r = 2160, 3840, 3, 24
+    lam, ss, sr = 50.0, 8.0, 0.05
+    prm = dict(lam=lam, sigma_s=ss, sigma_r=sr)
+    precs = ("fp32", "bf16", "fp16")
+    ms, stages, outs, eager = measure_image(blfls, torch, state["f"], prm, r, precs, args.steps, args.warmup,
+                                            prof_steps=min(args.steps, 5))
+    per = {}
+    for p, fb in zip(precs, (4, 2, 2)):
+        blf_ms = stages[p]["blf"][0] / max(stages[p]["blf"][1], 1)
+        per[p] = {"MPix/s": round(H * W / (ms[p] * 1e-3) / 1e6, 2), "ms_per_step": round(ms[p], 4),
+                  "graph_vs_eager_bitwise_equal": eager[p],
+                  "blf_ms": round(blf_ms, 4), "fft_passes": fft_passes(stages[p], H, W, C, fb)}
+    value = per["fp32"]["MPix/s"]
+    blf32 = stages["fp32"]["blf"][0] / max(stages["fp32"]["blf"][1], 1)
+    out = {
+        "metric": "MPix/s BLF-LS at 1 GPU (plain FP32 vs mixed) + p50/p99 served latency",
+        "value": value, "unit": "MPix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": per["fp32"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "uhd: 3840x2160 RGB, channels independent, lambda=50, sigma_s=8 (r=24), "
+                               "sigma_r=0.05, 1 iteration, circular boundaries; plain FP32 fields (value) "
+                               "against BF16 and FP16 field storage", "H": H, "W": W, "C": C},
+        "step_launch": "HIP graph replay of one blfls_smooth call; fp32, bf16 and fp16 replays interleaved "
+                       "in rotating rounds",
+        "roofline": blf_roofline(f"blf_field_kernel<R={r}>", H, W, C, r, blf32,
+                                 traffic_from_profile("blf_kernel.hip", "blf_kernel_uhd_pmc.md")),
+        "fft_passes": per["fp32"]["fft_passes"],
+        "precisions": per,
+        "mixed_vs_plain": {p: round(per[p]["MPix/s"] / value, 4) for p in ("bf16", "fp16")},
+    }
+    # the paper's timing shape (Table I), nested
+    r1 = 9
+    prm1 = dict(lam=20.0, sigma_s=3.0, sigma_r=0.1)
+    ms1, st1, outs1, eager1 = measure_image(blfls, torch, state["f1"], prm1, r1, ("fp32",), args.steps,
+                                            args.warmup, prof_steps=args.steps)
+    blf1 = st1["fp32"]["blf"][0] / max(st1["fp32"]["blf"][1], 1)
+    out["rgb1024"] = {
+        "config": "1024x1024 RGB, lambda=20, sigma_s=3 (r=9), sigma_r=0.1, 1 iteration, FP32 (Table I shape)",
+        "MPix/s": round(1024 * 1024 / (ms1["fp32"] * 1e-3) / 1e6, 2), "ms_per_step": round(ms1["fp32"], 5),
+        "graph_vs_eager_bitwise_equal": eager1["fp32"],
+        "roofline": blf_roofline(f"blf_field_kernel<R={r1}>", 1024, 1024, 3, r1, blf1,
+                                 traffic_from_profile("blf_kernel.hip", "blf_kernel_rgb1024_pmc.md")),
+        "fft_passes": fft_passes(st1["fp32"], 1024, 1024, 3, 4),
+        "paper_context": {"value": 2.18, "unit": "MPix/s", "note": "Table I: 0.48 s per 1024x1024 RGB image, "
+                          "CPU Python with an approximate (bilateral-grid) filter, hardware unstated"}}
+    if "pool" in state:
+        pool = state["pool"]
+        job = pool.apply_async(oracle_channel_timed, ((state["f"][0].astype(np.float64), lam, ss, sr),))
+        ref, blf_s, solve_s, threads = job.get()
+        job1 = pool.apply_async(oracle_channel_timed, ((state["f1"][0].astype(np.float64), 20.0, 3.0, 0.1),))
+        ref1 = job1.get()[0]
+        pool.close()
+        pool.join()
+        for p in precs:
+            d = outs[p][0] - ref
+            per[p]["max_abs_vs_oracle_ch0"] = float(np.max(np.abs(d)))
+            per[p]["psnr_vs_oracle_ch0_db"] = round(_psnr(outs[p][0], ref), 2)
+        out["max_abs_vs_oracle"] = per["fp32"]["max_abs_vs_oracle_ch0"]
+        out["rgb1024"]["max_abs_vs_oracle_ch0"] = float(np.max(np.abs(outs1["fp32"][0] - ref1)))
+        t = blf_s + solve_s
+        out["cpu_baseline"] = {
+            "value": round(H * W / (C * t) / 1e6, 5), "unit": "MPix/s", "cores": threads, "kind": "oracle",
+            "sample": f"channel 0 of the 3840x2160 image: both fields filtered by the oracle's C loops of "
+                      f"Eq. (1) with {threads} OpenMP threads in {blf_s:.1f} s, the Eq. (8) solve by numpy.fft "
+                      f"(one thread) in {solve_s:.1f} s; rate for the 3-channel image on {cpu_model()}",
+            "blf_s": round(blf_s, 2), "solve_s": round(solve_s, 2)}
+    return out
+
+
+def run_rgb1024(args, torch, blfls, state=None):
     import synth
     H = W = 1024
     C = 3
@@ -168,9 +381,7 @@ def run_rgb1024(args, torch, blfls):
     taps = C * H * W * 2 * (2 * r + 1) ** 2
     achieved = taps / (blf_ms * 1e-3) / 1e12
     traffic = traffic_from_profile("blf_kernel.hip", "blf_kernel_rgb1024_pmc.md")
-    roofline = {"kernel": "blf_field_kernel<R=9>", "bound": "alu", "achieved": round(achieved, 4),
-                "peak": round(BLF_TAP_PEAK_T, 4), "unit": "Ttap/s", "frac": round(achieved / BLF_TAP_PEAK_T, 4),
-                "traffic": traffic, "launch_ms": round(blf_ms, 5), "taps_per_launch": taps}
+    roofline = blf_roofline("blf_field_kernel<R=9>", H, W, C, r, blf_ms, traffic)
     rf, cl, ri = fft_bytes(H, W, C, 4)
     fft = {}
     for name, nbytes in (("rows_fwd", rf), ("cols", cl), ("rows_inv", ri)):
@@ -233,7 +444,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     state = None
-    if args.workload not in ("rgb1024", "copy"):
+    if args.workload == "headline":
+        state = prepare_headline(args)
+    elif args.workload not in ("rgb1024", "copy"):
         # CPU inputs and oracle worker processes start before anything touches the GPU
         import bench_workloads
         state = bench_workloads.prepare(args)
@@ -243,7 +456,9 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     blfls.lib()  # fail loudly if the HIP library is missing
-    if args.workload == "rgb1024":
+    if args.workload == "headline":
+        out = run_headline(args, torch, blfls, state)
+    elif args.workload == "rgb1024":
         out = run_rgb1024(args, torch, blfls)
     else:
         import bench_workloads

@@ -203,7 +203,7 @@ def run_copy(args, torch, blfls, state=None):
 
 
 def run_uhd(args, torch, blfls, state):
-    from bench import time_plan, fft_bytes, BLF_TAP_PEAK_T
+    from bench import time_plan, fft_bytes, blf_roofline
     H, W, C, r = 2160, 3840, 3, 24
     prm = dict(lam=50.0, sigma_s=8.0, sigma_r=0.05)
     f = torch.from_numpy(state["f"]).cuda()
@@ -224,9 +224,9 @@ def run_uhd(args, torch, blfls, state):
             t = stages[name][0] / max(stages[name][1], 1)
             fft[name] = {"ms": round(t, 4), "GB/s": round(nbytes / (t * 1e-3) / 1e9, 1),
                          "frac": round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        ro = blf_roofline(f"blf_field_kernel<R={r}>", H, W, C, r, blf_ms, None)
         results[prec] = {"MPix/s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
-                         "blf_ms": round(blf_ms, 4), "blf_Ttap_s": round(taps / (blf_ms * 1e-3) / 1e12, 4),
-                         "blf_frac": round(taps / (blf_ms * 1e-3) / 1e12 / BLF_TAP_PEAK_T, 4),
+                         "blf_ms": round(blf_ms, 4), "blf_roofline": ro,
                          "fft_ms": round(fft_ms, 4),
                          "fft_GB/s": round((rf + cl + ri) / (fft_ms * 1e-3) / 1e9, 1),
                          "fft_frac": round((rf + cl + ri) / (fft_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -241,10 +241,7 @@ def run_uhd(args, torch, blfls, state):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "uhd: 3840x2160 RGB, lambda=50, sigma_s=8 (r=24), sigma_r=0.05, 1 iteration",
                       "H": H, "W": W, "C": C},
-           "roofline": {"kernel": "blf_field_kernel<R=24>", "bound": "alu",
-                        "achieved": results["fp32"]["blf_Ttap_s"], "peak": round(BLF_TAP_PEAK_T, 4), "unit": "Ttap/s",
-                        "frac": results["fp32"]["blf_frac"], "traffic": None,
-                        "launch_ms": results["fp32"]["blf_ms"], "taps_per_launch": C * H * W * 2 * (2 * r + 1) ** 2},
+           "roofline": results["fp32"]["blf_roofline"],
            "precisions": results}
     if ref is not None:
         refs = np.stack(ref)

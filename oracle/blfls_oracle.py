@@ -865,7 +865,8 @@ def _field_inv_span(p, q, sigma_r, normalize):
     return 1.0 / span if span > 0 else None
 
 
-def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iterations=3, amf_height=0):
+def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iterations=3, amf_height=0,
+                  engine="numpy"):
     if filt == "grid":
         # the bilateral-grid approximation in place of the exact filter
         return grid_filter(p, q, sigma_s, sigma_r, _field_inv_span(p, q, sigma_r, normalize))
@@ -881,17 +882,21 @@ def _filter_field(p, q, sigma_s, sigma_r, radius, normalize, filt="blf", nc_iter
         # the averaging.
         inv = _field_inv_span(p, q, sigma_r, normalize)
         return nc_filter(p, q, sigma_s, sigma_r, nc_iterations, inv)
+    blf = bilateral_filter
+    if engine == "c":
+        # the same definition as plain C loops (oracle/blf_oracle.c), for large images
+        from .c_blf import bilateral_filter_c as blf
     if not normalize:
-        return bilateral_filter(p, q, sigma_s, sigma_r, radius)
+        return blf(p, q, sigma_s, sigma_r, radius)
     # experiments section: fields taken to [0, 1], filtered, then mapped back
     pn, plo, pspan = _normalise_unit(p)
     qn = pn if q is None else _normalise_unit(q)[0]
-    return bilateral_filter(pn, qn, sigma_s, sigma_r, radius) * pspan + plo
+    return blf(pn, qn, sigma_s, sigma_r, radius) * pspan + plo
 
 
 def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None,
                    normalize=False, sigma_guide=0.0, return_fields=False, filter="blf", nc_iterations=3,
-                   amf_height=0, detail_gain=0.0):
+                   amf_height=0, detail_gain=0.0, engine="numpy"):
     """BLF-LS on one channel (Section III-A two-step procedure, Section III-D extensions).
 
     Step 1 filters p_x, p_y with Eq. (1) (``filter="nc"``: the NC filter of the domain
@@ -899,6 +904,8 @@ def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None
     ``filter="amf"``: the adaptive-manifold filter, AMF-LS); step 2 solves Eq. (8).  ``guide`` switches to joint filtering;
     ``iterations`` > 1 is rolling guidance.  ``detail_gain`` m != 0 returns the detail-enhanced
     u + m (f - u) of the experiments section (the detail layer f - u boosted m times).
+    ``engine="c"`` evaluates Eq. (1) with the C loops of ``blf_oracle.c`` (same definition,
+    for images where the NumPy loops take minutes).
     """
     f = np.asarray(f, dtype=np.float64)
     f_in = f
@@ -926,8 +933,8 @@ def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None
             qx = qy = None
         else:
             qx, qy = grad_x(prev), grad_y(prev)
-        gx = _filter_field(px, qx, sigma_s, sigma_r, r, normalize, filter, nc_iterations, amf_height)
-        gy = _filter_field(py, qy, sigma_s, sigma_r, r, normalize, filter, nc_iterations, amf_height)
+        gx = _filter_field(px, qx, sigma_s, sigma_r, r, normalize, filter, nc_iterations, amf_height, engine)
+        gy = _filter_field(py, qy, sigma_s, sigma_r, r, normalize, filter, nc_iterations, amf_height, engine)
         u = blfls_solve(f, gx, gy, lam)
         prev = u
     out = u * span + lo
@@ -939,21 +946,21 @@ def smooth_channel(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None
 
 
 def smooth(f, lam, sigma_s, sigma_r, radius=-1, iterations=1, guide=None, normalize=False,
-           sigma_guide=0.0, filter="blf", nc_iterations=3, amf_height=0, detail_gain=0.0):
+           sigma_guide=0.0, filter="blf", nc_iterations=3, amf_height=0, detail_gain=0.0, engine="numpy"):
     """BLF-LS (or NC-LS, grid BLF-LS, AMF-LS with ``filter="nc"``, ``"grid"``, ``"amf"``) on a
     (H, W) or (C, H, W) image; channels are independent."""
     f = np.asarray(f, dtype=np.float64)
     if f.ndim == 2:
         return smooth_channel(f, lam, sigma_s, sigma_r, radius, iterations, guide, normalize,
                               sigma_guide, filter=filter, nc_iterations=nc_iterations,
-                              amf_height=amf_height, detail_gain=detail_gain)
+                              amf_height=amf_height, detail_gain=detail_gain, engine=engine)
     g = None if guide is None else np.asarray(guide, dtype=np.float64)
     outs = []
     for c in range(f.shape[0]):
         gc = None if g is None else (g[c] if g.ndim == 3 else g)
         outs.append(smooth_channel(f[c], lam, sigma_s, sigma_r, radius, iterations, gc,
                                    normalize, sigma_guide, filter=filter, nc_iterations=nc_iterations,
-                                   amf_height=amf_height, detail_gain=detail_gain))
+                                   amf_height=amf_height, detail_gain=detail_gain, engine=engine))
     return np.stack(outs)
 
 

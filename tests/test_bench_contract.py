@@ -47,11 +47,49 @@ def test_fft_pass_bytes():
         assert ri == spec + 2 * C * H * W * 4
 
 
-def test_tap_peak_and_count():
-    # 256 CUs x 4 SIMDs x 2.4 GHz x 64 lanes / 18 cycles per wave64 tap
-    assert abs(bench.BLF_TAP_PEAK_T - 8.7381) < 1e-3
-    # one tap = one weight of Eq. (1) for one output of one field; r = 9 at the default workload
+def test_filter_roofline_against_the_published_fp32_peak():
+    # one tap = one weight of Eq. (1) for one output of one field: 6 flops (difference,
+    # exponent FMA, weighted-value FMA, weight sum) against 157.3 TFLOP/s
+    assert bench.FP32_PEAK_TFLOPS == 157.3 and bench.BLF_FLOPS_PER_TAP == 6
+    ro = bench.blf_roofline("k", 2160, 3840, 3, 24, 10.0, None)
+    taps = 3 * 2160 * 3840 * 2 * 49 ** 2
+    assert ro["taps_per_launch"] == taps
+    assert abs(ro["achieved"] - taps * 6 / 1e-2 / 1e12) < 1e-3
+    assert abs(ro["frac"] - ro["achieved"] / 157.3) < 1e-4 and ro["unit"] == "TFLOP/s" and ro["bound"] == "alu"
+    # exponentials: a wave64 v_exp_f32 per 8 SIMD cycles, 256 CUs x 4 SIMDs at 2.4 GHz
+    assert abs(bench.EXP_PEAK_T - 19.6608) < 1e-3
     assert 3 * 1024 * 1024 * 2 * 19 ** 2 == 2271215616
+
+
+def test_interleaved_rounds_time_every_graph_exactly_steps_times():
+    class G:
+        def __init__(self):
+            self.n = 0
+
+        def replay(self):
+            self.n += 1
+
+    class Ev:
+        def record(self):
+            pass
+
+        def elapsed_time(self, other):
+            return 1.0
+
+    class Cuda:
+        Event = staticmethod(lambda enable_timing=True: Ev())
+
+        @staticmethod
+        def synchronize():
+            pass
+
+    class T:
+        cuda = Cuda
+
+    for steps in (1, 3, 7, 20):
+        gs = {"a": G(), "b": G(), "c": G()}
+        bench.time_interleaved(gs, steps, 2, T)
+        assert all(g.n == steps + 2 for g in gs.values()), steps
 
 
 def test_amf_byte_model_tree_height_matches_the_oracle():

@@ -473,3 +473,26 @@ def test_nc_decision_margin_by_loops():
                             if dist > rad:
                                 break
     assert abs(oracle.nc_decision_margin(q, ss, sr, 3) - best) < 1e-12
+
+
+@pytest.mark.parametrize("H,W,r,sr,joint", [(5, 7, 2, 0.3, False), (4, 6, 5, 0.2, True), (3, 3, 4, math.inf, False),
+                                            (6, 5, 1, 0.05, True)])
+def test_c_blf_matches_pixel_loops(H, W, r, sr, joint):
+    """The C loops of Eq. (1) (oracle/blf_oracle.c) against the Python pixel loops,
+    windows wider than the image included."""
+    from oracle.c_blf import bilateral_filter_c
+    rng = np.random.default_rng(H * W + r)
+    p = rng.random((H, W))
+    q = rng.random((H, W)) if joint else None
+    a = bilateral_filter_c(p, q, 1.3, sr, r)
+    b = oracle.bilateral_filter_bruteforce(p, q, 1.3, sr, r)
+    assert np.max(np.abs(a - b)) < 1e-14
+
+
+def test_c_engine_gives_the_numpy_result():
+    f = voronoi_image(40, 52, 12)
+    g = voronoi_image(40, 52, 13)
+    for kw in (dict(), dict(guide=g), dict(iterations=2, sigma_guide=1.0), dict(normalize=True)):
+        a = oracle.smooth(f, 30.0, 2.0, 0.08, engine="c", **kw)
+        b = oracle.smooth(f, 30.0, 2.0, 0.08, **kw)
+        assert np.max(np.abs(a - b)) < 1e-13, kw
