@@ -187,6 +187,25 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params *params, const f
                           const float *guide, float *u, int64_t pitch, void *workspace,
                           void *stream);
 
+/* Static device scratch of blfls_smooth_noalloc, per GPU (128 MiB: the
+ * workspace of a 1024 x 1024 RGB plan in FP32 for every filter but the AMF). */
+#define BLFLS_NOALLOC_SCRATCH_BYTES (128u << 20)
+
+/* blfls_smooth without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the workspace is a static array of the library, one
+ * per GPU, of BLFLS_NOALLOC_SCRATCH_BYTES, held from the library's load on
+ * that GPU until the process ends.  The call allocates nothing (no hipMalloc,
+ * no hipFree); its device address is looked up once per GPU, on the first call
+ * with that GPU current.  Arguments, results and errors as blfls_smooth, plus
+ * BLFLS_E_NOMEM when blfls_workspace_size(plan, params) exceeds the scratch.
+ * Every call on one GPU uses the same scratch: calls that overlap on a GPU
+ * (queued on different streams, or from several threads, without ordering
+ * between them) race and give wrong results; calls on one stream are ordered
+ * and safe.  The scratch's contents between calls are not part of the result. */
+blfls_status blfls_smooth_noalloc(blfls_plan_t plan, const blfls_params *params, const float *f,
+                                  const float *guide, float *u, int64_t pitch, void *stream);
+
 /* HDR tone mapping in the log domain (experiments section: the framework of
  * Durand and Dorsey 2002 with BLF-LS as the base/detail decomposition).
  *   I = max((20 R + 40 G + B) / 61, 1e-6), L = log10 I,

@@ -110,6 +110,8 @@ SIGNATURES = [
     ("blfls_smooth", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                     ctypes.c_void_p]),
+    ("blfls_smooth_noalloc", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     ("blfls_server_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_size_t,
                                            ctypes.c_int32, ctypes.c_int32, ctypes.c_int, ctypes.c_void_p]),
     ("blfls_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -264,6 +266,26 @@ class Plan:
                                   ctypes.c_void_p(u.data_ptr()), self.W, ctypes.c_void_p(self.workspace_ptr),
                                   ctypes.c_void_p(_stream_handle(stream))))
         return u.reshape(f.shape)
+
+    def smooth_noalloc(self, f, lam: float, sigma_s: float, sigma_r: float, out, radius: int = -1,
+                       iterations: int = 1, guide=None, normalize: bool = False, sigma_guide: float = 0.0,
+                       stream=None, filter: str = "blf", filter_iterations: int = 0, detail_gain: float = 0.0):
+        """``blfls_smooth_noalloc``: the same smoothing into the caller's ``out`` with the
+        library's static per-GPU scratch as workspace (no device allocation by the library
+        or by this call; calls that overlap on one GPU race)."""
+        shape = (self.C, self.H, self.W)
+        f3 = _checked_image(f, "f", shape, self.device)
+        g3 = None if guide is None else _checked_image(guide, "guide", shape, self.device)
+        if out is None:
+            raise ValueError("out is required (the call allocates nothing)")
+        u = _new_or_checked_out(out, f3, shape, self.device)
+        prm = make_params(lam, sigma_s, sigma_r, radius, iterations, normalize, sigma_guide, filter,
+                          filter_iterations, detail_gain)
+        _check(lib().blfls_smooth_noalloc(self._handle, ctypes.byref(prm), ctypes.c_void_p(f3.data_ptr()),
+                                          ctypes.c_void_p(g3.data_ptr() if g3 is not None else 0),
+                                          ctypes.c_void_p(u.data_ptr()), self.W,
+                                          ctypes.c_void_p(_stream_handle(stream))))
+        return out
 
     def close(self):
         if getattr(self, "_handle", None) is not None and self._handle.value:

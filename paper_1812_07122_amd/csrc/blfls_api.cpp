@@ -806,3 +806,66 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the workspace is a static device array of the
+// library, so a call makes no device allocation at all.
+// ---------------------------------------------------------------------------
+
+// One copy per GPU, held from the module's load on that GPU until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the device
+// memory: only the address hipGetSymbolAddress returns for the current device
+// may be passed to kernels.
+static __device__ __align__(256) unsigned char scratch[BLFLS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device ordinal, nullptr until looked up
+}  // namespace
+
+// The device address of `scratch` on device `dev` (which must be current),
+// looked up on the first call for that device.
+static blfls_status scratch_for_device(int dev, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0) return set_error(BLFLS_E_INVALID, "no current device");
+  if (g_scratch_ptr.size() <= static_cast<size_t>(dev)) g_scratch_ptr.resize(dev + 1, nullptr);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+    if (ptr == nullptr || reinterpret_cast<uintptr_t>(ptr) % 256 != 0)
+      return set_error(BLFLS_E_HIP, "static scratch has no aligned device address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return BLFLS_OK;
+}
+
+extern "C" {
+
+blfls_status blfls_smooth_noalloc(blfls_plan_t plan, const blfls_params* params, const float* f,
+                                  const float* guide, float* u, int64_t pitch, void* stream) {
+  g_last_error.clear();
+  if (plan == nullptr) return set_error(BLFLS_E_INVALID, "plan is NULL");
+  if (params == nullptr) return set_error(BLFLS_E_INVALID, "params is NULL");
+  int radius = 0;
+  blfls_status st = check_params(params, &radius);
+  if (st != BLFLS_OK) return st;
+  const size_t need = request_workspace_bytes(plan, *params);
+  if (need > BLFLS_NOALLOC_SCRATCH_BYTES)
+    return set_error(BLFLS_E_NOMEM, "workspace of " + std::to_string(need) +
+                                        " bytes exceeds the static scratch of BLFLS_NOALLOC_SCRATCH_BYTES (" +
+                                        std::to_string(static_cast<size_t>(BLFLS_NOALLOC_SCRATCH_BYTES)) +
+                                        "); use blfls_smooth with a caller workspace");
+  int dev = -1;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  void* ws = nullptr;
+  st = scratch_for_device(dev, &ws);
+  if (st != BLFLS_OK) return st;
+  // the workspace's contents on entry are ignored by every kernel of the call:
+  // nothing in it needs clearing
+  return blfls_smooth(plan, params, f, guide, u, pitch, ws, stream);
+}
+
+}  // extern "C"
