@@ -53,7 +53,12 @@ typedef enum {
 
 /* Storage precision of the two intermediate gradient-residual fields.  The
  * filter weights, its accumulation, the FFTs and the spectral divide run in
- * FP32 in every mode; FP64 is used only for the host-built tables. */
+ * FP32 in every mode; FP64 is used only for the host-built tables.  FP16
+ * fields are stored times a power of two per field: a residual is bounded by
+ * the span of its gradient field (the filters output weighted means), and a
+ * field whose span exceeds 2^15 is scaled to a span of at most 2^15 (an extra
+ * pass reads the image's gradient extrema first), so images of any range stay
+ * finite; spans up to 2^15 (e.g. 8- and 15-bit data) are stored unscaled. */
 typedef enum {
   BLFLS_FP32 = 0,
   BLFLS_MIXED_BF16 = 1,

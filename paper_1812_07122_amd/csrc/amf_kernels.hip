@@ -349,7 +349,7 @@ __global__ void __launch_bounds__(kThreads) amf_cols_kernel(AmfGeom G) {
             if (G.last) {
               const float pv = grad_at(P.f, P.pitch, H, W, i, j, P.field);
               const float r = den > 0.0f ? amax * (num / den - pv) : 0.0f;
-              store_field(P.out, static_cast<int64_t>(i) * W + j, r, G.ft);
+              store_field(P.out, static_cast<int64_t>(i) * W + j, r * G.inv[G.P + p], G.ft);
             } else {
               G.acc[idx] = num;
               G.acc[PN + idx] = den;
@@ -424,7 +424,8 @@ __global__ void __launch_bounds__(kThreads) amf_carry_kernel(AmfGeom G) {
   }
 }
 
-// Range scale of each field: 1/span of its range source with the normalise flag.
+// Range scale of each field: 1/span of its range source with the normalise
+// flag; and its FP16 store scale (1 for FP32 and BF16 fields).
 __global__ void __launch_bounds__(64) amf_prep_kernel(AmfGeom G) {
   const AmfPlane& P = G.planes[blockIdx.x];
   float inv = 1.0f;
@@ -432,7 +433,11 @@ __global__ void __launch_bounds__(64) amf_prep_kernel(AmfGeom G) {
     const float span = field_span(P.minmax, P.field);
     if (span > 0.0f) inv = __fdiv_rn(1.0f, span);
   }
-  if (threadIdx.x == 0) G.inv[blockIdx.x] = inv;
+  const float2 fsc = field_store_scales(P.fmm);
+  if (threadIdx.x == 0) {
+    G.inv[blockIdx.x] = inv;
+    G.inv[G.P + blockIdx.x] = P.field ? fsc.y : fsc.x;
+  }
 }
 
 namespace {

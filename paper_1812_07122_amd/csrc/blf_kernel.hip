@@ -79,6 +79,9 @@ __device__ __forceinline__ void blf_item(const BlfPlane* __restrict__ planes, in
     const float span = field_span(P.minmax, field);
     if (span > 0.0f) c = c / span;
   }
+  // FP16 fields: the residual's power-of-two store scale (1 otherwise)
+  const float2 fsc = field_store_scales(P.fmm);
+  const float ssc = field ? fsc.y : fsc.x;
 
   // circular index maps of the halo tile (one extra row/column for the differences)
   for (int a = tid; a < LH + 1; a += T) rowmap[a] = wrap_index(y0 - R + a, H);
@@ -192,7 +195,7 @@ __device__ __forceinline__ void blf_item(const BlfPlane* __restrict__ planes, in
       if (y < H) {
         // the centre tap has weight exactly 1, so acc_d >= 1
         const float res = JOINT ? acc_n[k] / acc_d[k] - ps[k] : acc_n[k] / (c * acc_d[k]);
-        store_field(out, static_cast<int64_t>(y) * W + x, res, field_type);
+        store_field(out, static_cast<int64_t>(y) * W + x, res * ssc, field_type);
       }
     }
   }

@@ -141,7 +141,7 @@ AmfLayout amf_layout(const blfls_plan_s* plan, int height) {
   L.sum = take(5 * line);
   L.carry_f = take(4 * line);
   L.carry_b = take(4 * line);
-  L.inv = take(P);
+  L.inv = take(2 * P);   // range scales, then FP16 store scales
   L.floats = w;
   return L;
 }
@@ -318,6 +318,8 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   size_t w = 0;
   p->off_desc = w; w = align_up(w + kDescBytes, 256);
   p->off_partial = w; w = align_up(w + static_cast<size_t>(C) * kMinmaxBlocks * 4 * sizeof(float), 256);
+  // FP16 fields: extrema partials of the image's own gradients (the fields' store scales)
+  p->off_fpartial = w; w = align_up(w + static_cast<size_t>(C) * kMinmaxBlocks * 4 * sizeof(float), 256);
   p->off_rx = w; w = align_up(w + C * plane * p->field_elem, 256);
   p->off_ry = w; w = align_up(w + C * plane * p->field_elem, 256);
   p->off_spec = w; w = align_up(w + static_cast<size_t>(C) * (M + 1) * H * sizeof(float2), 256);
@@ -378,6 +380,8 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
   out->blf_next.assign(C, BlfPlane{});
   out->mm_first.assign(C, AuxPlane{});
   out->mm_next.assign(C, AuxPlane{});
+  out->mm_f.assign(C, AuxPlane{});
+  out->fp16_scale = plan->precision == BLFLS_MIXED_FP16;
   out->gauss.assign(C, AuxPlane{});
   out->fft.assign(C, FftPlane{});
   out->grid_first.assign(C, GridPlane{});
@@ -395,6 +399,7 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
   float* gauss_base = reinterpret_cast<float*>(wsb + plan->off_gauss);
   float* tmp_base = reinterpret_cast<float*>(wsb + plan->off_tmp);
   float* partial_base = reinterpret_cast<float*>(wsb + plan->off_partial);
+  float* fpartial_base = reinterpret_cast<float*>(wsb + plan->off_fpartial);
   for (int ch = 0; ch < C; ++ch) {
     const float* fc = f + static_cast<int64_t>(ch) * H * pitch;
     const float* gc = guide ? guide + static_cast<int64_t>(ch) * H * pitch : nullptr;
@@ -422,6 +427,10 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
     AuxPlane& A2 = out->mm_next[ch];
     A2 = AuxPlane{};
     A2.src = uc; A2.partial = partial; A2.pitch = pitch; A2.H = H; A2.W = W;
+    float* fpartial = out->fp16_scale ? fpartial_base + static_cast<size_t>(ch) * kMinmaxBlocks * 4 : nullptr;
+    AuxPlane& AF = out->mm_f[ch];
+    AF = AuxPlane{};
+    AF.src = fc; AF.partial = fpartial; AF.pitch = pitch; AF.H = H; AF.W = W;
 
     for (int it = 0; it < 2; ++it) {
       BlfPlane& B = it == 0 ? out->blf_first[ch] : out->blf_next[ch];
@@ -437,6 +446,7 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
       B.cx = B.cy = c;
       B.spatial = spatial;
       B.minmax = out->normalize ? partial : nullptr;
+      B.fmm = fpartial;
       if (it == 0) {
         // joint when a guide (or its Gaussian-smoothed copy) is the range
         // source, and when the range kernel is off (q = 0: spatial weights only)
@@ -460,6 +470,7 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
       N.rx = rx;
       N.ry = ry;
       N.minmax = B.minmax;
+      N.fmm = fpartial;
       N.H = H; N.W = W;
       N.a = range_on ? static_cast<float>(static_cast<double>(prm.sigma_s) / static_cast<double>(prm.sigma_r)) : 0.0f;
       N.rcount = nc_row_items(H, W);
@@ -487,6 +498,7 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
       G2.sigma_r = range_on ? prm.sigma_r : 0.0f;
       G2.sig_xy = static_cast<float>(static_cast<double>(prm.sigma_s) / sc);
       G2.normalize = (prm.flags & BLFLS_F_NORMALIZE) != 0 ? 1 : 0;
+      G2.fmm = fpartial;
     }
     for (int it = 0; it < 2; ++it) {
       const BlfPlane& B = it == 0 ? out->blf_first[ch] : out->blf_next[ch];
@@ -499,6 +511,7 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
         A.out = field ? ry : rx;
         A.minmax = B.minmax;
         A.field = field;
+        A.fmm = fpartial;
       }
     }
     FftPlane& F = out->fft[ch];
@@ -517,6 +530,7 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
     F.h_div = make_fastdiv(static_cast<uint32_t>(H));
     F.rb_div = make_fastdiv(static_cast<uint32_t>(plan->rb));
     F.gain = 1.0f;
+    F.fmm = fpartial;
   }
   out->fft_last = out->fft;
   for (FftPlane& F : out->fft_last) F.gain = static_cast<float>(1.0 - static_cast<double>(prm.detail_gain));
@@ -551,6 +565,12 @@ hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, cons
   const int items = 2 * plan->tiles_x * plan->tiles_y * C;
   const int ft = plan->precision == BLFLS_FP32 ? kF32 : plan->precision == BLFLS_MIXED_BF16 ? kBF16 : kF16;
   hipError_t e;
+  if (rd.fp16_scale) {
+    // FP16 fields: the image's gradient extrema, which set the fields' store scales
+    StageTimer t(BLFLS_STAGE_MINMAX, s);
+    e = launch_minmax(dev.mm_f, C, s);
+    if (e != hipSuccess) return e;
+  }
   if (rd.smooth_guide) {
     StageTimer t(BLFLS_STAGE_GAUSS, s);
     e = launch_gauss(dev.gauss, C, static_cast<int64_t>(plan->H) * plan->W, s);
@@ -761,6 +781,7 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   const size_t o_b2 = place(rd.blf_next.data(), C * sizeof(BlfPlane));
   const size_t o_m1 = place(rd.mm_first.data(), C * sizeof(AuxPlane));
   const size_t o_m2 = place(rd.mm_next.data(), C * sizeof(AuxPlane));
+  const size_t o_mf = place(rd.mm_f.data(), C * sizeof(AuxPlane));
   const size_t o_g = place(rd.gauss.data(), C * sizeof(AuxPlane));
   const size_t o_f = place(rd.fft.data(), C * sizeof(FftPlane));
   const size_t o_fl = params->detail_gain != 0.0f ? place(rd.fft_last.data(), C * sizeof(FftPlane)) : o_f;
@@ -787,6 +808,7 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params* params, const f
   dd.blf_next = reinterpret_cast<const BlfPlane*>(dbase + o_b2);
   dd.mm_first = reinterpret_cast<const AuxPlane*>(dbase + o_m1);
   dd.mm_next = reinterpret_cast<const AuxPlane*>(dbase + o_m2);
+  dd.mm_f = reinterpret_cast<const AuxPlane*>(dbase + o_mf);
   dd.gauss = reinterpret_cast<const AuxPlane*>(dbase + o_g);
   dd.fft = reinterpret_cast<const FftPlane*>(dbase + o_f);
   dd.fft_last = reinterpret_cast<const FftPlane*>(dbase + o_fl);

@@ -56,6 +56,47 @@ __device__ inline void field_extrema(const float* partial, int field, float* lo_
   *hi_out = red[1];
 }
 
+// FP16 storage of the residual fields r = filter(p) - p.  Every filter's output
+// is a weighted mean of the field p, so |r| <= max p - min p; a field whose span
+// exceeds 2^15 is stored times 2^-e, e the smallest exponent that brings the span
+// to at most 2^15 (below the FP16 maximum 65504), and the right-hand side of the
+// solve multiplies it back (exact: powers of two).  Spans up to 2^15 (images in
+// [0, 1], 8-bit or 15-bit data) keep scale 1.
+__device__ inline float store_scale_of_span(float span) {
+  if (!(span > 32768.0f)) return 1.0f;
+  int k = 0;
+  (void)frexpf(span, &k);          // span = m 2^k, 0.5 <= m < 1
+  return ldexpf(1.0f, 15 - k);     // span 2^(15 - k) < 2^15
+}
+
+// Store scales of both fields from the image's gradient extrema partials fmm
+// (nullptr: no scaling).  Block-wide call: every thread of the workgroup must
+// reach it; it has its own LDS word pair, so it may follow field_extrema.
+__device__ inline float2 field_store_scales(const float* fmm) {
+  __shared__ float2 sc;
+  if (fmm == nullptr) return make_float2(1.0f, 1.0f);
+  __syncthreads();   // an earlier call's readers are done with sc
+  if (threadIdx.x < 64) {
+    float lo0 = INFINITY, hi0 = -INFINITY, lo1 = INFINITY, hi1 = -INFINITY;
+    for (int i = threadIdx.x; i < kMinmaxBlocks; i += 64) {
+      lo0 = fminf(lo0, fmm[i * 4 + 0]);
+      hi0 = fmaxf(hi0, fmm[i * 4 + 1]);
+      lo1 = fminf(lo1, fmm[i * 4 + 2]);
+      hi1 = fmaxf(hi1, fmm[i * 4 + 3]);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      lo0 = fminf(lo0, __shfl_xor(lo0, off));
+      hi0 = fmaxf(hi0, __shfl_xor(hi0, off));
+      lo1 = fminf(lo1, __shfl_xor(lo1, off));
+      hi1 = fmaxf(hi1, __shfl_xor(hi1, off));
+    }
+    if (threadIdx.x == 0) sc = make_float2(store_scale_of_span(hi0 - lo0), store_scale_of_span(hi1 - lo1));
+  }
+  __syncthreads();
+  return sc;
+}
+
 // max - min of the range source field (block-wide call).
 __device__ inline float field_span(const float* partial, int field) {
   float lo, hi;

@@ -65,6 +65,7 @@ struct BlfPlane {
   int tile_count;        // tiles_x * tiles_y
   float cx, cy;          // range scales sqrt(log2(e) / (2 sigma_r^2)) per field; 0 = range off
   const float* spatial;  // RequestTables::sy then ::ex of the request
+  const float* fmm;      // FP16 fields: the image's gradient extrema partials (store scale), else nullptr
 };
 
 // Per-request tables built in FP64 on the host and rounded to FP32.
@@ -102,6 +103,7 @@ struct FftPlane {
   FastDiv m_div;         // division by W/2
   FastDiv h_div;         // division by H
   FastDiv rb_div;        // division by rb
+  const float* fmm;      // FP16 fields: the image's gradient extrema partials (store scale), else nullptr
 };
 
 // One channel plane for the NC filter passes (NC-LS, Section III-D): both
@@ -123,6 +125,7 @@ struct NcPlane {
   int rbegin, rcount;    // items of the row passes: 2 fields x ceil(H/4) x ceil(W/64)
   int cbegin, ccount;    // items of the column passes: 2 fields x ceil(H/64) x ceil(W/64)
   int pad_;
+  const float* fmm;      // FP16 fields: the image's gradient extrema partials (store scale), else nullptr
 };
 
 // One gradient field of one channel for the adaptive-manifold filter.
@@ -137,6 +140,7 @@ struct AmfPlane {
   const float* minmax;   // range-source gradient extrema partials (normalise flag) or nullptr
   int field;             // 0: x, 1: y
   int pad_;
+  const float* fmm;      // FP16 fields: the image's gradient extrema partials (store scale), else nullptr
 };
 
 // One launch's view of the adaptive-manifold workspace (passed by value).
@@ -155,7 +159,8 @@ struct AmfGeom {
   float* sum;            // [P][S][5][W] segment summaries of a column scan
   float* carry_f;        // [P][S][4][W] carries into each segment, top to bottom
   float* carry_b;        // [P][S][4][W] and bottom to top
-  float* inv;            // [P] range scale of each field (1/span with the normalise flag, else 1)
+  float* inv;            // [2P] range scale of each field (1/span with the normalise flag, else 1),
+                         // then each field's FP16 store scale (1 for FP32 and BF16)
   int ft;                // residual field type
   int first, last;       // this slice starts / completes the sums
 };
@@ -181,6 +186,7 @@ struct GridPlane {
   float sigma_r;         // sigma_r (FP32): the range blur is sigma_r * inv cells wide
   float sig_xy;          // sigma_s / s: the spatial blur width in cells
   int normalize;         // divide the range scale by the field's span
+  const float* fmm;      // FP16 fields: the image's gradient extrema partials (store scale), else nullptr
 };
 
 // Minmax (normalise flag) and Gaussian-guide descriptors.

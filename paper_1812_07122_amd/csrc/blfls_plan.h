@@ -33,7 +33,7 @@ struct blfls_plan_s {
   int tiles_x = 0, tiles_y = 0;
   // workspace layout (bytes from the workspace base)
   size_t field_elem = 4;
-  size_t off_desc = 0, off_partial = 0, off_rx = 0, off_ry = 0, off_spec = 0, off_gauss = 0, off_tmp = 0, off_nc = 0;
+  size_t off_desc = 0, off_partial = 0, off_fpartial = 0, off_rx = 0, off_ry = 0, off_spec = 0, off_gauss = 0, off_tmp = 0, off_nc = 0;
   size_t ws_bytes = 0;
 };
 
@@ -73,6 +73,7 @@ struct RequestDesc {
   std::vector<BlfPlane> blf_next;    // iterations 2..n (range source = previous output)
   std::vector<AuxPlane> mm_first;    // normalise: extrema of iteration 1's range source
   std::vector<AuxPlane> mm_next;
+  std::vector<AuxPlane> mm_f;        // FP16 fields: extrema of the image's own gradients (store scales)
   std::vector<AuxPlane> gauss;       // guide smoothing
   std::vector<FftPlane> fft;
   std::vector<FftPlane> fft_last;    // the last iteration's (detail gain folded in)
@@ -94,6 +95,7 @@ struct RequestDesc {
   int iterations = 1;
   bool normalize = false;
   bool smooth_guide = false;
+  bool fp16_scale = false;           // FP16 fields: the image's gradient extrema set the store scales
 };
 
 // Build the descriptors of one request whose workspace starts at `ws`; the
@@ -111,6 +113,7 @@ struct DeviceDesc {
   const BlfPlane* blf_next = nullptr;
   const AuxPlane* mm_first = nullptr;
   const AuxPlane* mm_next = nullptr;
+  const AuxPlane* mm_f = nullptr;
   const AuxPlane* gauss = nullptr;
   const FftPlane* fft = nullptr;
   const FftPlane* fft_last = nullptr;

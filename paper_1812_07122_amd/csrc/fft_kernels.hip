@@ -22,6 +22,7 @@
 // arithmetic uses precomputed multiply-shift division; consecutive row blocks
 // are placed on the same XCD so partial lines of the transposed spectrum meet
 // in one L2.
+#include "blfls_field.h"
 #include "blfls_internal.h"
 #include "blfls_launch.h"
 #include "blfls_work.h"
@@ -347,6 +348,8 @@ constexpr int kLoadBatch = 8;
 
 // Right-hand side of the residual-form solve for row i0 + b, two reals per
 // complex: c(i, j) = lam ((r_x(i, j-1) - r_x(i, j)) + (r_y(i-1, j) - r_y(i, j))).
+// FP16 fields hold r_x s_x and r_y s_y (powers of two, see field_store_scales):
+// then lam is lambda / s_x and ky = s_x / s_y.
 template <int FT>
 struct RhsSrc {
   static constexpr bool kLds = false;
@@ -354,6 +357,7 @@ struct RhsSrc {
   const void* ry;
   int i0, H, W;
   float lam;
+  float ky;
   __device__ __forceinline__ float2 load(int b, int n) const {
     const int i = i0 + b;
     const int im1 = i == 0 ? H - 1 : i - 1;
@@ -364,6 +368,8 @@ struct RhsSrc {
     const float2 y = load_pair<FT>(ry, ri + j0);
     const float2 yp = load_pair<FT>(ry, imul(im1, W) + j0);
     const float xm = load_one<FT>(rx, ri + jm);
+    if (FT == kF16)
+      return make_float2(lam * ((xm - x.x) + ky * (yp.x - y.x)), lam * ((x.x - x.y) + ky * (yp.y - y.y)));
     return make_float2(lam * ((xm - x.x) + (yp.x - y.x)), lam * ((x.x - x.y) + (yp.y - y.y)));
   }
 };
@@ -547,7 +553,7 @@ __device__ __forceinline__ void wave_fft_inv(float2 (&d)[L / 8][8], float2 (&a)[
 // through LDS so each spectrum column receives kWaveCols consecutive values.
 // LDS: kWaveCols exchange blocks of W/2 values, then [W/2 + 1][kWaveCols + 1].
 template <int L, int FT>
-__device__ __forceinline__ void rows_fwd_wave_item(const FftPlane& P, int blk, float2* smem) {
+__device__ __forceinline__ void rows_fwd_wave_item(const FftPlane& P, int blk, float2* smem, float lam, float ky) {
   constexpr int kS = kWaveCols + 1;   // staging row stride (one spare slot against bank conflicts)
   const int H = P.H, W = P.W, M = W >> 1;
   const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -573,7 +579,10 @@ __device__ __forceinline__ void rows_fwd_wave_item(const FftPlane& P, int blk, f
       const float left = __shfl_up(x.y, 1);
       const float xm = l == 0 ? carry : left;
       carry = __shfl(x.y, 63);
-      a[m] = make_float2(P.lambda * ((xm - x.x) + (yp.x - y.x)), P.lambda * ((x.x - x.y) + (yp.y - y.y)));
+      if (FT == kF16)
+        a[m] = make_float2(lam * ((xm - x.x) + ky * (yp.x - y.x)), lam * ((x.x - x.y) + ky * (yp.y - y.y)));
+      else
+        a[m] = make_float2(lam * ((xm - x.x) + (yp.x - y.x)), lam * ((x.x - x.y) + (yp.y - y.y)));
     }
     wave_fft_fwd<L>(a, d, T, l, P.twM);
     wave_lds_sync();
@@ -624,12 +633,19 @@ __device__ __forceinline__ void rows_fwd_item(const FftPlane* __restrict__ plane
   const FftPlane& P = planes[find_fft_plane<false>(planes, nplanes, item)];
   const int blk = item - P.row_begin;
   if (blk >= P.row_count) return;
+  // FP16 fields: undo the fields' power-of-two store scales in the right-hand side
+  float lam = P.lambda, ky = 1.0f;
+  if (FT == kF16) {
+    const float2 fsc = field_store_scales(P.fmm);
+    lam = P.lambda / fsc.x;
+    ky = fsc.x / fsc.y;
+  }
   if (WAVE && P.roww == 8) {
-    rows_fwd_wave_item<8, FT>(P, blk, smem);
+    rows_fwd_wave_item<8, FT>(P, blk, smem, lam, ky);
     return;
   }
   if (WAVE && P.roww == 16) {
-    rows_fwd_wave_item<16, FT>(P, blk, smem);
+    rows_fwd_wave_item<16, FT>(P, blk, smem, lam, ky);
     return;
   }
   const int H = P.H, W = P.W, M = W >> 1;
@@ -644,7 +660,7 @@ __device__ __forceinline__ void rows_fwd_item(const FftPlane* __restrict__ plane
   __syncthreads();
   // the first stage forms the right-hand side straight from the residual fields
   const LdsIO lds{buf, M};
-  fft_run<T, kFftLdsComplex>(*P.szM, twS, -1.0f, nrows, RhsSrc<FT>{P.rx, P.ry, i0, H, W, P.lambda}, lds, lds);
+  fft_run<T, kFftLdsComplex>(*P.szM, twS, -1.0f, nrows, RhsSrc<FT>{P.rx, P.ry, i0, H, W, lam, ky}, lds, lds);
 
   // split step: X[k] = E[k] + exp(-2 pi i k/W) O[k], k = 0..M, Z[M] = Z[0]
   float2* spec = P.spec;

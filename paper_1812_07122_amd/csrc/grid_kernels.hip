@@ -111,6 +111,9 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
   // range axis: origin, scale (capped to kGridZMax bins), bins in use, blur width
   float qmin, qmax;
   field_extrema(P.minmax, field, &qmin, &qmax);
+  // FP16 fields: the residual's power-of-two store scale (1 otherwise)
+  const float2 fsc = field_store_scales(P.fmm);
+  const float ssc = field ? fsc.y : fsc.x;
   const float span = qmax - qmin;
   float inv = P.inv_r;
   float inv_span = 1.0f;
@@ -313,7 +316,7 @@ __global__ void __launch_bounds__(kGridThreads) grid_filter_kernel(const GridPla
               vn += wxy * ((1.0f - az) * snum[c] + az * snum[c + 1]);
               vd += wxy * ((1.0f - az) * sden[c] + az * sden[c + 1]);
             }
-          store_field(out, static_cast<int64_t>(i) * W + j, vn / vd - pvu, field_type);
+          store_field(out, static_cast<int64_t>(i) * W + j, (vn / vd - pvu) * ssc, field_type);
         }
       }
     }

@@ -234,6 +234,12 @@ __global__ void __launch_bounds__(256) nc_cols_kernel(const NcPlane* __restrict_
   const int j = j0 + c;
   float inv;
   const bool scaled = field_scale(P, field, &inv);
+  // FP16 fields: the residual's power-of-two store scale (1 otherwise)
+  float ssc = 1.0f;
+  if (LAST) {
+    const float2 fsc = field_store_scales(P.fmm);
+    ssc = field ? fsc.y : fsc.x;
+  }
   const float* __restrict__ g = P.g ? P.g : P.f;
   const int64_t gp = P.g ? P.gpitch : P.pitch;
   const float* __restrict__ in = P.buf[src][field];
@@ -276,7 +282,7 @@ __global__ void __launch_bounds__(256) nc_cols_kernel(const NcPlane* __restrict_
       const int64_t o = static_cast<int64_t>(i) * W + j;
       if (LAST) {
         const float res = out - grad_at(P.f, P.pitch, H, W, i, j, field);
-        store_field(field ? P.ry : P.rx, o, res, field_type);
+        store_field(field ? P.ry : P.rx, o, res * ssc, field_type);
       } else {
         store_global(P.buf[src ^ 1][field], o, out);
       }

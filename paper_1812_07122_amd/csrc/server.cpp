@@ -219,6 +219,8 @@ static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
       if (it >= rd.iterations) continue;
       if (rd.normalize || rd.filter == BLFLS_FILTER_GRID)
         for (auto& a : (first ? rd.mm_first : rd.mm_next)) push_desc(mm, a);
+      if (first && rd.fp16_scale)   // FP16 fields: the image's gradient extrema (store scales)
+        for (auto& a : rd.mm_f) push_desc(mm, a);
       if (rd.filter != BLFLS_FILTER_BLF) {
         Group g{4};
         g.job = jb;
@@ -612,7 +614,7 @@ blfls_status blfls_submit(blfls_server_t s, const blfls_request* r, uint64_t* ti
                               : filt == BLFLS_FILTER_GRID ? C * sizeof(GridPlane) + 256
                               : filt == BLFLS_FILTER_AMF  ? 2 * C * sizeof(AmfPlane) + 256
                                                           : C * sizeof(BlfPlane);
-  const size_t desc_bytes = sizeof(RequestTables) + 16 + C * sizeof(AuxPlane) +
+  const size_t desc_bytes = sizeof(RequestTables) + 16 + 2 * C * sizeof(AuxPlane) +
                             static_cast<size_t>(r->params.iterations) *
                                 (filter_group + C * (sizeof(FftPlane) + sizeof(AuxPlane)));
   if (desc_bytes + blfls_server_s::kHeaderBytes + blfls_server_s::kMaxGroups * 256 > s->stage_bytes)

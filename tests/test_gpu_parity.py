@@ -544,3 +544,62 @@ def test_server_orders_inputs_still_being_written_on_the_callers_stream():
     torch.cuda.synchronize()
     assert torch.equal(alone, u)
     server.close()
+
+
+def _psnr_peak(a, b, peak):
+    mse = float(np.mean((a - b) ** 2))
+    return float("inf") if mse == 0 else 10 * math.log10(peak * peak / mse)
+
+
+@pytest.mark.parametrize("k,filt", [(65535.0, "blf"), (65536.0, "blf"), (65536.0, "nc"), (65536.0, "grid"),
+                                    (65536.0, "amf"), (2.0 ** 24, "blf")])
+def test_fp16_fields_follow_the_data_range(k, filt):
+    """FP16 field storage of images with 16-bit sample values and beyond: the residual
+    fields reach the gradients' span, above the FP16 maximum 65504, so each field is
+    stored times the power of two that brings its span to 2^15 and the solve multiplies
+    it back.  The result is finite and matches the oracle within k times the mixed
+    bar (2e-3 k, 50 dB against the peak k).  The filters' windows and bins see the
+    image and sigma_r scaled alike (k a power of two: the same decisions)."""
+    from synth import quantized
+    f = quantized(voronoi_image(72, 96, 61)) * k
+    prm = dict(lam=30.0, sigma_s=3.0, sigma_r=0.0713 * k)
+    kw = {} if filt == "blf" else {"filter": filt}
+    u, fin, _ = _run(f, precision="fp16", **prm, **kw)
+    for q in (oracle.grad_x(fin), oracle.grad_y(fin)):   # decisions far from their thresholds
+        if filt == "nc":
+            assert oracle.nc_decision_margin(q, prm["sigma_s"], prm["sigma_r"]) >= 1e-3
+        if filt == "grid":
+            assert oracle.grid_bin_margin(q, prm["sigma_r"]) >= 1e-4
+    ref = oracle.smooth(fin, **prm, **kw)
+    assert np.all(np.isfinite(u))
+    err = float(np.max(np.abs(u - ref)))
+    psnr = _psnr_peak(u, ref, k)
+    print(f"FP16 fields, scale {k:g}, {filt}: max-abs {err:.3e} ({err / k:.2e} of the peak), {psnr:.1f} dB")
+    assert err <= TOL_MIXED * k and psnr >= 50.0
+
+
+def test_fp16_fields_joint_and_served_at_16_bit_scale():
+    """A guided request with 16-bit values through the server equals the same request
+    run alone, bit for bit, and matches the oracle within the scaled mixed bar."""
+    import time
+    b = blfls()
+    k = 65535.0
+    t, g = joint_pair(96, 128, 9)
+    t, g = t * k, g * k
+    prm = dict(lam=30.0, sigma_s=3.0, sigma_r=0.08 * k)
+    server = b.Server(arena_bytes=128 << 20, max_slots=2, precision="fp16")
+    tk, u = server.submit(_to_gpu(t), guide=_to_gpu(g), **prm)
+    deadline = time.time() + 60
+    while server.poll(tk)[0] not in (b.DONE, b.FAILED):
+        assert time.time() < deadline
+        time.sleep(0.001)
+    server.stream.synchronize()
+    alone = b.smooth(_to_gpu(t), guide=_to_gpu(g), precision="fp16", **prm)
+    torch.cuda.synchronize()
+    assert torch.equal(alone, u)
+    server.close()
+    ua = alone.cpu().numpy().astype(np.float64)
+    ref = oracle.smooth(np.asarray(t, np.float32).astype(np.float64), guide=np.asarray(g, np.float32).astype(np.float64),
+                        **prm)
+    assert np.all(np.isfinite(ua))
+    assert float(np.max(np.abs(ua - ref))) <= TOL_MIXED * k and _psnr_peak(ua, ref, k) >= 50.0
