@@ -10,7 +10,9 @@
 // step k+1 while step k runs, then retires step k when its event completes.
 // Requests that arrive while a step runs are admitted into the next one.
 // Every request's arithmetic is independent of its neighbours in a batch, so
-// a result is bitwise the same alone and in any mix.
+// a result is bitwise the same alone and in any mix.  Queueing, admission,
+// tickets, retirement and latencies live in the GPU-independent scheduling
+// core (server_core.h); this file is its HIP executor.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +23,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <tuple>
@@ -31,6 +34,7 @@
 #include "blfls_internal.h"
 #include "blfls_launch.h"
 #include "blfls_plan.h"
+#include "server_core.h"
 
 namespace blfls {
 namespace {
@@ -38,73 +42,14 @@ namespace {
 constexpr size_t kStageBytes = 8u << 20;  // descriptor staging per in-flight step
 constexpr int kDepth = 2;                 // steps in flight
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+size_t align_up(size_t v, size_t a) { return core_align_up(v, a); }
 
-double now_ms() {
-  using namespace std::chrono;
-  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
-}
+constexpr int kMaxGraphs = 32;            // captured step graphs kept (least recently used evicted)
 
-// First-fit allocator over [base, base + bytes) of the arena, 256-byte granules.
-class Arena {
- public:
-  void init(size_t base, size_t bytes) {
-    free_.clear();
-    if (bytes > 0) free_[base] = bytes;
-    total_ = bytes;
-    used_ = peak_ = 0;
-  }
-  bool alloc(size_t n, size_t* off) {
-    n = align_up(n, 256);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= n) {
-        *off = it->first;
-        const size_t rest = it->second - n;
-        const size_t start = it->first + n;
-        free_.erase(it);
-        if (rest) free_[start] = rest;
-        used_ += n;
-        peak_ = std::max(peak_, used_);
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t n) {
-    n = align_up(n, 256);
-    used_ -= n;
-    auto it = free_.emplace(off, n).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t total() const { return total_; }
-  size_t used() const { return used_; }
-  size_t peak() const { return peak_; }
-
- private:
-  std::map<size_t, size_t> free_;
-  size_t total_ = 0, used_ = 0, peak_ = 0;
-};
-
-struct Job {
-  uint64_t id = 0;
-  double t_submit = 0.0;
-  size_t desc_bytes = 0;  // staging bytes of this request's tables and descriptors
-  size_t ws_bytes = 0;    // arena bytes of its workspace (the AMF's is larger than the plan's)
+struct Job : CoreJob {
   blfls_request req{};
   int radius = 0;
   blfls_plan_s* plan = nullptr;
-  size_t ws_off = 0;
   RequestDesc rd;
 };
 
@@ -123,14 +68,6 @@ struct Group {
   bool wave_cols = false;       // fft: a plane's passes hold one column or row per wave
 };
 
-struct Step {
-  std::vector<Job*> jobs;
-  hipEvent_t done = nullptr;
-  hipError_t err = hipSuccess;
-  double t_launch = 0.0;
-  bool busy = false;
-};
-
 }  // namespace
 }  // namespace blfls
 
@@ -140,27 +77,15 @@ struct blfls_server_s {
   uint8_t* arena = nullptr;
   size_t arena_bytes = 0;
   size_t desc_region = 0;  // bytes of arena reserved for device descriptors (kDepth * kStageBytes)
-  int max_slots = 1;
-  int queue_cap = 1;
   blfls_precision precision = BLFLS_FP32;
   hipStream_t stream = nullptr;
   int device = 0;
 
-  std::mutex mu;
-  std::condition_variable cv;
-  bool stopping = false;
-  std::deque<Job*> queue;
-  std::unordered_map<uint64_t, std::pair<int, blfls_status>> tickets;
-  uint64_t next_id = 1;
-  int running = 0;
-  Arena arena_alloc;
+  SchedulerCore<Job, kDepth> core;
+  std::mutex plans_mu;
   std::map<std::tuple<int, int, int>, blfls_plan_s*> plans;
   uint8_t* staging[kDepth] = {nullptr, nullptr};
-  Step steps[kDepth];
-  blfls_stats stats{};
-  double step_ms_total = 0.0;
-  std::vector<double> latencies;  // submit -> done, ms
-  std::thread worker;
+  hipEvent_t done[kDepth] = {nullptr, nullptr};
 
   // staging layout of one slot: [work header][request tables][descriptor arrays]
   static constexpr size_t kHeaderBytes = 16384;
@@ -171,17 +96,25 @@ struct blfls_server_s {
   size_t stage_bytes = 0;
   size_t kFftLdsMax = 0;
   hipStream_t capture_stream = nullptr;
-  std::map<std::pair<std::vector<int>, int>, hipGraphExec_t> graphs;
-  // written by the scheduler thread outside the lock, read by blfls_server_stats
+  struct CachedGraph {
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_step = 0;  // launch index of the last step that replayed it
+  };
+  std::map<std::pair<std::vector<int>, int>, CachedGraph> graphs;
+  // read by blfls_server_stats from other threads
   std::atomic<uint64_t> stats_graph_steps{0}, stats_direct_steps{0};
 
-  void run();
-  void retire(Step& st);
-  void admit(std::vector<Job*>* admitted);
-  hipError_t launch_step(Step& st, int slot);
+  // executor of the scheduling core (called on its scheduler thread)
+  int launch(std::vector<Job*>& jobs, int slot);
+  int query(int slot);
+  void drain(int slot, int err);
+
+  hipError_t launch_step(std::vector<Job*>& jobs, int slot);
   hipError_t launch_direct(std::vector<Group>& groups, int slot, int ft, size_t tables_used);
   hipError_t launch_other_filter(const Job& jb, const uint8_t* planes, bool joint, int ft);
   hipError_t build_graph(const std::vector<Group>& groups, int slot, int ft, hipGraphExec_t* out);
+  void evict_graph();
+  std::shared_ptr<void> exec_holder;   // the core's executor (owned here, outlives the core's thread)
 };
 
 
@@ -387,22 +320,22 @@ hipError_t blfls_server_s::build_graph(const std::vector<Group>& groups, int slo
   return e;
 }
 
-hipError_t blfls_server_s::launch_step(Step& st, int slot) {
+hipError_t blfls_server_s::launch_step(std::vector<Job*>& jobs, int slot) {
   const int ft = precision == BLFLS_FP32 ? kF32 : precision == BLFLS_MIXED_BF16 ? kBF16 : kF16;
   uint8_t* host = staging[slot];
   uint8_t* dev = arena + slot * stage_bytes;
   // slot layout: [work header][request tables][packed descriptor arrays]; the
   // BLF and Gaussian descriptors point at their request's tables
   const size_t tables_base = kHeaderBytes;
-  for (size_t j = 0; j < st.jobs.size(); ++j) {
-    Job* jb = st.jobs[j];
+  for (size_t j = 0; j < jobs.size(); ++j) {
+    Job* jb = jobs[j];
     const blfls_request& q = jb->req;
     const size_t toff = tables_base + j * sizeof(RequestTables);
     build_request(jb->plan, q.params, jb->radius, q.f, q.guide, q.u, q.pitch, arena + jb->ws_off, dev + toff, &jb->rd);
     std::memcpy(host + toff, &jb->rd.tables, sizeof(RequestTables));
   }
-  size_t used = tables_base + st.jobs.size() * sizeof(RequestTables);
-  std::vector<Group> groups = build_groups(st.jobs);
+  size_t used = tables_base + jobs.size() * sizeof(RequestTables);
+  std::vector<Group> groups = build_groups(jobs);
   bool direct = static_cast<int>(groups.size()) > kMaxGroups;
   // per-request filters launch directly, and so do Fourier passes that hold one
   // column or row per wave (the captured persistent kernels have no such path)
@@ -410,7 +343,7 @@ hipError_t blfls_server_s::launch_step(Step& st, int slot) {
   if (direct) {
     stats_direct_steps++;
     const hipError_t e = launch_direct(groups, slot, ft, used);
-    return e == hipSuccess ? hipEventRecord(st.done, stream) : e;
+    return e == hipSuccess ? hipEventRecord(done[slot], stream) : e;
   }
   WorkHeader* header = reinterpret_cast<WorkHeader*>(host);
   std::memset(header, 0, kHeaderBytes);
@@ -427,102 +360,48 @@ hipError_t blfls_server_s::launch_step(Step& st, int slot) {
   const auto key = std::make_pair(signature(groups), slot);
   auto it = graphs.find(key);
   if (it == graphs.end()) {
+    if (graphs.size() >= static_cast<size_t>(kMaxGraphs)) evict_graph();
     hipGraphExec_t exec = nullptr;
     const hipError_t e = build_graph(groups, slot, ft, &exec);
     if (e != hipSuccess) return e;
-    it = graphs.emplace(key, exec).first;
+    it = graphs.emplace(key, CachedGraph{exec, 0}).first;
   }
   hipError_t e = hipMemcpyAsync(dev, host, used, hipMemcpyHostToDevice, stream);
   if (e != hipSuccess) return e;
-  e = hipGraphLaunch(it->second, stream);
+  e = hipGraphLaunch(it->second.exec, stream);
   if (e != hipSuccess) return e;
+  it->second.last_step = core.launched_steps() + 1;   // this step's launch index
   stats_graph_steps++;
-  return hipEventRecord(st.done, stream);
+  return hipEventRecord(done[slot], stream);
 }
 
-void blfls_server_s::retire(Step& st) {
-  hipError_t e = st.err;
-  if (e == hipSuccess) e = hipEventSynchronize(st.done);
-  else (void)hipStreamSynchronize(stream);  // let launched kernels drain before their memory is reused
-  const double ms = now_ms() - st.t_launch;
-  std::lock_guard<std::mutex> lk(mu);
-  for (Job* jb : st.jobs) {
-    auto it = tickets.find(jb->id);
-    if (it != tickets.end()) {
-      it->second.first = e == hipSuccess ? BLFLS_DONE : BLFLS_FAILED;
-      it->second.second = e == hipSuccess ? BLFLS_OK : BLFLS_E_HIP;
-    }
-    if (e == hipSuccess) {
-      stats.completed++;
-      latencies.push_back(now_ms() - jb->t_submit);
-    } else {
-      stats.failed++;
-    }
-    arena_alloc.release(jb->ws_off, jb->ws_bytes);
-    running--;
-    delete jb;
-  }
-  st.jobs.clear();
-  st.busy = false;
-  step_ms_total += ms;
-  cv.notify_all();
+// Destroy the least recently used graph that no step in flight replays: its
+// last step has retired (steps retire in launch order).
+void blfls_server_s::evict_graph() {
+  const uint64_t retired = core.retired_steps();
+  auto victim = graphs.end();
+  for (auto it = graphs.begin(); it != graphs.end(); ++it)
+    if (it->second.last_step <= retired && (victim == graphs.end() || it->second.last_step < victim->second.last_step))
+      victim = it;
+  if (victim == graphs.end()) return;
+  (void)hipGraphExecDestroy(victim->second.exec);
+  graphs.erase(victim);
 }
 
-void blfls_server_s::admit(std::vector<Job*>* admitted) {
-  // descriptor budget of one step: header, per-group alignment, then requests
-  size_t desc = kHeaderBytes + static_cast<size_t>(kMaxGroups) * 256;
-  while (!queue.empty() && running < max_slots) {
-    Job* jb = queue.front();
-    if (desc + jb->desc_bytes > stage_bytes) break;  // the rest waits for the next step
-    size_t off = 0;
-    if (!arena_alloc.alloc(jb->ws_bytes, &off)) break;  // FIFO: the head waits for space
-    desc += jb->desc_bytes;
-    jb->ws_off = off;
-    queue.pop_front();
-    tickets[jb->id].first = BLFLS_RUNNING;
-    running++;
-    stats.admitted++;
-    admitted->push_back(jb);
-  }
+int blfls_server_s::launch(std::vector<Job*>& jobs, int slot) {
+  const hipError_t e = launch_step(jobs, slot);
+  return e == hipSuccess ? 0 : -static_cast<int>(e);
 }
 
-void blfls_server_s::run() {
-  (void)hipSetDevice(device);
-  int next = 0;    // slot the next step launches into
-  int oldest = 0;  // oldest in-flight step (steps complete in launch order: one stream)
-  for (;;) {
-    while (steps[oldest].busy) {
-      Step& st = steps[oldest];
-      if (st.err == hipSuccess) {
-        const hipError_t q = hipEventQuery(st.done);
-        if (q == hipErrorNotReady) break;
-        if (q != hipSuccess) st.err = q;
-      }
-      retire(st);
-      oldest = (oldest + 1) % kDepth;
-    }
-    std::unique_lock<std::mutex> lk(mu);
-    bool any_busy = false;
-    for (auto& x : steps) any_busy = any_busy || x.busy;
-    if (stopping && queue.empty() && !any_busy) break;
-    Step& st = steps[next];
-    std::vector<Job*> admitted;
-    if (!st.busy) admit(&admitted);
-    if (!admitted.empty()) {
-      stats.steps++;
-      lk.unlock();
-      st.jobs = std::move(admitted);
-      st.busy = true;
-      st.t_launch = now_ms();
-      st.err = launch_step(st, next);
-      next = (next + 1) % kDepth;
-      continue;
-    }
-    if (any_busy)
-      cv.wait_for(lk, std::chrono::microseconds(50));  // poll the in-flight step's event
-    else
-      cv.wait(lk, [&] { return stopping || !queue.empty(); });
-  }
+int blfls_server_s::query(int slot) {
+  const hipError_t q = hipEventQuery(done[slot]);
+  if (q == hipErrorNotReady) return 1;
+  return q == hipSuccess ? 0 : -static_cast<int>(q);
+}
+
+void blfls_server_s::drain(int slot, int err) {
+  if (err == 0) (void)hipEventSynchronize(done[slot]);
+  else (void)hipStreamSynchronize(stream);  // kernels launched before the error finish first
 }
 
 extern "C" {
@@ -544,8 +423,6 @@ blfls_status blfls_server_create(blfls_server_t* out, void* arena, size_t arena_
   s->arena = static_cast<uint8_t*>(arena);
   s->arena_bytes = arena_bytes;
   s->desc_region = reserved;
-  s->max_slots = max_slots;
-  s->queue_cap = queue_capacity;
   s->precision = precision;
   s->stream = static_cast<hipStream_t>(stream);
   hipError_t e = hipGetDevice(&s->device);
@@ -554,21 +431,45 @@ blfls_status blfls_server_create(blfls_server_t* out, void* arena, size_t arena_
   s->kFftLdsMax = std::max(fft_rows_lds_bytes(kFftLdsComplex - 1, 1), fft_cols_lds_bytes(kFftLdsComplex, 1));
   e = hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking);
   if (e != hipSuccess) { delete s; return hip_error(e, "capture stream"); }
-  s->arena_alloc.init(reserved, arena_bytes - reserved);
-  s->stats.arena_bytes = arena_bytes - reserved;
   for (int i = 0; i < kDepth; ++i) {
     e = hipHostMalloc(reinterpret_cast<void**>(&s->staging[i]), stage_bytes, hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->steps[i].done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->done[i], hipEventDisableTiming);
     if (e != hipSuccess) {
       for (int j = 0; j <= i; ++j) {
         if (s->staging[j]) (void)hipHostFree(s->staging[j]);
-        if (s->steps[j].done) (void)hipEventDestroy(s->steps[j].done);
+        if (s->done[j]) (void)hipEventDestroy(s->done[j]);
       }
+      (void)hipStreamDestroy(s->capture_stream);
       delete s;
       return hip_error(e, "server setup");
     }
   }
-  s->worker = std::thread([s] { s->run(); });
+  CoreConfig cfg;
+  cfg.arena_base = reserved;
+  cfg.arena_bytes = arena_bytes - reserved;
+  cfg.max_slots = max_slots;
+  cfg.queue_cap = queue_capacity;
+  cfg.step_budget = stage_bytes;
+  // descriptor budget of one step: header, per-group alignment, then requests
+  cfg.step_overhead = blfls_server_s::kHeaderBytes + static_cast<size_t>(blfls_server_s::kMaxGroups) * 256;
+  s->core.configure(cfg);
+  const int dev = s->device;
+  struct Exec {
+    blfls_server_s* s;
+    int dev;
+    bool bound = false;
+    int launch(std::vector<Job*>& jobs, int slot) {
+      if (!bound) { (void)hipSetDevice(dev); bound = true; }
+      return s->launch(jobs, slot);
+    }
+    int query(int slot) { return s->query(slot); }
+    void drain(int slot, int err) { s->drain(slot, err); }
+  };
+  static_assert(sizeof(Exec) <= 64, "executor state");
+  auto* ex = new (std::nothrow) Exec{s, dev};
+  if (!ex) { blfls_server_destroy(s); return set_error(BLFLS_E_NOMEM, "host allocation failed"); }
+  s->exec_holder.reset(ex, [](void* p) { delete static_cast<Exec*>(p); });
+  s->core.start(ex);
   *out = s;
   return BLFLS_OK;
 }
@@ -589,25 +490,23 @@ blfls_status blfls_submit(blfls_server_t s, const blfls_request* r, uint64_t* ti
   };
   if (ov(r->u, img, r->f, img) || (r->guide && ov(r->u, img, r->guide, img)) || ov(r->u, img, s->arena, s->arena_bytes))
     return set_error(BLFLS_E_INVALID, "u must not overlap f, guide or the arena");
-  std::unique_lock<std::mutex> lk(s->mu);
-  if (s->stopping) return set_error(BLFLS_E_INVALID, "server is shutting down");
-  if (static_cast<int>(s->queue.size()) >= s->queue_cap) return set_error(BLFLS_E_AGAIN, "queue full");
   const auto key = std::make_tuple(r->H, r->W, r->C);
   blfls_plan_s* plan = nullptr;
-  auto it = s->plans.find(key);
-  if (it == s->plans.end()) {
-    st = plan_create(r->H, r->W, r->C, s->precision, &plan);
-    if (st != BLFLS_OK) return st;
-    s->plans[key] = plan;
-  } else {
-    plan = it->second;
+  {
+    std::lock_guard<std::mutex> lk(s->plans_mu);
+    auto it = s->plans.find(key);
+    if (it == s->plans.end()) {
+      st = plan_create(r->H, r->W, r->C, s->precision, &plan);
+      if (st != BLFLS_OK) return st;
+      s->plans[key] = plan;
+    } else {
+      plan = it->second;
+    }
   }
   const size_t ws_bytes = request_workspace_bytes(plan, r->params);
-  if (ws_bytes > s->arena_bytes - s->desc_region)
-    return set_error(BLFLS_E_NOMEM, "request workspace exceeds the arena");
-  // staging bytes: tables, the Gaussian descriptors, and per iteration the
-  // filter's descriptors (one group of its own, aligned, for the filters other
-  // than the BLF), one FFT and one extrema descriptor per channel
+  // staging bytes: tables, the Gaussian and image-extrema descriptors, and per
+  // iteration the filter's descriptors (one group of its own, aligned, for the
+  // filters other than the BLF), one FFT and one extrema descriptor per channel
   const int filt = r->params.filter;
   const size_t C = static_cast<size_t>(r->C);
   const size_t filter_group = filt == BLFLS_FILTER_NC     ? C * sizeof(NcPlane) + 256
@@ -623,52 +522,30 @@ blfls_status blfls_submit(blfls_server_t s, const blfls_request* r, uint64_t* ti
   if (!jb) return set_error(BLFLS_E_NOMEM, "host allocation failed");
   jb->desc_bytes = desc_bytes;
   jb->ws_bytes = ws_bytes;
-  jb->id = s->next_id++;
-  jb->t_submit = now_ms();
   jb->req = *r;
   jb->radius = radius;
   jb->plan = plan;
-  s->queue.push_back(jb);
-  s->tickets[jb->id] = {BLFLS_QUEUED, BLFLS_OK};
-  s->stats.submitted++;
-  *ticket = jb->id;
-  s->cv.notify_all();
+  st = s->core.submit(jb, ticket);
+  if (st != BLFLS_OK) {
+    delete jb;
+    if (st == BLFLS_E_NOMEM) return set_error(st, "request workspace exceeds the arena");
+    if (st == BLFLS_E_AGAIN) return set_error(st, "queue full");
+    return set_error(st, "server is shutting down");
+  }
   return BLFLS_OK;
 }
 
 blfls_status blfls_poll(blfls_server_t s, uint64_t ticket, int32_t* state, blfls_status* result) {
   if (s == nullptr || state == nullptr || result == nullptr) return set_error(BLFLS_E_INVALID, "NULL argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  auto it = s->tickets.find(ticket);
-  if (it == s->tickets.end()) return set_error(BLFLS_E_UNKNOWN_TICKET, "unknown or retired ticket");
-  *state = it->second.first;
-  *result = it->second.second;
-  if (*state == BLFLS_DONE || *state == BLFLS_FAILED) s->tickets.erase(it);
+  const blfls_status st = s->core.poll(ticket, state, result);
+  if (st != BLFLS_OK) return set_error(st, "unknown or retired ticket");
   return BLFLS_OK;
 }
 
 blfls_status blfls_server_stats(blfls_server_t s, blfls_stats* out) {
   if (s == nullptr || out == nullptr) return set_error(BLFLS_E_INVALID, "NULL argument");
-  std::lock_guard<std::mutex> lk(s->mu);
-  *out = s->stats;
-  out->queued_now = s->queue.size();
-  out->running_now = static_cast<uint64_t>(s->running);
-  out->arena_in_use = s->arena_alloc.used();
-  out->arena_peak = s->arena_alloc.peak();
-  out->step_ms_mean = s->stats.steps ? s->step_ms_total / static_cast<double>(s->stats.steps) : 0.0;
-  std::vector<double> lat = s->latencies;
-  out->latency_samples = lat.size();
-  out->latency_p50_ms = out->latency_p99_ms = out->latency_max_ms = 0.0;
-  if (!lat.empty()) {
-    std::sort(lat.begin(), lat.end());
-    auto pct = [&](double q) {
-      const size_t i = static_cast<size_t>(std::ceil(q * static_cast<double>(lat.size()))) - 1;
-      return lat[std::min(i, lat.size() - 1)];
-    };
-    out->latency_p50_ms = pct(0.50);
-    out->latency_p99_ms = pct(0.99);
-    out->latency_max_ms = lat.back();
-  }
+  *out = blfls_stats{};
+  s->core.fill_stats(out);
   out->graph_steps = s->stats_graph_steps.load(std::memory_order_relaxed);
   out->direct_steps = s->stats_direct_steps.load(std::memory_order_relaxed);
   return BLFLS_OK;
@@ -676,20 +553,14 @@ blfls_status blfls_server_stats(blfls_server_t s, blfls_stats* out) {
 
 blfls_status blfls_server_destroy(blfls_server_t s) {
   if (s == nullptr) return set_error(BLFLS_E_INVALID, "server is NULL");
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->stopping = true;
-  }
-  s->cv.notify_all();
-  if (s->worker.joinable()) s->worker.join();
-  for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  s->core.stop();   // drains everything queued or in flight
+  for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second.exec);
   if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
   for (auto& kv : s->plans) plan_free(kv.second);
   for (int i = 0; i < kDepth; ++i) {
     if (s->staging[i]) (void)hipHostFree(s->staging[i]);
-    if (s->steps[i].done) (void)hipEventDestroy(s->steps[i].done);
+    if (s->done[i]) (void)hipEventDestroy(s->done[i]);
   }
-  for (Job* jb : s->queue) delete jb;
   delete s;
   return BLFLS_OK;
 }
