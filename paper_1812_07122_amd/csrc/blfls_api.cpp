@@ -30,9 +30,12 @@ thread_local std::string g_last_error;
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Factor n into radices up to max_pow2 (16 or 8) for the powers of two, then one
-// 8, 4 or 2, then 3s and 5s; false if another prime divides n.  Row transforms
-// use at most radix 8 (their first stage reads HBM and needs enough butterflies
-// to occupy the workgroup), column transforms radix 16 (fewer barriers).
+// 8, 4 or 2, then the odd part as 15s (3 x 5, prime-factor butterflies), 9s
+// (3 x 3), 3s and 5s; false if another prime divides n.  Fewer, larger stages
+// mean fewer LDS round trips, barriers and twiddle products per element.  Row
+// transforms use at most radix 8 for the powers of two (their first stage reads
+// HBM and needs enough butterflies to occupy the workgroup), column transforms
+// radix 16 (fewer barriers).
 bool factorize(int n, std::vector<int>* radices, int max_pow2 = 16) {
   radices->clear();
   int m = n;
@@ -41,6 +44,8 @@ bool factorize(int n, std::vector<int>* radices, int max_pow2 = 16) {
   while (m % 8 == 0) { radices->push_back(8); m /= 8; }
   if (m % 4 == 0) { radices->push_back(4); m /= 4; }
   if (m % 2 == 0) { radices->push_back(2); m /= 2; }
+  while (m % 15 == 0) { radices->push_back(15); m /= 15; }
+  while (m % 9 == 0) { radices->push_back(9); m /= 9; }
   while (m % 3 == 0) { radices->push_back(3); m /= 3; }
   while (m % 5 == 0) { radices->push_back(5); m /= 5; }
   return m == 1;
@@ -295,6 +300,9 @@ blfls_status plan_create(int H, int W, int C, blfls_precision prec, blfls_plan_s
   rb = std::min(rb, floor_pow2(H));
   int cb = std::min(16, std::max(1, kFftLdsComplex / H));
   while (cb > 1 && static_cast<long>(C) * ((M + 1 + cb - 1) / cb) < 256) cb = (cb + 1) / 2;
+  // a radix-15 stage holds one butterfly per thread across its barrier
+  if (M % 15 == 0) while (rb > 1 && static_cast<long>(rb) * M > kFftRadix15Elems) rb /= 2;
+  if (H % 15 == 0) while (cb > 1 && static_cast<long>(cb) * H > kFftRadix15Elems) --cb;
   // H = 512 or 1024: one spectrum column per wave, held in registers; likewise
   // one row per wave for W/2 = 512 or 1024
   const int colw = (H == 512 || H == 1024) ? H / 64 : 0;

@@ -17,6 +17,8 @@ constexpr int kMaxStages = 16;          // FFT stages per transform length
 constexpr int kMaxFft = 4096;           // longest transform (W/2 or H)
 constexpr int kFftThreads = 512;        // threads per FFT workgroup
 constexpr int kFftLdsComplex = 8192;    // complex values per FFT workgroup (64 KiB)
+constexpr int kFftRadix15Elems = 7680;  // complex values per FFT workgroup when a stage has radix 15
+                                        // (one radix-15 butterfly per thread)
 constexpr int kMinmaxBlocks = 256;      // partial-reduction blocks per plane
 
 enum FieldType : int { kF32 = 0, kBF16 = 1, kF16 = 2 };

@@ -15,7 +15,7 @@
 //   cols     : per spectrum column: forward FFT over H, multiply by
 //              1/(H W den), inverse FFT over H, all in LDS (one read, one write);
 //   rows_inv : complex-to-real inverse of each row, u = f + delta.
-// Transforms are in-place Stockham passes in LDS with radices 2, 3, 4, 5, 8.
+// Transforms are in-place Stockham passes in LDS with radices 2, 3, 4, 5, 8, 9, 15, 16.
 // Each workgroup first stages two-level twiddle tables of its transform lengths
 // (FP64 host tables rounded to FP32, about 1.5 KiB) in LDS next to the data, so
 // no stage waits on global memory and two workgroups fit on a CU; index
@@ -173,6 +173,53 @@ __device__ __forceinline__ void butterfly<16>(float2* a, float sg) {
   }
 }
 
+// Radix 9 as 3 x 3: with t = t1 + 3 t2 and k = 3 k1 + k2,
+// A_{3k1+k2} = sum_{t1} w3^{t1 k1} [ w9^{t1 k2} sum_{t2} a_{t1+3t2} w3^{t2 k2} ].
+template <>
+__device__ __forceinline__ void butterfly<9>(float2* a, float sg) {
+  // cos and sin of 2 pi m / 9 for the products m = t1 k2 in {1, 2, 4}
+  constexpr float kC[5] = {1.0f, 0.76604444311897803520f, 0.17364817766693034885f, 0.0f, -0.93969262078590838405f};
+  constexpr float kS[5] = {0.0f, 0.64278760968653932632f, 0.98480775301220805936f, 0.0f, 0.34202014332566873304f};
+  float2 b[3][3];
+#pragma unroll
+  for (int t1 = 0; t1 < 3; ++t1) {
+    float2 c[3] = {a[t1], a[t1 + 3], a[t1 + 6]};
+    butterfly<3>(c, sg);
+#pragma unroll
+    for (int k2 = 0; k2 < 3; ++k2) {
+      const int m = t1 * k2;
+      b[k2][t1] = m == 0 ? c[k2] : cmul(c[k2], make_float2(kC[m], sg * kS[m]));
+    }
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < 3; ++k2) {
+    butterfly<3>(b[k2], sg);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) a[3 * k1 + k2] = b[k2][k1];
+  }
+}
+
+// Radix 15 as 3 x 5 by the prime-factor (Good-Thomas) mapping, no twiddles:
+// input t = (5 t1 + 3 t2) mod 15, output k = (10 k1 + 6 k2) mod 15 (k = k1 mod 3,
+// k = k2 mod 5), so A_k = sum_{t1} w3^{t1 k1} sum_{t2} w5^{t2 k2} a_t.
+template <>
+__device__ __forceinline__ void butterfly<15>(float2* a, float sg) {
+  float2 b[3][5];
+#pragma unroll
+  for (int t1 = 0; t1 < 3; ++t1) {
+#pragma unroll
+    for (int t2 = 0; t2 < 5; ++t2) b[t1][t2] = a[(5 * t1 + 3 * t2) % 15];
+    butterfly<5>(b[t1], sg);
+  }
+#pragma unroll
+  for (int k2 = 0; k2 < 5; ++k2) {
+    float2 c[3] = {b[0][k2], b[1][k2], b[2][k2]};
+    butterfly<3>(c, sg);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) a[(10 * k1 + 6 * k2) % 15] = c[k1];
+  }
+}
+
 // Padded LDS index: one spare slot per 16 complex values, so the stride-R
 // writes of the early Stockham stages spread over the LDS banks.
 __device__ __forceinline__ int pad(int i) { return i + (i >> 4); }
@@ -196,7 +243,10 @@ struct LdsIO {  // in-place LDS buffer (padded layout)
 template <int R, int T, int MAXE, class SRC, class DST>
 __device__ __forceinline__ void fft_stage(const SRC& src, const DST& dst, int batch, const FftStage& S,
                                           const float2* tw, float sg) {
-  constexpr int kMaxB = (MAXE / R + T - 1) / T;
+  // butterflies per thread held across the barrier; radix 15 keeps one (the plan
+  // bounds its workgroups to T radix-15 butterflies, kFftRadix15Elems elements)
+  constexpr int kMaxB = R == 15 ? 1 : (MAXE / R + T - 1) / T;
+  static_assert(R != 15 || T * 15 == kFftRadix15Elems, "radix-15 workgroup bound");
   const int per = S.per;
   const int Ns = S.ns;
   const int total = per * batch;
@@ -249,6 +299,8 @@ __device__ __forceinline__ void fft_stage_r(const SRC& src, const DST& dst, int 
     case 4: fft_stage<4, T, MAXE>(src, dst, batch, S, tw, sg); break;
     case 5: fft_stage<5, T, MAXE>(src, dst, batch, S, tw, sg); break;
     case 8: fft_stage<8, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    case 9: fft_stage<9, T, MAXE>(src, dst, batch, S, tw, sg); break;
+    case 15: fft_stage<15, T, MAXE>(src, dst, batch, S, tw, sg); break;
     default: fft_stage<16, T, MAXE>(src, dst, batch, S, tw, sg); break;
   }
 }
