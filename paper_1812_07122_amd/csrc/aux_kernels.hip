@@ -34,18 +34,20 @@ hipError_t launch_desc_copy(const void* host_src, size_t bytes, void* dev_dst, h
   return hipSuccess;
 }
 
-constexpr int kMinmaxBatch = 4;   // columns per thread whose loads go out together
+constexpr int kMinmaxBatch = 8;   // columns per thread whose loads go out together
 
 // partial[b] = (min D_x, max D_x, min D_y, max D_y) over the elements of block b
-// (kMinmaxBlocks blocks per plane, rows strided over the blocks).
+// (kMinmaxBlocks blocks per plane, each a contiguous band of rows, so a row's
+// lower neighbour is mostly the band's own next row, already in cache).
 __device__ __forceinline__ void minmax_item(const AuxPlane& P, int blk) {
   const int H = P.H, W = P.W;
   float lx = INFINITY, hx = -INFINITY, ly = INFINITY, hy = -INFINITY;
-  // block blk takes rows blk, blk + kMinmaxBlocks, ...; threads stride the columns,
-  // kMinmaxBatch at a time with every load issued before the first use.  Columns
-  // past the row are clamped to its last one: a repeated value leaves a min or max
-  // unchanged, so they need no guard.
-  for (int i = blk; i < H; i += kMinmaxBlocks) {
+  // threads stride the columns, kMinmaxBatch at a time with every load issued
+  // before the first use.  Columns past the row are clamped to its last one: a
+  // repeated value leaves a min or max unchanged, so they need no guard.
+  const int i_begin = static_cast<int>(static_cast<int64_t>(H) * blk / kMinmaxBlocks);
+  const int i_end = static_cast<int>(static_cast<int64_t>(H) * (blk + 1) / kMinmaxBlocks);
+  for (int i = i_begin; i < i_end; ++i) {
     const int64_t o = static_cast<int64_t>(i) * P.pitch;
     const int64_t on = static_cast<int64_t>(i + 1 == H ? 0 : i + 1) * P.pitch;
     for (int j0 = threadIdx.x; j0 < W; j0 += 256 * kMinmaxBatch) {

@@ -36,6 +36,17 @@ __device__ __forceinline__ int wrap_index(int v, int n) {
   return m < 0 ? m + n : m;
 }
 
+// Logical item of a direct launch's workgroup such that consecutive items run on
+// one XCD (workgroups go round-robin over the 8 XCDs, each with its own L2): the
+// two fields of a tile and neighbouring tiles, which read overlapping halo rows,
+// then meet in one L2.
+__device__ __forceinline__ int xcd_item(int b, int nblk) {
+  constexpr int kXcd = 8;
+  const int q = nblk / kXcd, rem = nblk % kXcd;
+  const int x = b % kXcd;
+  return x * q + min(x, rem) + b / kXcd;
+}
+
 __device__ __forceinline__ int find_plane(const BlfPlane* planes, int nplanes, int item) {
   // items of plane p: [2*tile_begin, 2*(tile_begin+tile_count))
   int lo = 0, hi = nplanes - 1;
@@ -67,8 +78,9 @@ __device__ __forceinline__ void blf_item(const BlfPlane* __restrict__ planes, in
   const BlfPlane& P = planes[pi];
   const int local = item - 2 * P.tile_begin;
   if (local >= 2 * P.tile_count) return;  // uniform: more items than work
-  const int field = local >= P.tile_count ? 1 : 0;
-  const int tile = local - field * P.tile_count;
+  // the two fields of a tile are consecutive items: they read the same halo tile
+  const int field = local & 1;
+  const int tile = local >> 1;
   const int H = P.H, W = P.W;
   const int x0 = (tile % P.tiles_x) * TW;
   const int y0 = (tile / P.tiles_x) * TH;
@@ -211,7 +223,7 @@ __global__ void __launch_bounds__(64 * WAVES)
 blf_field_kernel(const BlfPlane* __restrict__ planes, int nplanes, int field_type,
                  WorkHeader* __restrict__ work) {
   if (!PERSIST) {
-    blf_item<R, K, WAVES, JOINT>(planes, nplanes, field_type, blockIdx.x);
+    blf_item<R, K, WAVES, JOINT>(planes, nplanes, field_type, xcd_item(blockIdx.x, gridDim.x));
     return;
   }
   const int total = work->items;
