@@ -59,8 +59,23 @@ BLF_FLOPS_PER_TAP = 6
 # exponential issue rate: one wave64 v_exp_f32 per 8 SIMD cycles (a quarter of the
 # 32-lane FP32 rate), 256 CUs x 4 SIMDs at 2.4 GHz
 EXP_PEAK_T = 256 * 4 * 2.4e9 * 64 / 8 / 1e12
-# the library's kernel spends this many v_exp_f32 per tap (a symmetric pair shares one)
-BLF_KERNEL_EXPS_PER_TAP = 1.0
+# v_exp_f32 per tap: the symmetric-pair kernel evaluates each unordered pair of taps
+# once (radius classes >= 8 on images with bands at least R wide, R + K - 1 tall),
+# the tile kernel every tap
+EXPS_PER_TAP = {"pair": 0.5, "tile": 1.0}
+KERNELS = {"pair": "blf_pair_kernel<R={r}> + blf_pair_merge_kernel", "tile": "blf_field_kernel<R={r}>"}
+PMC_SOURCE = {"pair": "blf_pair_kernel.hip", "tile": "blf_kernel.hip"}
+
+
+def filter_path(blfls, H, W, C, prm) -> str:
+    """Which BLF kernel a request runs: the pair path needs partial-sum records
+    beyond the plan's own workspace, the tile path does not."""
+    plan = blfls.Plan(H, W, C)
+    try:
+        need = plan.workspace_for(blfls.make_params(prm["lam"], prm["sigma_s"], prm["sigma_r"]))
+        return "pair" if need > plan.workspace_bytes else "tile"
+    finally:
+        plan.close()
 
 
 def parse():
@@ -162,17 +177,22 @@ def fft_bytes(H, W, C, field_bytes):
     return rows_fwd, cols, rows_inv
 
 
-def blf_roofline(kernel, H, W, C, r, blf_ms, traffic):
+def blf_roofline(path, H, W, C, r, blf_ms, pmc_summary=None):
     """The filter's roofline object: algorithmic FP32 flops of Eq. (1) per launch (every tap
-    of both fields of every channel) over the launch duration, against the FP32 vector
-    peak; the exponentials per second beside it."""
+    of both fields of every channel) over the launch duration (the filter stage: for the
+    pair path its band kernel and merge pass), against the FP32 vector peak; the
+    exponentials the kernel issues per second beside it; HBM bytes per launch from the
+    committed PMC summary when it was taken on the current kernel source."""
     taps = C * H * W * 2 * (2 * r + 1) ** 2
     tflops = taps * BLF_FLOPS_PER_TAP / (blf_ms * 1e-3) / 1e12
-    exps = taps * BLF_KERNEL_EXPS_PER_TAP / (blf_ms * 1e-3) / 1e12
-    return {"kernel": kernel, "bound": "alu", "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4), "traffic": traffic,
-            "launch_ms": round(blf_ms, 5), "taps_per_launch": taps, "flops_per_tap": BLF_FLOPS_PER_TAP,
-            "exp_pipe": {"exps_per_tap": BLF_KERNEL_EXPS_PER_TAP, "achieved_T_exp_s": round(exps, 3),
+    epp = EXPS_PER_TAP[path]
+    exps = taps * epp / (blf_ms * 1e-3) / 1e12
+    traffic = traffic_from_profile(PMC_SOURCE[path], pmc_summary) if pmc_summary else None
+    return {"kernel": KERNELS[path].format(r=r), "bound": "alu", "achieved": round(tflops, 3),
+            "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+            "traffic": traffic, "launch_ms": round(blf_ms, 5), "taps_per_launch": taps,
+            "flops_per_tap": BLF_FLOPS_PER_TAP,
+            "exp_pipe": {"exps_per_tap": epp, "achieved_T_exp_s": round(exps, 3),
                          "peak_T_exp_s": round(EXP_PEAK_T, 3), "frac": round(exps / EXP_PEAK_T, 4)}}
 
 
@@ -315,8 +335,7 @@ def run_headline(args, torch, blfls, state):
                                "against BF16 and FP16 field storage", "H": H, "W": W, "C": C},
         "step_launch": "HIP graph replay of one blfls_smooth call; fp32, bf16 and fp16 replays interleaved "
                        "in rotating rounds",
-        "roofline": blf_roofline(f"blf_field_kernel<R={r}>", H, W, C, r, blf32,
-                                 traffic_from_profile("blf_kernel.hip", "blf_kernel_uhd_pmc.md")),
+        "roofline": blf_roofline(filter_path(blfls, H, W, C, prm), H, W, C, r, blf32, "blf_filter_uhd_pmc.md"),
         "fft_passes": per["fp32"]["fft_passes"],
         "precisions": per,
         "mixed_vs_plain": {p: round(per[p]["MPix/s"] / value, 4) for p in ("bf16", "fp16")},
@@ -331,8 +350,8 @@ def run_headline(args, torch, blfls, state):
         "config": "1024x1024 RGB, lambda=20, sigma_s=3 (r=9), sigma_r=0.1, 1 iteration, FP32 (Table I shape)",
         "MPix/s": round(1024 * 1024 / (ms1["fp32"] * 1e-3) / 1e6, 2), "ms_per_step": round(ms1["fp32"], 5),
         "graph_vs_eager_bitwise_equal": eager1["fp32"],
-        "roofline": blf_roofline(f"blf_field_kernel<R={r1}>", 1024, 1024, 3, r1, blf1,
-                                 traffic_from_profile("blf_kernel.hip", "blf_kernel_rgb1024_pmc.md")),
+        "roofline": blf_roofline(filter_path(blfls, 1024, 1024, 3, prm1), 1024, 1024, 3, r1, blf1,
+                                 "blf_filter_rgb1024_pmc.md"),
         "fft_passes": fft_passes(st1["fp32"], 1024, 1024, 3, 4),
         "paper_context": {"value": 2.18, "unit": "MPix/s", "note": "Table I: 0.48 s per 1024x1024 RGB image, "
                           "CPU Python with an approximate (bilateral-grid) filter, hardware unstated"}}
@@ -380,8 +399,7 @@ def run_rgb1024(args, torch, blfls, state=None):
     blf_ms = stages["blf"][0] / max(stages["blf"][1], 1)
     taps = C * H * W * 2 * (2 * r + 1) ** 2
     achieved = taps / (blf_ms * 1e-3) / 1e12
-    traffic = traffic_from_profile("blf_kernel.hip", "blf_kernel_rgb1024_pmc.md")
-    roofline = blf_roofline("blf_field_kernel<R=9>", H, W, C, r, blf_ms, traffic)
+    roofline = blf_roofline(filter_path(blfls, H, W, C, prm), H, W, C, r, blf_ms, "blf_filter_rgb1024_pmc.md")
     rf, cl, ri = fft_bytes(H, W, C, 4)
     fft = {}
     for name, nbytes in (("rows_fwd", rf), ("cols", cl), ("rows_inv", ri)):

@@ -203,7 +203,7 @@ def run_copy(args, torch, blfls, state=None):
 
 
 def run_uhd(args, torch, blfls, state):
-    from bench import time_plan, fft_bytes, blf_roofline
+    from bench import time_plan, fft_bytes, blf_roofline, filter_path
     H, W, C, r = 2160, 3840, 3, 24
     prm = dict(lam=50.0, sigma_s=8.0, sigma_r=0.05)
     f = torch.from_numpy(state["f"]).cuda()
@@ -224,7 +224,7 @@ def run_uhd(args, torch, blfls, state):
             t = stages[name][0] / max(stages[name][1], 1)
             fft[name] = {"ms": round(t, 4), "GB/s": round(nbytes / (t * 1e-3) / 1e9, 1),
                          "frac": round(nbytes / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        ro = blf_roofline(f"blf_field_kernel<R={r}>", H, W, C, r, blf_ms, None)
+        ro = blf_roofline(filter_path(blfls, H, W, C, prm), H, W, C, r, blf_ms)
         results[prec] = {"MPix/s": round(H * W / (ms * 1e-3) / 1e6, 2), "ms_per_step": round(ms, 4),
                          "blf_ms": round(blf_ms, 4), "blf_roofline": ro,
                          "fft_ms": round(fft_ms, 4),

@@ -192,9 +192,10 @@ blfls_status blfls_smooth(blfls_plan_t plan, const blfls_params *params, const f
                           const float *guide, float *u, int64_t pitch, void *workspace,
                           void *stream);
 
-/* Static device scratch of blfls_smooth_noalloc, per GPU (128 MiB: the
- * workspace of a 1024 x 1024 RGB plan in FP32 for every filter but the AMF). */
-#define BLFLS_NOALLOC_SCRATCH_BYTES (128u << 20)
+/* Static device scratch of blfls_smooth_noalloc, per GPU (192 MiB: the
+ * workspace of a 1024 x 1024 RGB plan in FP32 for every filter but the AMF,
+ * the pair filter's partial sums included). */
+#define BLFLS_NOALLOC_SCRATCH_BYTES (192u << 20)
 
 /* blfls_smooth without a caller workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses

@@ -151,7 +151,18 @@ AmfLayout amf_layout(const blfls_plan_s* plan, int height) {
 }
 }  // namespace
 
+// Symmetric-pair filter of a BLF request: its geometry, or false for the tile kernel.
+static bool request_pair_geometry(const blfls_plan_s* plan, const blfls_params& p, BlfPairGeom* g) {
+  if (p.filter != BLFLS_FILTER_BLF) return false;
+  const int r = p.radius >= 0 ? p.radius : static_cast<int>(std::ceil(3.0 * static_cast<double>(p.sigma_s)));
+  const int R = blf_radius_class(r);
+  return R > 0 && blf_pair_geometry(plan->H, plan->W, plan->C, R, g);
+}
+
 size_t request_workspace_bytes(const blfls_plan_s* plan, const blfls_params& p) {
+  BlfPairGeom pg;
+  if (request_pair_geometry(plan, p, &pg))   // the pair filter's partial sums follow the plan's workspace
+    return plan->ws_bytes + align_up(2 * static_cast<size_t>(plan->C) * pg.field_elems * sizeof(float2), 256);
   if (p.filter != BLFLS_FILTER_AMF) return plan->ws_bytes;
   return plan->ws_bytes + amf_layout(plan, amf_tree_height(p)).floats * sizeof(float);
 }
@@ -362,6 +373,12 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
     T.ex[d + kMaxR] = static_cast<float>(std::exp2(-q));
     T.gw[d + kMaxR] = 0.0f;
   }
+  for (int dx = 0; dx <= kMaxR; ++dx)
+    for (int dy = 0; dy <= kMaxR; ++dy) {
+      const double q = static_cast<double>(dx * dx + dy * dy) * log2e / (2.0 * ss * ss);
+      T.pw[dx * (kMaxR + 1) + dy] =
+          dx <= radius && dy <= radius ? static_cast<float>(-q) : -std::numeric_limits<float>::infinity();
+    }
   int rg = 0;
   if (prm.sigma_guide > 0.0f) {
     const double sg = prm.sigma_guide;
@@ -383,6 +400,11 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
   out->smooth_guide = prm.sigma_guide > 0.0f;
   out->joint_first = guide != nullptr || out->smooth_guide || !range_on;
   const int tiles = plan->tiles_x * plan->tiles_y;
+  BlfPairGeom pg;
+  out->pair = request_pair_geometry(plan, prm, &pg);
+  out->pair_items = out->pair ? 2 * C * pg.nbx * pg.nby : 0;
+  out->merge_items = out->pair ? 2 * C * pg.merge_count : 0;
+  float2* pair_rec = reinterpret_cast<float2*>(wsb + plan->ws_bytes);
   out->blf_first.assign(C, BlfPlane{});
   out->blf_next.assign(C, BlfPlane{});
   out->mm_first.assign(C, AuxPlane{});
@@ -451,6 +473,19 @@ void build_request(const blfls_plan_s* plan, const blfls_params& prm, int radius
       B.tile_begin = ch * tiles;
       B.tile_count = tiles;
       B.cx = B.cy = c;
+      if (out->pair) {
+        B.tile_begin = ch * pg.nbx * pg.nby;
+        B.tile_count = pg.nbx * pg.nby;
+        B.nbx = pg.nbx;
+        B.nby = pg.nby;
+        B.max_nblk = pg.max_nblk;
+        B.pair_r = out->R;
+        B.pair_k = pair_block_rows(out->R);
+        B.merge_begin = ch * pg.merge_count;
+        B.merge_count = pg.merge_count;
+        B.rec = pair_rec + 2 * ch * pg.field_elems;
+        B.rec_field = pg.field_elems;
+      }
       B.spatial = spatial;
       B.minmax = out->normalize ? partial : nullptr;
       B.fmm = fpartial;
@@ -614,7 +649,11 @@ hipError_t enqueue_request(const blfls_plan_s* plan, const RequestDesc& rd, cons
       }
     } else {
       StageTimer t(BLFLS_STAGE_BLF, s);
-      e = launch_blf(rd.R, first ? dev.blf_first : dev.blf_next, C, items, first ? rd.joint_first : true, ft, s);
+      if (rd.pair)
+        e = launch_blf_pair(rd.R, first ? dev.blf_first : dev.blf_next, C, rd.pair_items, rd.merge_items,
+                            first ? rd.joint_first : true, ft, s);
+      else
+        e = launch_blf(rd.R, first ? dev.blf_first : dev.blf_next, C, items, first ? rd.joint_first : true, ft, s);
       if (e != hipSuccess) return e;
     }
     const FftPlane* fp = it + 1 == rd.iterations ? dev.fft_last : dev.fft;

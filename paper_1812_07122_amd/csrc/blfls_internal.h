@@ -68,13 +68,29 @@ struct BlfPlane {
   float cx, cy;          // range scales sqrt(log2(e) / (2 sigma_r^2)) per field; 0 = range off
   const float* spatial;  // RequestTables::sy then ::ex of the request
   const float* fmm;      // FP16 fields: the image's gradient extrema partials (store scale), else nullptr
+  // Symmetric-pair decomposition (BlfPairGeom): the items of the plane are its
+  // bands (tile_begin / tile_count count bands instead of tiles), the merge pass
+  // has its own items, and the partial sums live in `rec`.
+  int nbx, nby;          // column bands (at most 64 columns) and row bands (whole blocks of pair_k rows)
+  int max_nblk;          // most blocks in a row band
+  int pair_r;            // radius class of the record layout
+  int pair_k;            // rows per block, pair_block_rows(pair_r)
+  int merge_begin;       // first merge item / 2 (a plane has 2 * merge_count merge items)
+  int merge_count;       // merge items per field
+  float2* rec;           // partial sums of field 0; field 1 follows at rec + rec_field
+  int64_t rec_field;     // float2 elements per field
 };
+
+// Rows per block of the symmetric-pair filter kernel at radius class R: fewer
+// for large windows, whose partner sums (K + R rows) fill the registers.
+constexpr int pair_block_rows(int R) { return R >= 20 ? 4 : 8; }
 
 // Per-request tables built in FP64 on the host and rounded to FP32.
 struct RequestTables {
   float sy[kSpan];       // log2 spatial weight per row offset dy+kMaxR: -dy^2 log2(e)/(2 sigma_s^2), -inf beyond r
   float ex[kSpan];       // spatial weight per column offset dx+kMaxR: 2^(-dx^2 log2(e)/(2 sigma_s^2))
   float gw[kSpan];       // normalised 1-D Gaussian of the guide smoothing, index d+kMaxR
+  float pw[(kMaxR + 1) * (kMaxR + 1)];  // log2 spatial weight at |offset| (dx, dy): pw[dx (kMaxR+1) + dy], -inf beyond r
 };
 
 // One channel plane for the three FFT passes (Eq. (8) in residual form).

@@ -27,6 +27,25 @@ hipError_t launch_desc_copy(const void* host_src, size_t bytes, void* dev_dst, h
 // when the kernel runs.
 hipError_t launch_blf(int R, const BlfPlane* planes, int nplanes, int total_items, bool joint,
                       int field_type, hipStream_t s, WorkHeader* work = nullptr);
+
+// Symmetric-pair filter (Eq. (1) with one exp per unordered pair of taps): bands
+// of at most 64 columns and whole blocks of kPairK rows, their partial sums, and
+// the merge pass that adds the neighbours' partial sums and writes the fields.
+struct BlfPairGeom {
+  int nbx = 0, nby = 0;     // column and row bands
+  int max_nblk = 0;         // most blocks in a row band
+  int64_t field_elems = 0;  // float2 partial sums per field
+  int merge_count = 0;      // merge items per field
+};
+// Geometry of a C-channel H x W plan at radius class R; false when the tile
+// kernel filters this shape instead (R below 8, or a band narrower than R or
+// shorter than R + kPairK - 1 rows).
+bool blf_pair_geometry(int H, int W, int C, int R, BlfPairGeom* g);
+// Both passes: `items` band items (2 per band and plane), then `merge_items`
+// merge items.  Persistent launches (work != nullptr) read their counts from
+// the header's items / items2 and use grids of `items` and `merge_items`.
+hipError_t launch_blf_pair(int R, const BlfPlane* planes, int nplanes, int items, int merge_items, bool joint,
+                           int field_type, hipStream_t s, WorkHeader* work = nullptr);
 size_t fft_rows_lds_bytes(int M, int rb);
 size_t fft_cols_lds_bytes(int H, int cb);
 // Column pass with one column per wave (H = 64 L): columns per workgroup, LDS bytes.

@@ -92,6 +92,9 @@ struct RequestDesc {
   int nc_R[8] = {};                  // farthest pixel offset of each round
   bool joint_first = false;
   int R = 0;                         // kernel radius class
+  bool pair = false;                 // BLF by the symmetric-pair kernel (partial sums after the plan's workspace)
+  int pair_items = 0;                // its band items, all channels
+  int merge_items = 0;               // its merge items, all channels
   int iterations = 1;
   bool normalize = false;
   bool smooth_guide = false;

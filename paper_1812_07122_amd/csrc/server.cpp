@@ -59,6 +59,7 @@ struct Group {
   int kind;  // 0 gauss, 1 minmax, 2 blf, 3 fft, 4 other filter (one request)
   int R = 0;
   bool joint = false;
+  bool pair = false;            // kind 2: the symmetric-pair filter (items: bands, items2: merge items)
   const Job* job = nullptr;     // kind 4: the request
   std::vector<uint8_t> planes;  // descriptor array bytes
   int n = 0;                    // planes
@@ -91,6 +92,8 @@ struct blfls_server_s {
   static constexpr size_t kHeaderBytes = 16384;
   static constexpr int kMaxGroups = static_cast<int>(kHeaderBytes / sizeof(WorkHeader));
   static constexpr int kBlfGrid = 2048;  // persistent grids of the captured kernels
+  static constexpr int kPairGrid = 3072;  // one-wave workgroups of the pair filter
+  static constexpr int kMergeGrid = 1024;
   static constexpr int kFftGrid = 1024;
   static constexpr int kAuxGrid = 1024;
   size_t stage_bytes = 0;
@@ -144,7 +147,7 @@ static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
   for (int it = 0; it < max_iter; ++it) {
     const bool first = it == 0;
     Group mm{1};
-    std::map<std::pair<int, bool>, Group> blf;
+    std::map<std::tuple<int, bool, bool>, Group> blf;
     std::vector<Group> other;
     Group fft{3};
     for (Job* jb : jobs) {
@@ -166,19 +169,24 @@ static std::vector<Group> build_groups(std::vector<Job*>& jobs) {
           for (const auto& d : (first ? rd.amf_first : rd.amf_next)) push_desc(g, d);
         other.push_back(std::move(g));
       }
-      const std::pair<int, bool> key{rd.R, first ? rd.joint_first : true};
-      auto found = blf.find(key);
-      if (found == blf.end()) {
-        Group g{2};
-        g.R = key.first;
-        g.joint = key.second;
-        found = blf.emplace(key, std::move(g)).first;
-      }
-      Group& bg = found->second;
       if (rd.filter == BLFLS_FILTER_BLF) {
+        const std::tuple<int, bool, bool> key{rd.R, first ? rd.joint_first : true, rd.pair};
+        auto found = blf.find(key);
+        if (found == blf.end()) {
+          Group g{2};
+          g.R = std::get<0>(key);
+          g.joint = std::get<1>(key);
+          g.pair = std::get<2>(key);
+          found = blf.emplace(key, std::move(g)).first;
+        }
+        Group& bg = found->second;
         for (auto b : (first ? rd.blf_first : rd.blf_next)) {
           b.tile_begin = bg.items / 2;
           bg.items += 2 * b.tile_count;
+          if (rd.pair) {
+            b.merge_begin = bg.items2 / 2;
+            bg.items2 += 2 * b.merge_count;
+          }
           push_desc(bg, b);
         }
       }
@@ -217,7 +225,7 @@ static std::vector<int> signature(const std::vector<Group>& groups) {
   std::vector<int> sig;
   for (const Group& g : groups) {
     sig.push_back(g.kind);
-    if (g.kind == 2) sig.push_back(g.R * 2 + (g.joint ? 1 : 0));
+    if (g.kind == 2) sig.push_back(g.R * 4 + (g.pair ? 2 : 0) + (g.joint ? 1 : 0));
     else if (g.kind == 3) sig.push_back(std::max(g.lds_rows, g.lds_cols) <= kFftLdsSmall ? 1 : 2);
     else sig.push_back(0);
   }
@@ -246,7 +254,11 @@ hipError_t blfls_server_s::launch_direct(std::vector<Group>& groups, int slot, i
     switch (g.kind) {
       case 0: e = launch_gauss(reinterpret_cast<const AuxPlane*>(d), g.n, g.max_pix, stream); break;
       case 1: e = launch_minmax(reinterpret_cast<const AuxPlane*>(d), g.n, stream); break;
-      case 2: e = launch_blf(g.R, reinterpret_cast<const BlfPlane*>(d), g.n, g.items, g.joint, ft, stream); break;
+      case 2:
+        e = g.pair ? launch_blf_pair(g.R, reinterpret_cast<const BlfPlane*>(d), g.n, g.items, g.items2, g.joint, ft,
+                                     stream)
+                   : launch_blf(g.R, reinterpret_cast<const BlfPlane*>(d), g.n, g.items, g.joint, ft, stream);
+        break;
       case 4: e = launch_other_filter(*g.job, d, g.joint, ft); break;
       default: {
         const FftPlane* fp = reinterpret_cast<const FftPlane*>(d);
@@ -300,7 +312,10 @@ hipError_t blfls_server_s::build_graph(const std::vector<Group>& groups, int slo
     switch (g.kind) {
       case 0: le = launch_gauss(nullptr, 0, 0, capture_stream, w, kAuxGrid); break;
       case 1: le = launch_minmax(nullptr, 0, capture_stream, w, kAuxGrid); break;
-      case 2: le = launch_blf(g.R, nullptr, 0, kBlfGrid, g.joint, ft, capture_stream, w); break;
+      case 2:
+        le = g.pair ? launch_blf_pair(g.R, nullptr, 0, kPairGrid, kMergeGrid, g.joint, ft, capture_stream, w)
+                    : launch_blf(g.R, nullptr, 0, kBlfGrid, g.joint, ft, capture_stream, w);
+        break;
       default: {
         const size_t lds = fft_lds_class(g, kFftLdsMax);
         le = launch_fft_rows_fwd(nullptr, 0, kFftGrid, lds, ft, capture_stream, w);

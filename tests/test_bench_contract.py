@@ -51,11 +51,18 @@ def test_filter_roofline_against_the_published_fp32_peak():
     # one tap = one weight of Eq. (1) for one output of one field: 6 flops (difference,
     # exponent FMA, weighted-value FMA, weight sum) against 157.3 TFLOP/s
     assert bench.FP32_PEAK_TFLOPS == 157.3 and bench.BLF_FLOPS_PER_TAP == 6
-    ro = bench.blf_roofline("k", 2160, 3840, 3, 24, 10.0, None)
+    ro = bench.blf_roofline("pair", 2160, 3840, 3, 24, 10.0)
     taps = 3 * 2160 * 3840 * 2 * 49 ** 2
     assert ro["taps_per_launch"] == taps
     assert abs(ro["achieved"] - taps * 6 / 1e-2 / 1e12) < 1e-3
     assert abs(ro["frac"] - ro["achieved"] / 157.3) < 1e-4 and ro["unit"] == "TFLOP/s" and ro["bound"] == "alu"
+    # the pair kernel issues one exp per unordered pair of taps, the tile kernel one per tap
+    assert ro["exp_pipe"]["exps_per_tap"] == 0.5 and ro["kernel"].startswith("blf_pair_kernel<R=24>")
+    assert abs(ro["exp_pipe"]["achieved_T_exp_s"] - taps * 0.5 / 1e-2 / 1e12) < 1e-3
+    rt = bench.blf_roofline("tile", 1024, 1024, 3, 9, 1.0)
+    assert rt["exp_pipe"]["exps_per_tap"] == 1.0 and rt["kernel"] == "blf_field_kernel<R=9>"
+    # traffic only from a summary taken on the current kernel source
+    assert ro["traffic"] is None
     # exponentials: a wave64 v_exp_f32 per 8 SIMD cycles, 256 CUs x 4 SIMDs at 2.4 GHz
     assert abs(bench.EXP_PEAK_T - 19.6608) < 1e-3
     assert 3 * 1024 * 1024 * 2 * 19 ** 2 == 2271215616

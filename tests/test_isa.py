@@ -56,3 +56,36 @@ def test_filter_one_exp_per_tap(asm):
         counts.append(exps)
     # the runtime dx loop evaluates K outputs x (2R+1) rows: one exp per tap
     assert 8 * 19 in counts, counts
+
+
+def _blocks(text, prefix):
+    """Instruction lines of every basic block (label to label) of one kernel."""
+    start = text.index(prefix)
+    start = text.index(":", start)
+    body = text[start:text.index("s_endpgm", start)].split("\n")
+    blocks, cur = [], []
+    for line in body:
+        if re.match(r"\s*\.LBB\S+:", line):
+            blocks.append(cur)
+            cur = []
+        elif line.strip() and not line.strip().startswith(";"):
+            cur.append(line.strip())
+    blocks.append(cur)
+    return blocks
+
+
+def test_pair_filter_one_exp_per_pair(asm):
+    """The symmetric-pair kernel evaluates every unordered pair of taps once: at
+    R = 24 (blocks of K = 4 rows) each step of its two column-offset loops is one
+    straight block of K (R + 1) = 100 or K R = 96 pairs with one exp each and seven
+    VALU instructions per pair (difference, exponent FMA, exp, two FMACs and two
+    adds, the sums of both pixels)."""
+    text = asm["blf_pair_kernel.hip"]
+    counts = []
+    for lines in _blocks(text, "_ZN5blfls15blf_pair_kernelILi24ELb0ELb0EE"):
+        exps = sum(bool(re.match(r"v_exp_f32", l)) for l in lines)
+        if exps:
+            valu = sum(bool(re.match(r"v_", l)) for l in lines)
+            counts.append(exps)
+            assert valu <= 7.05 * exps, (exps, valu)
+    assert sorted(counts) == [96, 100], counts
