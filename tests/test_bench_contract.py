@@ -130,8 +130,8 @@ def test_traffic_is_read_only_while_the_kernel_source_matches(tmp_path, monkeypa
 
 def test_committed_summaries_name_their_sources():
     # every PMC summary that feeds a roofline records the hash and the per-launch bytes
-    for name, src in (("blf_kernel_rgb1024_pmc.md", "blf_kernel.hip"), ("nc_passes_rgb1024_pmc.md", "nc_kernels.hip"),
-                      ("amf_passes_rgb1024_pmc.md", "amf_kernels.hip")):
+    for name, src in (("blf_filter_uhd_pmc.md", "blf_pair_kernel.hip"), ("blf_filter_rgb1024_pmc.md", "blf_pair_kernel.hip"),
+                      ("nc_passes_rgb1024_pmc.md", "nc_kernels.hip"), ("amf_passes_rgb1024_pmc.md", "amf_kernels.hip")):
         text = open(os.path.join(ROOT, "profiles", name)).read()
         assert "source_sha256:" in text and "hbm_bytes_per_launch:" in text, name
         assert "rocprofv3 --pmc" in text, name
