@@ -129,3 +129,41 @@ def test_pair_path_channels_bitwise_independent_and_repeatable():
     for c in range(3):
         u1, _, _ = _smooth(f[c], lam=20.0, sigma_s=4.0, sigma_r=0.1)
         assert np.array_equal(u1, u3[c])
+
+
+def test_pair_path_served_graphs_equal_direct_calls():
+    """Served steps replay captured graphs of the persistent pair kernels (band items
+    drawn from a counter, any band of any request in any order): every result equals
+    its direct call bit for bit, for radius classes 12 and 24, self and joint."""
+    import time
+    b = blfls()
+    reqs = []
+    for k in range(12):
+        H, W = [(72, 90), (96, 128), (64, 200)][k % 3]
+        f = voronoi_image(H, W, 2100 + k)
+        prm = dict(lam=[20.0, 50.0][k % 2], sigma_s=[4.0, 8.0][(k // 2) % 2], sigma_r=0.1)
+        guide = voronoi_image(H, W, 2200 + k) if k % 4 == 3 else None
+        reqs.append((f, guide, prm))
+    server = b.Server(arena_bytes=256 << 20, max_slots=6, precision="fp32")
+    pending = []
+    for f, guide, prm in reqs:
+        g = None if guide is None else _gpu(guide)
+        pending.append(server.submit(_gpu(f), guide=g, **prm))
+    deadline = time.time() + 60
+    for t, u in pending:
+        while True:
+            state, status = server.poll(t)
+            if state in (b.DONE, b.FAILED):
+                break
+            assert time.time() < deadline
+            time.sleep(0.001)
+        assert state == b.DONE and status == 0
+    server.stream.synchronize()
+    stats = server.stats()
+    assert stats["graph_steps"] >= 1
+    server.close()
+    for (f, guide, prm), (_, u) in zip(reqs, pending):
+        g = None if guide is None else _gpu(guide)
+        alone = b.smooth(_gpu(f), guide=g, **prm)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, u), prm
