@@ -545,9 +545,11 @@ bool blf_pair_geometry(int H, int W, int C, int R, BlfPairGeom* out) {
   if (W / nbx < R) return false;                    // every band at least R columns
   const int T = (H + K - 1) / K;
   const int min_blocks = (R + K - 1 + K - 1) / K;   // every row band at least R + K - 1 rows
-  // blocks per row band: 64 rows' worth, fewer while the launch would give the
-  // chip under 4096 waves (bands of both fields of every channel)
-  int per = 64 / K;
+  // blocks per row band: 40 rows' worth (measured at 3840x2160 RGB, r = 24: 40-row
+  // bands 11.59 ms per step, 64-row 12.14, 32-row 11.62; shorter waves balance the
+  // launch's last round), fewer while the launch would give the chip under 4096
+  // waves (bands of both fields of every channel)
+  int per = (40 + K - 1) / K;
   while (per > min_blocks && 2L * C * nbx * std::max(1, T / per) < 4096) --per;
   per = std::max(per, min_blocks);
   // fewer row bands while the shortest is under R + K - 1 rows: the non-last
