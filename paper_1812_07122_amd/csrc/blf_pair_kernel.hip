@@ -31,6 +31,7 @@
 // source sums hold the negated sums (both are e * (q_s - q_t)); joint fields sum
 // w * p of the other pixel on both sides.
 #include <algorithm>
+#include <type_traits>
 
 #include "blfls_field.h"
 #include "blfls_internal.h"
@@ -449,47 +450,77 @@ __device__ __forceinline__ void pair_merge_item(const BlfPlane* __restrict__ pla
   const int ovf_row = (ly / K) * R;
   const int ovf_k = ly % K;
 
-  for (int x = seg * kMergeSeg + static_cast<int>(threadIdx.x); x < min(W, (seg + 1) * kMergeSeg);
-       x += kMergeThreads) {
-    const int bx = ((x + 1) * P.nbx - 1) / W;
-    const int x0 = bx * W / P.nbx;
-    const int lx = x - x0;
-    f2v v = load2(rec, main_off(P, bx, by) + static_cast<int64_t>(ly) * 64 + lx);
-    if (above) {
-      const f2v a = load2(rec, main_off(P, bx, bya) + static_cast<int64_t>(la) * 64 + lx);
-      v.x += a.x;
-      v.y += a.y;
+  // Every load of the thread's kPer pixels is issued before any is used, so the item
+  // waits on memory once (a pixel past the image reads column W - 1).  Rows with and
+  // without carry-over rows from the band above take separate loops.
+  constexpr int kPer = kMergeSeg / kMergeThreads;
+  static_assert(kMergeSeg % kMergeThreads == 0, "whole pixels per thread");
+  const int xbeg = seg * kMergeSeg + static_cast<int>(threadIdx.x);
+  const int xend = min(W, (seg + 1) * kMergeSeg);
+  auto run = [&](auto has_above) {
+    constexpr bool kAbove = decltype(has_above)::value;
+    f2v v[kPer], a[kPer], o_r[kPer], o_l[kPer];
+    float fo[kPer], fn[kPer];
+    bool take_r[kPer], take_l[kPer];
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int x = min(xbeg + i * kMergeThreads, W - 1);
+      const int bx = ((x + 1) * P.nbx - 1) / W;
+      const int x0 = bx * W / P.nbx;
+      const int lx = x - x0;
+      const int64_t own = main_off(P, bx, by) + static_cast<int64_t>(ly) * 64 + lx;
+      // sources in the band to the right, carried out through its lane 0
+      const int bxr = bx + 1 == P.nbx ? 0 : bx + 1;
+      int dr = bxr * W / P.nbx - x;
+      if (dr <= 0) dr += W;
+      // sources in the band to the left, carried out through its last lane
+      const int bxl = bx == 0 ? P.nbx - 1 : bx - 1;
+      int dl = x - ((bxl + 1) * W / P.nbx - 1);
+      if (dl <= 0) dl += W;
+      take_r[i] = dr <= r;
+      take_l[i] = dl <= r;
+      v[i] = load2(rec, own);
+      if (kAbove) a[i] = load2(rec, main_off(P, bx, bya) + static_cast<int64_t>(la) * 64 + lx);
+      // (an edge sum a pixel does not take is read at the nearest offset, r, and dropped)
+      const int er = max(1, min(dr, r)), el = max(1, min(dl, r));
+      o_r[i] = load2(rec, ovf_off(P, bxr, by, 0) + static_cast<int64_t>(ovf_row + er - 1) * K + ovf_k);
+      o_l[i] = load2(rec, ovf_off(P, bxl, by, 1) + static_cast<int64_t>(ovf_row + el - 1) * K + ovf_k);
+      if (JOINT) {
+        const int xn = field ? x : (x + 1 == W ? 0 : x + 1);
+        fo[i] = load_global(f, Y * pitch + x);
+        fn[i] = load_global(f, rn * pitch + xn);
+      }
     }
-    // sources in the band to the right, carried out through its lane 0
-    const int bxr = bx + 1 == P.nbx ? 0 : bx + 1;
-    int dr = bxr * W / P.nbx - x;
-    if (dr <= 0) dr += W;
-    if (dr <= r) {
-      const f2v o = load2(rec, ovf_off(P, bxr, by, 0) + static_cast<int64_t>(ovf_row + dr - 1) * K + ovf_k);
-      v.x = JOINT ? v.x + o.x : v.x - o.x;
-      v.y += o.y;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int x = xbeg + i * kMergeThreads;
+      if (x >= xend) break;
+      f2v s = v[i];
+      if (kAbove) {
+        s.x += a[i].x;
+        s.y += a[i].y;
+      }
+      if (take_r[i]) {
+        s.x = JOINT ? s.x + o_r[i].x : s.x - o_r[i].x;
+        s.y += o_r[i].y;
+      }
+      if (take_l[i]) {
+        s.x = JOINT ? s.x + o_l[i].x : s.x - o_l[i].x;
+        s.y += o_l[i].y;
+      }
+      // the centre tap (weight 1), then the residual
+      const float den = 1.0f + s.y;
+      float res;
+      if (JOINT) {
+        const float ps = fn[i] - fo[i];
+        res = (ps + s.x) / den - ps;
+      } else {
+        res = s.x / (c * den);
+      }
+      store_field(out, static_cast<int64_t>(Y) * W + x, res * ssc, field_type);
     }
-    // sources in the band to the left, carried out through its last lane
-    const int bxl = bx == 0 ? P.nbx - 1 : bx - 1;
-    int dl = x - ((bxl + 1) * W / P.nbx - 1);
-    if (dl <= 0) dl += W;
-    if (dl <= r) {
-      const f2v o = load2(rec, ovf_off(P, bxl, by, 1) + static_cast<int64_t>(ovf_row + dl - 1) * K + ovf_k);
-      v.x = JOINT ? v.x + o.x : v.x - o.x;
-      v.y += o.y;
-    }
-    // the centre tap (weight 1), then the residual
-    const float den = 1.0f + v.y;
-    float res;
-    if (JOINT) {
-      const int xn = field ? x : (x + 1 == W ? 0 : x + 1);
-      const float ps = load_global(f, rn * pitch + xn) - load_global(f, Y * pitch + x);
-      res = (ps + v.x) / den - ps;
-    } else {
-      res = v.x / (c * den);
-    }
-    store_field(out, static_cast<int64_t>(Y) * W + x, res * ssc, field_type);
-  }
+  };
+  if (above) run(std::true_type{}); else run(std::false_type{});
 }
 
 // Waves per SIMD the register allocation targets (no spills at any radius class):
