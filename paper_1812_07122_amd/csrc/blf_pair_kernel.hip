@@ -526,7 +526,9 @@ __device__ __forceinline__ void pair_merge_item(const BlfPlane* __restrict__ pla
 // Waves per SIMD the register allocation targets (no spills at any radius class):
 // the persistent loop and the joint fields' values hold more registers.
 constexpr int pair_waves(int R, bool joint, bool persist) {
-  return persist ? (joint && R >= 32 ? 1 : 2) : joint ? (R >= 28 ? 2 : 3) : (R >= 28 || R == 16 ? 3 : 4);
+  if (persist) return joint && R >= 32 ? 1 : 2;
+  if (joint) return R >= 28 ? 2 : (R >= 10 && R <= 14) ? 4 : 3;
+  return R >= 28 ? 3 : (R >= 10 && R <= 14) ? 5 : 4;
 }
 
 template <int R, bool JOINT, bool PERSIST>

@@ -81,9 +81,11 @@ struct BlfPlane {
   int64_t rec_field;     // float2 elements per field
 };
 
-// Rows per block of the symmetric-pair filter kernel at radius class R: fewer
-// for large windows, whose partner sums (K + R rows) fill the registers.
-constexpr int pair_block_rows(int R) { return R >= 20 ? 4 : 8; }
+// Rows per block of the symmetric-pair filter kernel at radius class R.  Four from
+// class 10 up: the partner sums (K + R rows) then leave room for four to five
+// waves per SIMD (measured 2-6% faster than eight-row blocks at classes 10-16);
+// classes 8 and 9 run faster with eight.
+constexpr int pair_block_rows(int R) { return R >= 10 ? 4 : 8; }
 
 // Per-request tables built in FP64 on the host and rounded to FP32.
 struct RequestTables {

@@ -8,7 +8,8 @@ The cases below put every one of those hand-overs to work: several column and
 row bands, ragged widths and heights, a last block cut by the image edge, one
 band that wraps onto itself in either direction, radius classes 8 to 32 with r
 below its class, joint fields, the range kernel off, normalising, rolling
-guidance and 16-bit field storage.  Radius classes below 8 and images too small
+guidance and 16-bit field storage; blocks of eight rows (classes 8 and 9) and of four
+(classes 10 and up).  Radius classes below 8 and images too small
 for bands at least R wide and R + K - 1 tall take the tile kernel (the other
 GPU tests); the workspace test shows which path a request takes.
 """
@@ -81,6 +82,8 @@ def test_path_selection_by_workspace(H, W, ss, r, pair):
     (160, 64, 5.0, 0.1, 16, 20.0),     # class 16, one column band of 64, several row bands
     (54, 150, 6.0, 0.15, 20, 40.0),    # class 20, H = 54: last block of 2 rows
     (90, 256, 9.0, 0.1, 28, 20.0),     # class 28
+    (48, 160, 3.3, 0.2, 10, 15.0),     # class 10, the smallest with 4-row blocks
+    (70, 140, 4.7, 0.15, 14, 25.0),    # class 14, 3 x 3 bands, last row band 22 rows
 ])
 def test_pair_path_parity(H, W, ss, sr, r, lam):
     f = voronoi_image(H, W, 1000 + H + W + r)
@@ -91,7 +94,8 @@ def test_pair_path_parity(H, W, ss, sr, r, lam):
     assert err <= TOL_FP32
 
 
-@pytest.mark.parametrize("H,W,ss,r", [(40, 72, 3.0, 9), (72, 90, 10.0, 30), (64, 200, 8.0, 24)])
+@pytest.mark.parametrize("H,W,ss,r", [(40, 72, 3.0, 9), (72, 90, 10.0, 30), (64, 200, 8.0, 24),
+                                      (64, 128, 4.0, 12), (80, 96, 5.3, 16)])
 def test_pair_path_joint(H, W, ss, r):
     t, g = joint_pair(H, W, 5)
     u, tin, gin = _smooth(t, g, lam=30.0, sigma_s=ss, sigma_r=0.1, radius=r)
