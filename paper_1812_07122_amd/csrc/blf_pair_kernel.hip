@@ -8,7 +8,7 @@
 // enters the sums of both pixels.
 //
 // Work split.  The image is cut into bands of at most 64 columns and whole
-// blocks of K rows (8, or 4 for R >= 20); one wave sweeps a band block by block.  A pair is
+// blocks of K rows (8 for R = 8, 9; 4 from R = 10); one wave sweeps a band block by block.  A pair is
 // evaluated by the band that holds the column of its partner t and the block
 // that holds the row of its source s.  Lane l owns image column x0+l:
 //   * its partner sums A[j] (rows y..y+K+R-1 of its own column) stay in
