@@ -171,3 +171,40 @@ def test_pair_path_served_graphs_equal_direct_calls():
         alone = b.smooth(_gpu(f), guide=g, **prm)
         torch.cuda.synchronize()
         assert torch.equal(alone, u), prm
+
+
+def _smooth235(n):
+    for p in (2, 3, 5):
+        while n % p == 0:
+            n //= p
+    return n == 1
+
+
+def test_pair_path_random_layouts():
+    """Seeded random shapes (H and W/2 with factors 2, 3, 5 only), radius classes 8-32,
+    self- and joint-guided, three range scales: every case element by element against
+    the oracle.  Most take the pair path; the rest (bands narrower than R, images
+    shorter than R + K - 1) the tile kernel, counted in the message."""
+    b = blfls()
+    heights = [n for n in range(16, 241) if _smooth235(n)]
+    widths = [2 * n for n in range(8, 161) if _smooth235(n)]
+    rng = np.random.default_rng(2024)
+    on_pair = 0
+    for case in range(24):
+        H, W = int(rng.choice(heights)), int(rng.choice(widths))
+        r = int(rng.integers(8, 33))
+        joint = bool(rng.integers(0, 2))
+        sr = float(rng.choice([0.05, 0.1, 0.3]))
+        lam = float(rng.uniform(5, 60))
+        plan = b.Plan(H, W, 1)
+        on_pair += plan.workspace_for(b.make_params(lam, r / 3.0, sr, r)) > plan.workspace_bytes
+        plan.close()
+        print(f"case {case}: {H}x{W} r={r} joint={joint} sigma_r={sr}", flush=True)
+        f = voronoi_image(H, W, 7000 + case)
+        g = joint_pair(H, W, 7100 + case)[1] if joint else None
+        u, fin, gin = _smooth(f, g, lam=lam, sigma_s=r / 3.0, sigma_r=sr, radius=r)
+        ref = oracle.smooth(fin, lam, r / 3.0, sr, radius=r, guide=gin)
+        err = float(np.max(np.abs(u - ref)))
+        assert err <= TOL_FP32, (H, W, r, joint, err)
+    print(f"{on_pair} of 24 cases on the pair path")
+    assert on_pair >= 16
