@@ -42,8 +42,10 @@ namespace blfls {
 
 namespace {
 
+static_assert(kPairMaxR == kMaxR && kPairBandCols == 64, "pair classes and wave width");
+
 constexpr float kHuge = 1e30f;   // range value of a source row / partner lane outside the band: weight 0
-constexpr int kMergeSeg = 1024;  // columns per merge item
+constexpr int kMergeSeg = kPairMergeSeg;  // columns per merge item
 constexpr int kMergeThreads = 256;
 
 __device__ __forceinline__ int wrap_i(int v, int n) {
@@ -121,28 +123,23 @@ __device__ __forceinline__ Band band_of(const BlfPlane& P, int bx, int by) {
   const int K = P.pair_k;
   const int T = (P.H + K - 1) / K;
   Band b;
-  b.x0 = bx * P.W / P.nbx;
-  b.wb = (bx + 1) * P.W / P.nbx - b.x0;
-  const int blk0 = by * T / P.nby;
-  b.nblk = (by + 1) * T / P.nby - blk0;
+  b.x0 = pair_band_x0(P.W, P.nbx, bx);
+  b.wb = pair_band_x0(P.W, P.nbx, bx + 1) - b.x0;
+  const int blk0 = pair_band_first_block(T, P.nby, by);
+  b.nblk = pair_band_first_block(T, P.nby, by + 1) - blk0;
   b.Y0 = blk0 * K;
   b.Y1 = min(P.H, b.Y0 + b.nblk * K);
   return b;
 }
 
-__device__ __forceinline__ int64_t main_rows(const BlfPlane& P) {
-  return static_cast<int64_t>(P.max_nblk) * P.pair_k + P.pair_r;
-}
-// main region of band (bx, by): [main_rows][64] float2
+// main region of band (bx, by): [max_nblk K + R][64] float2; the sums that left
+// band (bx, by) through lane 0 (dir 0, sources in the band to the left) or the
+// last lane (dir 1): [max_nblk][R][K] float2 (layout in blfls_pair_geom.h)
 __device__ __forceinline__ int64_t main_off(const BlfPlane& P, int bx, int by) {
-  return (static_cast<int64_t>(by) * P.nbx + bx) * main_rows(P) * 64;
+  return pair_main_off(P.nbx, P.max_nblk, P.pair_k, P.pair_r, bx, by);
 }
-// travelling sums of band (bx, by) that left through lane 0 (dir 0, sources in
-// the band to the left) or the last lane (dir 1): [max_nblk][pair_r][K] float2
 __device__ __forceinline__ int64_t ovf_off(const BlfPlane& P, int bx, int by, int dir) {
-  const int64_t nb = static_cast<int64_t>(P.nbx) * P.nby;
-  const int64_t per = static_cast<int64_t>(P.max_nblk) * P.pair_r * P.pair_k;
-  return nb * main_rows(P) * 64 + (dir * nb + static_cast<int64_t>(by) * P.nbx + bx) * per;
+  return pair_edge_off(P.nbx, P.nby, P.max_nblk, P.pair_k, P.pair_r, bx, by, dir);
 }
 
 // Range scale of a field: c = sqrt(log2 e / (2 sigma_r^2)), divided by the
@@ -570,38 +567,6 @@ __global__ void __launch_bounds__(kMergeThreads) blf_pair_merge_kernel(const Blf
 // ---------------------------------------------------------------------------
 // Host side: geometry and launch
 // ---------------------------------------------------------------------------
-
-bool blf_pair_geometry(int H, int W, int C, int R, BlfPairGeom* out) {
-  if (R < 8 || R > kMaxR) return false;
-  const int K = pair_block_rows(R);
-  const int nbx = (W + 63) / 64;
-  if (W / nbx < R) return false;                    // every band at least R columns
-  const int T = (H + K - 1) / K;
-  const int min_blocks = (R + K - 1 + K - 1) / K;   // every row band at least R + K - 1 rows
-  // blocks per row band: 40 rows' worth (measured at 3840x2160 RGB, r = 24: 40-row
-  // bands 11.59 ms per step, 64-row 12.14, 32-row 11.62; shorter waves balance the
-  // launch's last round), fewer while the launch would give the chip under 4096
-  // waves (bands of both fields of every channel)
-  int per = (40 + K - 1) / K;
-  while (per > min_blocks && 2L * C * nbx * std::max(1, T / per) < 4096) --per;
-  per = std::max(per, min_blocks);
-  // fewer row bands while the shortest is under R + K - 1 rows: the non-last
-  // bands have at least floor(T / nby) full blocks, the last one ends at H
-  int nby = std::max(1, T / per);
-  auto min_height = [&](int n) { return std::min((T / n) * K, H - ((n - 1) * T / n) * K); };
-  while (nby > 1 && min_height(nby) < R + K - 1) --nby;
-  if (min_height(nby) < R + K - 1) return false;
-  const int max_nblk = (T + nby - 1) / nby;
-  BlfPairGeom g;
-  g.nbx = nbx;
-  g.nby = nby;
-  g.max_nblk = max_nblk;
-  const int64_t nb = static_cast<int64_t>(nbx) * nby;
-  g.field_elems = nb * (static_cast<int64_t>(max_nblk) * K + R) * 64 + 2 * nb * static_cast<int64_t>(max_nblk) * R * K;
-  g.merge_count = H * ((W + kMergeSeg - 1) / kMergeSeg);
-  *out = g;
-  return true;
-}
 
 namespace {
 template <int R>

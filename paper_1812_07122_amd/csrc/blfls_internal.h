@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "blfls_pair_geom.h"
+
 namespace blfls {
 
 constexpr int kMaxR = 32;               // largest filter radius
@@ -80,12 +82,6 @@ struct BlfPlane {
   float2* rec;           // partial sums of field 0; field 1 follows at rec + rec_field
   int64_t rec_field;     // float2 elements per field
 };
-
-// Rows per block of the symmetric-pair filter kernel at radius class R.  Four from
-// class 10 up: the partner sums (K + R rows) then leave room for four to five
-// waves per SIMD (measured 2-6% faster than eight-row blocks at classes 10-16);
-// classes 8 and 9 run faster with eight.
-constexpr int pair_block_rows(int R) { return R >= 10 ? 4 : 8; }
 
 // Per-request tables built in FP64 on the host and rounded to FP32.
 struct RequestTables {

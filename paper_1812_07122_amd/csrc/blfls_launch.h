@@ -29,18 +29,9 @@ hipError_t launch_blf(int R, const BlfPlane* planes, int nplanes, int total_item
                       int field_type, hipStream_t s, WorkHeader* work = nullptr);
 
 // Symmetric-pair filter (Eq. (1) with one exp per unordered pair of taps): bands
-// of at most 64 columns and whole blocks of kPairK rows, their partial sums, and
-// the merge pass that adds the neighbours' partial sums and writes the fields.
-struct BlfPairGeom {
-  int nbx = 0, nby = 0;     // column and row bands
-  int max_nblk = 0;         // most blocks in a row band
-  int64_t field_elems = 0;  // float2 partial sums per field
-  int merge_count = 0;      // merge items per field
-};
-// Geometry of a C-channel H x W plan at radius class R; false when the tile
-// kernel filters this shape instead (R below 8, or a band narrower than R or
-// shorter than R + kPairK - 1 rows).
-bool blf_pair_geometry(int H, int W, int C, int R, BlfPairGeom* g);
+// of at most 64 columns and whole blocks of K rows (geometry and record layout in
+// blfls_pair_geom.h), their partial sums, and the merge pass that adds the
+// neighbours' partial sums and writes the fields.
 // Both passes: `items` band items (2 per band and plane), then `merge_items`
 // merge items.  Persistent launches (work != nullptr) read their counts from
 // the header's items / items2 and use grids of `items` and `merge_items`.
