@@ -84,6 +84,7 @@ def test_path_selection_by_workspace(H, W, ss, r, pair):
     (90, 256, 9.0, 0.1, 28, 20.0),     # class 28
     (48, 160, 3.3, 0.2, 10, 15.0),     # class 10, the smallest with 4-row blocks
     (75, 150, 4.7, 0.15, 14, 25.0),    # class 14, 3 x 3 bands, a last block of 3 rows
+    (64, 1200, 4.0, 0.1, 12, 20.0),    # two merge segments of 1024 columns, the second partial
 ])
 def test_pair_path_parity(H, W, ss, sr, r, lam):
     f = voronoi_image(H, W, 1000 + H + W + r)
