@@ -209,3 +209,41 @@ def test_pair_path_random_layouts():
         assert err <= TOL_FP32, (H, W, r, joint, err)
     print(f"{on_pair} of 24 cases on the pair path")
     assert on_pair >= 16
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_served_random_mixes_equal_direct_calls(precision):
+    """Seeded random requests (radius classes 2-32 on both filter paths, RGB and
+    grey, self- and joint-guided, normalising, one or two rolling iterations)
+    served in one mix: each result equals the same request run alone, bit for bit."""
+    import time
+    b = blfls()
+    heights = [n for n in range(24, 200) if _smooth235(n)]
+    widths = [2 * n for n in range(16, 150) if _smooth235(n)]
+    rng = np.random.default_rng(31 if precision == "fp32" else 32)
+    reqs = []
+    for k in range(16):
+        H, W, C = int(rng.choice(heights)), int(rng.choice(widths)), int(rng.choice([1, 3]))
+        r = int(rng.integers(2, 33))
+        prm = dict(lam=float(rng.uniform(5, 100)), sigma_s=r / 3.0, sigma_r=float(rng.uniform(0.03, 0.3)),
+                   radius=r, iterations=int(rng.integers(1, 3)), normalize=bool(rng.integers(0, 4) == 0))
+        f = np.stack([voronoi_image(H, W, 8000 + 3 * k + c) for c in range(C)])
+        g = np.stack([voronoi_image(H, W, 8500 + 3 * k + c) for c in range(C)]) if rng.integers(0, 3) == 0 else None
+        reqs.append((_gpu(f), None if g is None else _gpu(g), prm))
+    server = b.Server(arena_bytes=512 << 20, max_slots=8, precision=precision)
+    pending = [server.submit(f, guide=g, **prm) for f, g, prm in reqs]
+    deadline = time.time() + 60
+    for t, _ in pending:
+        while True:
+            state, status = server.poll(t)
+            if state in (b.DONE, b.FAILED):
+                break
+            assert time.time() < deadline
+            time.sleep(0.001)
+        assert state == b.DONE and status == 0
+    server.stream.synchronize()
+    server.close()
+    for (f, g, prm), (_, u) in zip(reqs, pending):
+        alone = b.smooth(f, guide=g, precision=precision, **prm)
+        torch.cuda.synchronize()
+        assert torch.equal(alone, u), prm
